@@ -1,0 +1,170 @@
+/*
+ * dotsocp.h -- C ABI of the gfx950 (MI355X) solver for dynamic optimal
+ * transport on a staggered space-time grid, recast as a linear second-order
+ * cone program and solved by the inexact proximal augmented Lagrangian method
+ * (Chen, Lin & Zhou, arXiv 2505.05424, Algorithm 2).
+ *
+ * Every function returns 0 (DOT_OK) on success or a negative dot_status; no
+ * C++ exception crosses this boundary. dot_last_error() returns a message for
+ * the most recent failure on the calling thread.
+ *
+ * ---------------------------------------------------------------------------
+ * Problem and grids (Sec. 2.2)
+ *   D spatial dimensions (1..3); n[0] = n0 time segments, n[1..D] spatial
+ *   segments; h_d = 1/n_d. Nodes G^c: (n0+1) x (n1+1) x ... x (nD+1).
+ *   Cells G^s_0 (time t+1/2, spatial node x): n0 x (n1+1) x ... (the cones).
+ *   G^s_d (d >= 1): time node t, staggered point s+1/2 on axis d.
+ *   rho0, rho1: node masses on the spatial nodes (C order, last axis
+ *   fastest), non-negative, finite, equal totals (relative mismatch at most
+ *   1e-12); they give the boundary vector c of eq. defc. An optional mask
+ *   (1 = obstacle) gives the cell weights omega of the weighted problem of
+ *   Sec. 5.4.5: omega = 1e-6 on obstacle nodes, 1 elsewhere, time-invariant.
+ *   Internally c is divided by h0*h1*...*hD, so the multipliers come out as
+ *   density (alpha0 = rho) and momentum density (alpha_d = m_d).
+ *
+ * Device data layout ("padded box", used by every device pointer below)
+ *   A plane is an array of NB = (n0+1)*(n1+1)*...*(nD+1) scalars indexed like
+ *   the node grid (time slowest, last spatial axis fastest). A cell-valued
+ *   plane (q0, alpha0, one cone component) leaves its time slice n0 unused;
+ *   a G^s_d plane (q_d, alpha_d) leaves the slice x_d = n_d unused. Unused
+ *   entries must be zero on input and are written as zero.
+ *     q, alpha : D+1 consecutive planes (d = 0..D)
+ *     beta, z  : K = 4D+2 consecutive planes, component order
+ *                [1 - q0 side, (d=1,v=1..4), ..., (d=D,v=1..4), 1 + q0 side]
+ *                as in eq. bdd / eq. operBF.
+ *   Scalars are double in DOT_FP64 mode; DOT_MIXED stores the bulk state as
+ *   float (see dot_plan_info.scalar_bytes).
+ *
+ * Ownership: the caller owns every buffer it passes; the library keeps no
+ * pointer to caller memory after a call returns. A dot_plan owns only small
+ * constant tables on its device (transform matrices, eigenvalues, weights).
+ * Streams are hipStream_t passed as void*; NULL means the default stream.
+ * All step functions are asynchronous on that stream.
+ */
+#ifndef DOTSOCP_H
+#define DOTSOCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DOT_OK = 0,
+  DOT_EINVAL = -1,   /* invalid argument or problem data */
+  DOT_ENOMEM = -2,   /* a device or host allocation failed */
+  DOT_EDEVICE = -3,  /* a HIP runtime call failed */
+  DOT_EBUSY = -4     /* a serving request can never fit the HBM budget */
+} dot_status;
+
+typedef enum { DOT_FP64 = 0, DOT_MIXED = 1 } dot_precision;
+
+typedef enum {
+  DOT_RUNNING = -1,
+  DOT_CONVERGED = 0, /* eta_dot <= tol at a residual check */
+  DOT_MAXITER = 1,   /* iteration cap reached */
+  DOT_TIMEOUT = 2,
+  DOT_DIVERGED = 3   /* a residual became NaN or Inf */
+} dot_term;
+
+typedef struct {
+  int32_t D;              /* 1..3 */
+  int32_t n[4];           /* n[0] = n0 >= 1 time segments; n[1..D] >= 1 */
+  const double* rho0;     /* host, prod_d (n_d+1) node masses, >= 0 */
+  const double* rho1;     /* host, same shape and total mass */
+  const uint8_t* mask;    /* host, optional (NULL): 1 = obstacle */
+  double tol;             /* stop when eta_dot <= tol; < 0: never stop */
+  int32_t max_iter;       /* iteration cap (> 0) */
+  int32_t precision;      /* dot_precision */
+  double tau;             /* dual step in (0, 2); 0 selects 1.9 */
+  double sigma0;          /* initial penalty; 0 selects 1.0 */
+  int32_t check_every;    /* residual-check cadence; 0 selects 5 */
+  int32_t adapt_sigma;    /* 1: sigma rule of Sec. 5.3 on the growing schedule */
+} dot_problem;
+
+typedef struct {
+  double objective;       /* -<c, phi> in unscaled units (about W2^2 / 2) */
+  double dual_objective;  /* 1/2 sum_d sum_{r_d>0} m_d^2 / r_d (unscaled) */
+  double eta_dot, eta_p, eta_d, eta_c, eta_p_soc, eta_d_soc;
+  double sigma;           /* penalty after the last check */
+  int32_t iters;          /* PALM iterations done */
+  int32_t term;           /* dot_term */
+  int32_t checks;         /* residual checks done */
+  int32_t sigma_changes;  /* sigma decisions that changed sigma */
+} dot_result;
+
+typedef struct {
+  int32_t D, K;
+  int32_t n[4];
+  int64_t nb;             /* scalars per plane */
+  int32_t scalar_bytes;   /* 8 (FP64) or 4 (MIXED bulk) */
+  int32_t n_planes;       /* planes in the state buffer */
+  size_t state_bytes;     /* bytes the caller must provide for a state buffer */
+  /* plane offsets (in planes) inside a state buffer */
+  int32_t off_phi, off_q, off_qn, off_alpha, off_beta, off_w;
+} dot_plan_info;
+
+typedef struct dot_plan dot_plan;
+
+const char* dot_last_error(void);
+
+/* Validate p (mass balance, sizes, finite data), build c, omega, the cosine
+ * transform tables and eigenvalues of A^*A (Sec. 4, Alg. 2 line 2) on the
+ * current HIP device. The plan copies everything it needs from p. */
+int dot_plan_create(const dot_problem* p, dot_plan** out);
+void dot_plan_destroy(dot_plan* plan);
+int dot_plan_get_info(const dot_plan* plan, dot_plan_info* out);
+
+/* Initial point of Algorithm 1: q = alpha = beta = 0 (0 lies in Q), sigma =
+ * sigma0, counters cleared. `state` is a device buffer of info.state_bytes. */
+int dot_state_reset(dot_plan* plan, void* state, void* stream);
+
+/* Run PALM iterations of Algorithm 2 on `state` until eta_dot <= tol at a
+ * residual check, or `max_iters` more iterations, on `stream`; blocks until
+ * done and fills *res (may be NULL). Residual checks and the sigma rule run on
+ * the device every check_every iterations. */
+int dot_run(dot_plan* plan, void* state, int32_t max_iters, void* stream, dot_result* res);
+
+/* Copy rho = alpha0 (n0 x prod(n_d+1), density at half-times) and the D
+ * momentum blocks m_d = alpha_d (exact G^s_d shapes, concatenated) from a
+ * state buffer into host arrays (either may be NULL). */
+int dot_extract(dot_plan* plan, const void* state, double* rho_out, double* m_out, void* stream);
+
+/* ---- step-level entry points (one row of the hot path each) ------------ */
+
+/* a3: b = A^*(q - alpha/sigma) - c/sigma (Alg. 2 line 1), node plane b. */
+int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double sigma,
+                        void* b, void* stream);
+/* a4: phi = (A^*A)^+ b in place on the node plane (Alg. 2 line 2): forward
+ * DCT-II on every axis, divide by the eigenvalues, zero mode set to 0 (phi in
+ * rge A^*), inverse transform. */
+int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
+/* a3 + a4 as the iteration runs them (divergence fused into the first
+ * transform pass): phi from (q, alpha, sigma). */
+int dot_step_rhs_poisson(dot_plan* plan, const void* q, const void* alpha, double sigma,
+                         void* phi, void* stream);
+/* a1 + a2: z = Pi_Q(B_omega F q + d - beta/sigma) (Alg. 2 line 3; eq. app-proj
+ * per cell, eq. fdetails for the gather), K planes. */
+int dot_step_cone(dot_plan* plan, const void* q, const void* beta, double sigma,
+                  void* z, void* stream);
+/* a5: q_new, alpha, beta updates of Alg. 2 lines 4-6 from phi and the old
+ * (q, alpha, beta); alpha and beta are updated in place, q_new written to
+ * q_out; w_scratch holds 4D planes of workspace. */
+int dot_step_update(dot_plan* plan, const void* phi, const void* q, void* alpha, void* beta,
+                    double sigma, double tau, void* q_out, void* w_scratch, void* stream);
+/* a6: the relative KKT residuals of Sec. 5.3 at (phi, z, q, alpha, beta),
+ * the objective and the dual objective; blocks and fills *res (iters and
+ * term are left 0). */
+int dot_step_residuals(dot_plan* plan, const void* phi, const void* z, const void* q,
+                       const void* alpha, const void* beta, dot_result* res, void* stream);
+
+/* One-shot, blocking: allocate, solve, copy rho/m out (either may be NULL),
+ * free. rho_out: n0*prod(n_d+1); m_out: sum_d |G^s_d| doubles. */
+int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* res);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DOTSOCP_H */

@@ -1,0 +1,308 @@
+"""ctypes binding of libdotsocp (include/dotsocp.h), one Python function per C
+entry point with the same name. Only argument marshalling happens here:
+every step of the solver runs in the library's HIP kernels. Device buffers
+are passed as raw pointers (for instance torch.Tensor.data_ptr() of a CUDA
+tensor) and streams as the integer handle of a hipStream_t (0 = default).
+
+Loading fails loudly if the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libdotsocp.so")
+
+DOT_FP64 = 0
+DOT_MIXED = 1
+TERM_NAMES = {-1: "running", 0: "converged", 1: "maxiter", 2: "timeout", 3: "diverged"}
+
+EXPORTED = [
+    "dot_last_error", "dot_plan_create", "dot_plan_destroy", "dot_plan_get_info",
+    "dot_state_reset", "dot_run", "dot_extract",
+    "dot_step_divergence", "dot_step_poisson", "dot_step_rhs_poisson", "dot_step_cone",
+    "dot_step_update", "dot_step_residuals", "dot_solve",
+]
+
+
+class dot_problem(ctypes.Structure):
+    _fields_ = [
+        ("D", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 4),
+        ("rho0", ctypes.POINTER(ctypes.c_double)),
+        ("rho1", ctypes.POINTER(ctypes.c_double)),
+        ("mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("sigma0", ctypes.c_double),
+        ("check_every", ctypes.c_int32),
+        ("adapt_sigma", ctypes.c_int32),
+    ]
+
+
+class dot_result(ctypes.Structure):
+    _fields_ = [
+        ("objective", ctypes.c_double),
+        ("dual_objective", ctypes.c_double),
+        ("eta_dot", ctypes.c_double),
+        ("eta_p", ctypes.c_double),
+        ("eta_d", ctypes.c_double),
+        ("eta_c", ctypes.c_double),
+        ("eta_p_soc", ctypes.c_double),
+        ("eta_d_soc", ctypes.c_double),
+        ("sigma", ctypes.c_double),
+        ("iters", ctypes.c_int32),
+        ("term", ctypes.c_int32),
+        ("checks", ctypes.c_int32),
+        ("sigma_changes", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class dot_plan_info(ctypes.Structure):
+    _fields_ = [
+        ("D", ctypes.c_int32),
+        ("K", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 4),
+        ("nb", ctypes.c_int64),
+        ("scalar_bytes", ctypes.c_int32),
+        ("n_planes", ctypes.c_int32),
+        ("state_bytes", ctypes.c_size_t),
+        ("off_phi", ctypes.c_int32),
+        ("off_q", ctypes.c_int32),
+        ("off_qn", ctypes.c_int32),
+        ("off_alpha", ctypes.c_int32),
+        ("off_beta", ctypes.c_int32),
+        ("off_w", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None) -> ctypes.CDLL:
+    """Load libdotsocp.so (built by paper_2505_05424_amd.build); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"libdotsocp.so not built at {p}; run python -m paper_2505_05424_amd.build")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Loading torch first makes the dynamic linker bind this library to that
+    # runtime, so torch's device pointers and streams are valid here; loading
+    # a second runtime into the process would leave torch without a device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(p)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.dot_last_error.restype = ctypes.c_char_p
+    lib.dot_plan_create.argtypes = [ctypes.POINTER(dot_problem), ctypes.POINTER(vp)]
+    lib.dot_plan_destroy.argtypes = [vp]
+    lib.dot_plan_destroy.restype = None
+    lib.dot_plan_get_info.argtypes = [vp, ctypes.POINTER(dot_plan_info)]
+    lib.dot_state_reset.argtypes = [vp, vp, vp]
+    lib.dot_run.argtypes = [vp, vp, i32, vp, ctypes.POINTER(dot_result)]
+    lib.dot_extract.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), vp]
+    lib.dot_step_divergence.argtypes = [vp, vp, vp, dbl, vp, vp]
+    lib.dot_step_poisson.argtypes = [vp, vp, vp]
+    lib.dot_step_rhs_poisson.argtypes = [vp, vp, vp, dbl, vp, vp]
+    lib.dot_step_cone.argtypes = [vp, vp, vp, dbl, vp, vp]
+    lib.dot_step_update.argtypes = [vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
+    lib.dot_step_residuals.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dot_result), vp]
+    lib.dot_solve.argtypes = [ctypes.POINTER(dot_problem), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result)]
+    for name in EXPORTED:
+        if name not in ("dot_last_error", "dot_plan_destroy"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+class DotError(RuntimeError):
+    pass
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = load().dot_last_error().decode(errors="replace")
+        raise DotError(f"dotsocp error {rc}: {msg}")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_problem(D: int, n: Sequence[int], rho0, rho1, mask=None, tol=1e-6, max_iter=10000,
+                 precision=DOT_FP64, tau=0.0, sigma0=0.0, check_every=0, adapt_sigma=1):
+    """Fill a dot_problem; returns (struct, keepalive) — keep both alive while in use."""
+    r0 = np.ascontiguousarray(rho0, dtype=np.float64).ravel()
+    r1 = np.ascontiguousarray(rho1, dtype=np.float64).ravel()
+    keep = [r0, r1]
+    p = dot_problem()
+    p.D = D
+    for i in range(4):
+        p.n[i] = int(n[i]) if i <= D else 0
+    p.rho0 = _dptr(r0)
+    p.rho1 = _dptr(r1)
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+        keep.append(mk)
+        p.mask = mk.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    p.tol = tol
+    p.max_iter = max_iter
+    p.precision = precision
+    p.tau = tau
+    p.sigma0 = sigma0
+    p.check_every = check_every
+    p.adapt_sigma = adapt_sigma
+    return p, keep
+
+
+class Plan:
+    """Owns a dot_plan handle; `info` describes the state-buffer layout."""
+
+    def __init__(self, handle, info: dot_plan_info, D: int, n):
+        self.handle = handle
+        self.info = info
+        self.D = D
+        self.n = tuple(int(k) for k in n[:D + 1])
+
+    def close(self):
+        if self.handle:
+            load().dot_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dot_plan_create(D, n, rho0, rho1, mask=None, **kw) -> Plan:
+    lib = load()
+    p, keep = make_problem(D, n, rho0, rho1, mask, **kw)
+    h = ctypes.c_void_p()
+    _check(lib.dot_plan_create(ctypes.byref(p), ctypes.byref(h)))
+    info = dot_plan_info()
+    _check(lib.dot_plan_get_info(h, ctypes.byref(info)))
+    return Plan(h, info, D, n)
+
+
+def dot_plan_destroy(plan: Plan):
+    plan.close()
+
+
+def dot_state_reset(plan: Plan, state_ptr: int, stream: int = 0):
+    _check(load().dot_state_reset(plan.handle, ctypes.c_void_p(state_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_run(plan: Plan, state_ptr: int, max_iters: int, stream: int = 0) -> dot_result:
+    r = dot_result()
+    _check(load().dot_run(plan.handle, ctypes.c_void_p(state_ptr), int(max_iters), ctypes.c_void_p(stream),
+                          ctypes.byref(r)))
+    return r
+
+
+def dot_extract(plan: Plan, state_ptr: int, stream: int = 0):
+    """Returns (rho, [m_1..m_D]) as numpy arrays in the paper's exact shapes."""
+    D, n = plan.D, plan.n
+    sp = tuple(k + 1 for k in n[1:])
+    rho = np.zeros((n[0],) + sp)
+    shapes = []
+    for d in range(1, D + 1):
+        s = [n[0] + 1] + list(sp)
+        s[d] = n[d]
+        shapes.append(tuple(s))
+    m = np.zeros(sum(int(np.prod(s)) for s in shapes))
+    _check(load().dot_extract(plan.handle, ctypes.c_void_p(state_ptr), _dptr(rho), _dptr(m),
+                              ctypes.c_void_p(stream)))
+    out, o = [], 0
+    for s in shapes:
+        k = int(np.prod(s))
+        out.append(m[o:o + k].reshape(s))
+        o += k
+    return rho, out
+
+
+def dot_step_divergence(plan, q_ptr, alpha_ptr, sigma, b_ptr, stream=0):
+    _check(load().dot_step_divergence(plan.handle, ctypes.c_void_p(q_ptr), ctypes.c_void_p(alpha_ptr),
+                                      float(sigma), ctypes.c_void_p(b_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_step_poisson(plan, b_ptr, stream=0):
+    _check(load().dot_step_poisson(plan.handle, ctypes.c_void_p(b_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_step_rhs_poisson(plan, q_ptr, alpha_ptr, sigma, phi_ptr, stream=0):
+    _check(load().dot_step_rhs_poisson(plan.handle, ctypes.c_void_p(q_ptr), ctypes.c_void_p(alpha_ptr),
+                                       float(sigma), ctypes.c_void_p(phi_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_step_cone(plan, q_ptr, beta_ptr, sigma, z_ptr, stream=0):
+    _check(load().dot_step_cone(plan.handle, ctypes.c_void_p(q_ptr), ctypes.c_void_p(beta_ptr), float(sigma),
+                                ctypes.c_void_p(z_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_step_update(plan, phi_ptr, q_ptr, alpha_ptr, beta_ptr, sigma, tau, q_out_ptr, w_ptr, stream=0):
+    _check(load().dot_step_update(plan.handle, ctypes.c_void_p(phi_ptr), ctypes.c_void_p(q_ptr),
+                                  ctypes.c_void_p(alpha_ptr), ctypes.c_void_p(beta_ptr), float(sigma), float(tau),
+                                  ctypes.c_void_p(q_out_ptr), ctypes.c_void_p(w_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_step_residuals(plan, phi_ptr, z_ptr, q_ptr, alpha_ptr, beta_ptr, stream=0) -> dot_result:
+    r = dot_result()
+    _check(load().dot_step_residuals(plan.handle, ctypes.c_void_p(phi_ptr), ctypes.c_void_p(z_ptr),
+                                     ctypes.c_void_p(q_ptr), ctypes.c_void_p(alpha_ptr), ctypes.c_void_p(beta_ptr),
+                                     ctypes.byref(r), ctypes.c_void_p(stream)))
+    return r
+
+
+def dot_solve(D, n, rho0, rho1, mask=None, **kw):
+    """One-shot blocking solve from host arrays; returns (result, rho, [m_d])."""
+    lib = load()
+    p, keep = make_problem(D, n, rho0, rho1, mask, **kw)
+    sp = tuple(int(k) + 1 for k in n[1:D + 1])
+    rho = np.zeros((int(n[0]),) + sp)
+    shapes = []
+    for d in range(1, D + 1):
+        s = [int(n[0]) + 1] + list(sp)
+        s[d] = int(n[d])
+        shapes.append(tuple(s))
+    m = np.zeros(sum(int(np.prod(s)) for s in shapes))
+    r = dot_result()
+    _check(lib.dot_solve(ctypes.byref(p), _dptr(rho), _dptr(m), ctypes.byref(r)))
+    out, o = [], 0
+    for s in shapes:
+        k = int(np.prod(s))
+        out.append(m[o:o + k].reshape(s))
+        o += k
+    return r, rho, out
+
+
+# ---- padded-box marshalling (host side, numpy) -----------------------------
+def box_shape(n):
+    return tuple(int(k) + 1 for k in n)
+
+
+def to_box(arr, n):
+    """Zero-pad an exact-shape array (cells or G^s_d) to the node box."""
+    full = box_shape(n)
+    a = np.asarray(arr)
+    pad = [(0, f - s) for s, f in zip(a.shape, full)]
+    return np.pad(a, pad)
+
+
+def from_box(plane, shape):
+    return np.asarray(plane)[tuple(slice(0, s) for s in shape)]

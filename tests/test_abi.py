@@ -1,0 +1,50 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/dotsocp.h declares, and rejects invalid problems before touching a
+device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2505_05424_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dotsocp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dot_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_names():
+    assert set(_declared()) == set(B.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def _bad(**kw):
+    base = dict(D=1, n=(4, 8), rho0=np.ones(9) / 9, rho1=np.ones(9) / 9)
+    base.update(kw)
+    D = base.pop("D")
+    n = base.pop("n")
+    r0 = base.pop("rho0")
+    r1 = base.pop("rho1")
+    with pytest.raises(B.DotError) as e:
+        B.dot_plan_create(D, n, r0, r1, **base)
+    return str(e.value)
+
+
+def test_invalid_problems_are_rejected():
+    assert "equal" in _bad(rho1=np.r_[np.ones(8) / 9, 2.0 / 9])      # mass mismatch
+    assert "non-negative" in _bad(rho0=np.r_[-1.0, np.ones(8) / 4])   # negative mass
+    assert "finite" in _bad(rho0=np.r_[np.nan, np.ones(8) / 8])        # NaN
+    assert "D must be" in _bad(D=4, n=(2, 2, 2, 2))
+    assert "segment" in _bad(n=(0, 8))
+    assert "tau" in _bad(tau=2.5)
+    assert "positive total" in _bad(rho0=np.zeros(9), rho1=np.zeros(9))
