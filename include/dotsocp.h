@@ -82,6 +82,9 @@ typedef struct {
   double sigma0;          /* initial penalty; 0 selects 1.0 */
   int32_t check_every;    /* residual-check cadence; 0 selects 5 */
   int32_t adapt_sigma;    /* 1: sigma rule of Sec. 5.3 on the growing schedule */
+  int32_t sigma_gap0;     /* first sigma decision after this many iterations; 0 selects 10 */
+  double sigma_growth;    /* gap growth g' = floor(growth*g) + check_every, rounded down
+                             to a multiple of check_every; 0 selects 1.2 */
 } dot_problem;
 
 typedef struct {
@@ -111,7 +114,7 @@ typedef struct dot_plan dot_plan;
 const char* dot_last_error(void);
 
 /* Validate p (mass balance, sizes, finite data), build c, omega, the cosine
- * transform tables and eigenvalues of A^*A (Sec. 4, Alg. 2 line 2) on the
+ * transform tables and eigenvalues of A^*A (Sec. 4, phi-step of Algorithm 2) on the
  * current HIP device. The plan copies everything it needs from p. */
 int dot_plan_create(const dot_problem* p, dot_plan** out);
 void dot_plan_destroy(dot_plan* plan);
@@ -134,10 +137,11 @@ int dot_extract(dot_plan* plan, const void* state, double* rho_out, double* m_ou
 
 /* ---- step-level entry points (one row of the hot path each) ------------ */
 
-/* a3: b = A^*(q - alpha/sigma) - c/sigma (Alg. 2 line 1), node plane b. */
+/* a3: b = A^*(q - alpha/sigma) - c/sigma (right-hand side of the phi-step of
+ * Algorithm 2), node plane b. */
 int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double sigma,
                         void* b, void* stream);
-/* a4: phi = (A^*A)^+ b in place on the node plane (Alg. 2 line 2): forward
+/* a4: phi = (A^*A)^+ b in place on the node plane (phi-step of Algorithm 2): forward
  * DCT-II on every axis, divide by the eigenvalues, zero mode set to 0 (phi in
  * rge A^*), inverse transform. */
 int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
@@ -145,11 +149,12 @@ int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
  * transform pass): phi from (q, alpha, sigma). */
 int dot_step_rhs_poisson(dot_plan* plan, const void* q, const void* alpha, double sigma,
                          void* phi, void* stream);
-/* a1 + a2: z = Pi_Q(B_omega F q + d - beta/sigma) (Alg. 2 line 3; eq. app-proj
+/* a1 + a2: z = Pi_Q(B_omega F q + d - beta/sigma) (z-step of Algorithm 2; eq. app-proj
  * per cell, eq. fdetails for the gather), K planes. */
 int dot_step_cone(dot_plan* plan, const void* q, const void* beta, double sigma,
                   void* z, void* stream);
-/* a5: q_new, alpha, beta updates of Alg. 2 lines 4-6 from phi and the old
+/* a5: q_new, alpha, beta updates of Algorithm 2 (q-step and both
+ * multiplier steps) from phi and the old
  * (q, alpha, beta); alpha and beta are updated in place, q_new written to
  * q_out; w_scratch holds 4D planes of workspace. */
 int dot_step_update(dot_plan* plan, const void* phi, const void* q, void* alpha, void* beta,
@@ -159,6 +164,28 @@ int dot_step_update(dot_plan* plan, const void* phi, const void* q, void* alpha,
  * term are left 0). */
 int dot_step_residuals(dot_plan* plan, const void* phi, const void* z, const void* q,
                        const void* alpha, const void* beta, dot_result* res, void* stream);
+
+/* ---- measurement hook ---------------------------------------------------- */
+/* Kernel classes of one iteration, for dot_profile_select. */
+typedef enum {
+  DOT_K_DCT_FIRST = 0, /* time-axis forward pass with the divergence fused in */
+  DOT_K_DCT_MID = 1,   /* forward passes on the middle spatial axes */
+  DOT_K_DCT_LAST = 2,  /* last axis: forward, 1/Lambda, inverse */
+  DOT_K_DCT_INV = 3,   /* inverse passes on the other axes */
+  DOT_K_CONE = 4,      /* cone gather + projection + q0/alpha0 update */
+  DOT_K_QD = 5,        /* q_d / alpha_d update */
+  DOT_K_BETA = 6,      /* beta update */
+  DOT_K_RESID = 7,     /* residual partial sums (checks only) */
+  DOT_K_FINAL = 8,     /* residual finalize + sigma rule (checks only) */
+  DOT_K_NONE = -1
+} dot_kernel_class;
+
+/* Record HIP events around every launch of one kernel class inside dot_run
+ * on its stream (DOT_K_NONE switches recording off); dot_profile_read returns
+ * the summed event time in ms and the number of launches since the last read
+ * and clears them. */
+int dot_profile_select(dot_plan* plan, int32_t kernel_class);
+int dot_profile_read(dot_plan* plan, double* total_ms, int64_t* launches);
 
 /* One-shot, blocking: allocate, solve, copy rho/m out (either may be NULL),
  * free. rho_out: n0*prod(n_d+1); m_out: sum_d |G^s_d| doubles. */

@@ -464,11 +464,12 @@ class SolveResult:
 
 
 def solve(P: Problem, tol=1e-6, max_iter=10000, tau=1.9, sigma0=1.0, check_every=5,
-          adapt_sigma=True, state: Optional[State] = None, on_check=None) -> SolveResult:
+          adapt_sigma=True, state: Optional[State] = None, on_check=None,
+          sigma_gap0=10, sigma_growth=1.2) -> SolveResult:
     """Run Algorithm 2 from zero (or `state`), checking eta_dot and adapting
     sigma every `check_every` iterations; stop at eta_dot <= tol."""
     S = state if state is not None else zero_state(P, sigma0)
-    upd = set(sigma_update_points(S.k + max_iter + 1))
+    upd = set(sigma_update_points(S.k + max_iter + 1, sigma_gap0, sigma_growth, check_every))
     hist = []
     res = {}
     conv = False
@@ -499,10 +500,11 @@ def solve(P: Problem, tol=1e-6, max_iter=10000, tau=1.9, sigma0=1.0, check_every
                        dual_objective(P, S.alpha), hist, secs)
 
 
-def run_fixed(P: Problem, iters, tau=1.9, sigma0=1.0, check_every=5, adapt_sigma=True) -> SolveResult:
+def run_fixed(P: Problem, iters, tau=1.9, sigma0=1.0, check_every=5, adapt_sigma=True,
+              sigma_gap0=10, sigma_growth=1.2) -> SolveResult:
     """Exactly `iters` iterations with the same check/sigma schedule and no stop."""
-    return solve(P, tol=-1.0, max_iter=iters, tau=tau, sigma0=sigma0,
-                 check_every=check_every, adapt_sigma=adapt_sigma)
+    return solve(P, tol=-1.0, max_iter=iters, tau=tau, sigma0=sigma0, check_every=check_every,
+                 adapt_sigma=adapt_sigma, sigma_gap0=sigma_gap0, sigma_growth=sigma_growth)
 
 
 def duality_gap(p, d):

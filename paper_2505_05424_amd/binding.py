@@ -25,8 +25,11 @@ EXPORTED = [
     "dot_last_error", "dot_plan_create", "dot_plan_destroy", "dot_plan_get_info",
     "dot_state_reset", "dot_run", "dot_extract",
     "dot_step_divergence", "dot_step_poisson", "dot_step_rhs_poisson", "dot_step_cone",
-    "dot_step_update", "dot_step_residuals", "dot_solve",
+    "dot_step_update", "dot_step_residuals", "dot_profile_select", "dot_profile_read", "dot_solve",
 ]
+
+KERNEL_CLASSES = {"dct_first": 0, "dct_mid": 1, "dct_last": 2, "dct_inv": 3, "cone": 4, "qd": 5,
+                  "beta": 6, "resid": 7, "final": 8}
 
 
 class dot_problem(ctypes.Structure):
@@ -43,6 +46,8 @@ class dot_problem(ctypes.Structure):
         ("sigma0", ctypes.c_double),
         ("check_every", ctypes.c_int32),
         ("adapt_sigma", ctypes.c_int32),
+        ("sigma_gap0", ctypes.c_int32),
+        ("sigma_growth", ctypes.c_double),
     ]
 
 
@@ -120,6 +125,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_step_cone.argtypes = [vp, vp, vp, dbl, vp, vp]
     lib.dot_step_update.argtypes = [vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
     lib.dot_step_residuals.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dot_result), vp]
+    lib.dot_profile_select.argtypes = [vp, i32]
+    lib.dot_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.dot_solve.argtypes = [ctypes.POINTER(dot_problem), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result)]
     for name in EXPORTED:
@@ -144,7 +151,8 @@ def _dptr(a: np.ndarray):
 
 
 def make_problem(D: int, n: Sequence[int], rho0, rho1, mask=None, tol=1e-6, max_iter=10000,
-                 precision=DOT_FP64, tau=0.0, sigma0=0.0, check_every=0, adapt_sigma=1):
+                 precision=DOT_FP64, tau=0.0, sigma0=0.0, check_every=0, adapt_sigma=1,
+                 sigma_gap0=0, sigma_growth=0.0):
     """Fill a dot_problem; returns (struct, keepalive) — keep both alive while in use."""
     r0 = np.ascontiguousarray(rho0, dtype=np.float64).ravel()
     r1 = np.ascontiguousarray(rho1, dtype=np.float64).ravel()
@@ -166,6 +174,8 @@ def make_problem(D: int, n: Sequence[int], rho0, rho1, mask=None, tol=1e-6, max_
     p.sigma0 = sigma0
     p.check_every = check_every
     p.adapt_sigma = adapt_sigma
+    p.sigma_gap0 = sigma_gap0
+    p.sigma_growth = sigma_growth
     return p, keep
 
 
@@ -267,6 +277,18 @@ def dot_step_residuals(plan, phi_ptr, z_ptr, q_ptr, alpha_ptr, beta_ptr, stream=
                                      ctypes.c_void_p(q_ptr), ctypes.c_void_p(alpha_ptr), ctypes.c_void_p(beta_ptr),
                                      ctypes.byref(r), ctypes.c_void_p(stream)))
     return r
+
+
+def dot_profile_select(plan, kernel_class: int):
+    _check(load().dot_profile_select(plan.handle, int(kernel_class)))
+
+
+def dot_profile_read(plan):
+    """Returns (total_ms, launches) of the selected kernel class since the last read."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().dot_profile_read(plan.handle, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 def dot_solve(D, n, rho0, rho1, mask=None, **kw):

@@ -69,7 +69,8 @@ struct dot_plan {
   int D = 0, K = 0;
   int n[4] = {0, 0, 0, 0};
   double tau = 1.9, sigma0 = 1.0, tol = 1e-6;
-  int max_iter = 1000, cadence = 5, adapt = 1;
+  int max_iter = 1000, cadence = 5, adapt = 1, gap0 = 10;
+  double growth = 1.2;
   double vol = 1.0, c_norm2 = 0.0, d_norm2 = 0.0;
   int64_t nblocks = 0;  // blocks of kBlock over one plane
   // device constant tables
@@ -91,6 +92,12 @@ struct dot_plan {
   int off_phi = 0, off_q = 0, off_qn = 0, off_alpha = 0, off_beta = 0, off_w = 0;
   size_t planes_bytes = 0, ctl_offset = 0, partials_offset = 0, state_bytes = 0;
   int device = 0;
+  // measurement hook: events around launches of one kernel class
+  int prof_class = -1;
+  std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
+  size_t prof_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_launches = 0;
 };
 
 namespace {
@@ -195,6 +202,46 @@ double* state_partials(void* state, const dot_plan* P) {
   return reinterpret_cast<double*>(static_cast<char*>(state) + P->partials_offset);
 }
 
+// Event bracket for the measurement hook; a no-op unless `cls` is selected.
+struct ProfScope {
+  dot_plan* P;
+  hipStream_t st;
+  bool on;
+  hipEvent_t stop = nullptr;
+  ProfScope(const dot_plan* Pc, int cls, hipStream_t s) : P(const_cast<dot_plan*>(Pc)), st(s), on(Pc->prof_class == cls) {
+    if (!on) return;
+    if (P->prof_used + 2 > P->prof_ev.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          on = false;
+          return;
+        }
+        P->prof_ev.push_back(e);
+      }
+    }
+    hipEvent_t start = P->prof_ev[P->prof_used];
+    stop = P->prof_ev[P->prof_used + 1];
+    P->prof_used += 2;
+    (void)hipEventRecord(start, st);
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(stop, st);
+  }
+};
+
+// Sum the recorded event pairs (the stream must be synchronised).
+void prof_collect(dot_plan* P) {
+  for (size_t k = 0; k + 1 < P->prof_used; k += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, P->prof_ev[k], P->prof_ev[k + 1]) == hipSuccess) {
+      P->prof_ms += ms;
+      P->prof_launches += 1;
+    }
+  }
+  P->prof_used = 0;
+}
+
 template <typename T>
 const AxisTab<T>& tab_of(const dot_plan* P, int a);
 template <>
@@ -211,8 +258,20 @@ int launch_pass(const dot_plan* P, int a, T* pl, const T* q, const T* al, const 
   pa.ncols = g.nb / g.N[a];
   const size_t smem = (size_t)g.N[a] * (kCW + 1) * sizeof(T);
   auto fn = k_axis_pass<T, D, KIND, SRC>;
-  HIP_OK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  // the LDS opt-in is per kernel and process; set it once to the device maximum
+  static int smem_set = 0;
+  if (!smem_set) {
+    int max_smem = 0;
+    HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
+    HIP_OK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_smem));
+    smem_set = 1;
+  }
   const unsigned grid = (unsigned)((pa.ncols + kCW - 1) / kCW);
+  const int cls = SRC == kSrcDivergence ? DOT_K_DCT_FIRST
+                  : KIND == kFwdScaleInv ? DOT_K_DCT_LAST
+                  : KIND == kInv         ? DOT_K_DCT_INV
+                                         : (a == 0 ? DOT_K_DCT_FIRST : DOT_K_DCT_MID);
+  ProfScope ps(P, cls, st);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kDctWaves * 64), smem, st, g, pa, tab_of<T>(P, a), pl, q, al,
                      P->c_lo, P->c_hi, (const T*)P->lam_other, (const T*)P->lam_last, ctl, sigma);
   HIP_OK(hipGetLastError());
@@ -243,13 +302,22 @@ template <typename T, int D>
 int run_update(const dot_plan* P, const T* phi, const T* q, T* alpha, T* beta, T* qn, T* W, Ctl* ctl,
                double* partials, int check, hipStream_t st) {
   const Geo& g = P->g;
-  hipLaunchKernelGGL((k_cone_q0<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, q, alpha, beta,
-                     P->sw_sp, qn, W, ctl);
+  {
+    ProfScope ps(P, DOT_K_CONE, st);
+    hipLaunchKernelGGL((k_cone_q0<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, q, alpha, beta,
+                       P->sw_sp, qn, W, ctl);
+  }
   HIP_OK(hipGetLastError());
-  hipLaunchKernelGGL((k_qd<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, alpha, P->om_sp, qn, W, ctl);
+  {
+    ProfScope ps(P, DOT_K_QD, st);
+    hipLaunchKernelGGL((k_qd<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, alpha, P->om_sp, qn, W, ctl);
+  }
   HIP_OK(hipGetLastError());
-  hipLaunchKernelGGL((k_beta<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, q, qn, beta, P->sw_sp, ctl,
-                     partials, check);
+  {
+    ProfScope ps(P, DOT_K_BETA, st);
+    hipLaunchKernelGGL((k_beta<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, q, qn, beta, P->sw_sp, ctl,
+                       partials, check);
+  }
   HIP_OK(hipGetLastError());
   return DOT_OK;
 }
@@ -267,10 +335,16 @@ template <typename T, int D>
 int run_check(const dot_plan* P, const T* phi, const T* q, const T* alpha, const T* beta, Ctl* ctl,
               double* partials, int update_ctl, hipStream_t st) {
   const Geo& g = P->g;
-  hipLaunchKernelGGL((k_resid<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, q, alpha, beta, P->om_sp,
-                     P->sw_sp, P->c_lo, P->c_hi, update_ctl ? ctl : nullptr, partials);
+  {
+    ProfScope ps(P, DOT_K_RESID, st);
+    hipLaunchKernelGGL((k_resid<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, q, alpha, beta, P->om_sp,
+                       P->sw_sp, P->c_lo, P->c_hi, update_ctl ? ctl : nullptr, partials);
+  }
   HIP_OK(hipGetLastError());
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, fin_args(P), partials, ctl, update_ctl);
+  {
+    ProfScope ps(P, DOT_K_FINAL, st);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, fin_args(P), partials, ctl, update_ctl);
+  }
   HIP_OK(hipGetLastError());
   return DOT_OK;
 }
@@ -302,11 +376,13 @@ int run_iters(dot_plan* P, void* state, int max_iters, hipStream_t st, dot_resul
     if ((j + 1) % poll == 0 || j + 1 == max_iters) {
       HIP_OK(hipMemcpyAsync(P->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
+      prof_collect(P);
       stopped = P->host_ctl->stop;
     }
   }
   HIP_OK(hipMemcpyAsync(P->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
+  prof_collect(P);
   if (res) {
     const Ctl& c = *P->host_ctl;
     res->objective = c.objective;
@@ -419,6 +495,7 @@ int validate(const dot_problem* p) {
   if (p->tau < 0 || p->tau >= 2) return fail(DOT_EINVAL, "tau must be in (0, 2) (0 selects 1.9)");
   if (p->sigma0 < 0 || !std::isfinite(p->sigma0)) return fail(DOT_EINVAL, "sigma0 must be > 0 (0 selects 1)");
   if (p->check_every < 0) return fail(DOT_EINVAL, "check_every must be >= 0");
+  if (p->sigma_gap0 < 0 || p->sigma_growth < 0) return fail(DOT_EINVAL, "sigma schedule must be >= 0");
   int64_t nx = 1;
   for (int d = 1; d <= p->D; ++d) nx *= (int64_t)p->n[d] + 1;
   double m0 = 0.0, m1 = 0.0;
@@ -442,6 +519,7 @@ const char* dot_last_error(void) { return g_err.c_str(); }
 
 void dot_plan_destroy(dot_plan* P) {
   if (!P) return;
+  for (auto e : P->prof_ev) (void)hipEventDestroy(e);
   (void)hipFree(P->sw_sp);
   (void)hipFree(P->om_sp);
   (void)hipFree(P->c_lo);
@@ -473,6 +551,8 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   P->max_iter = p->max_iter;
   P->cadence = p->check_every > 0 ? p->check_every : 5;
   P->adapt = p->adapt_sigma;
+  P->gap0 = p->sigma_gap0 > 0 ? p->sigma_gap0 : 10;
+  P->growth = p->sigma_growth > 0 ? p->sigma_growth : 1.2;
   HIP_OK(hipGetDevice(&P->device));
   Geo& g = P->g;
   g.D = D;
@@ -575,8 +655,9 @@ int dot_state_reset(dot_plan* P, void* state, void* stream) {
   h.tol = P->tol;
   h.iter = 0;
   h.stop = 0;
-  h.next_update = 10;
-  h.gap = 10;
+  h.next_update = P->gap0;
+  h.gap = P->gap0;
+  h.growth = P->growth;
   h.adapt = P->adapt;
   h.cadence = P->cadence;
   *P->host_ctl = h;
@@ -667,6 +748,24 @@ int dot_step_residuals(dot_plan* P, const void* phi, const void* z, const void* 
   res->eta_c = c.eta[3];
   res->eta_p_soc = c.eta[4];
   res->eta_d_soc = c.eta[5];
+  return DOT_OK;
+}
+
+int dot_profile_select(dot_plan* P, int32_t kernel_class) {
+  if (!P || kernel_class < -1 || kernel_class > DOT_K_FINAL) return fail(DOT_EINVAL, "bad kernel class");
+  P->prof_class = kernel_class;
+  P->prof_used = 0;
+  P->prof_ms = 0.0;
+  P->prof_launches = 0;
+  return DOT_OK;
+}
+
+int dot_profile_read(dot_plan* P, double* total_ms, int64_t* launches) {
+  if (!P) return fail(DOT_EINVAL, "null plan");
+  if (total_ms) *total_ms = P->prof_ms;
+  if (launches) *launches = P->prof_launches;
+  P->prof_ms = 0.0;
+  P->prof_launches = 0;
   return DOT_OK;
 }
 

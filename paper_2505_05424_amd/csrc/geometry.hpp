@@ -42,6 +42,7 @@ struct Ctl {
   int32_t gap;           // current gap of the sigma schedule
   int32_t adapt;         // apply the sigma rule
   int32_t cadence;       // residual-check cadence
+  double growth;         // growth factor of the sigma schedule gaps
 };
 
 }  // namespace dot

@@ -1,5 +1,5 @@
-// Cosine-transform passes of the space-time Poisson solve (Sec. 4, Alg. 2
-// line 2): A^*A is the sum over axes of path-graph Laplacians / h_d^2, whose
+// Cosine-transform passes of the space-time Poisson solve (Sec. 4, the
+// phi-step of Algorithm 2): A^*A is the sum over axes of path-graph Laplacians / h_d^2, whose
 // eigenvectors are the orthonormal DCT-II basis of length N_d = n_d + 1.
 //
 // One pass transforms every line of one axis. A workgroup stages a tile of
@@ -157,7 +157,7 @@ __device__ __forceinline__ void tile_inverse(T* tile, const AxisTab<T>& a) {
 }
 
 // Divergence b = A^*(q - alpha/sigma) - c/sigma at node (t, spatial index xs),
-// Alg. 2 line 1 (zero extension outside each staggered set).
+// the right-hand side of the phi-step of Algorithm 2 (zero extension outside each staggered set).
 template <typename T, int D>
 __device__ __forceinline__ T divergence_at(const Geo& g, const T* __restrict__ q, const T* __restrict__ al,
                                            const double* __restrict__ c_lo, const double* __restrict__ c_hi,

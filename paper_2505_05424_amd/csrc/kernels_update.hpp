@@ -1,5 +1,6 @@
 // Cone gather + projection, proximal q update, multiplier updates and the
-// KKT-residual reductions of Algorithm 2 (lines 3-6) and Sec. 5.3.
+// KKT-residual reductions of Algorithm 2 (z-step, q-step, multiplier steps)
+// and Sec. 5.3.
 //
 // Every kernel is a coalesced sweep over the padded box: one lane per node
 // (or per cell), neighbours along axis d at +-stride[d]. The four maps F^d_v
@@ -25,7 +26,8 @@ __device__ __forceinline__ void node_coords(const Geo& g, int64_t i, int (&x)[kM
   x[0] = (int)r;
 }
 
-// u = B_omega F q + d - beta/sigma at cell i (Alg. 2 line 3), in double.
+// u = B_omega F q + d - beta/sigma at cell i (argument of the z-step
+// projection of Algorithm 2), in double.
 // sw = sqrt(omega/2) of the cell.
 template <typename T, int D>
 __device__ __forceinline__ void cone_input(const Geo& g, const T* __restrict__ q, const T* __restrict__ beta,
@@ -421,7 +423,7 @@ k_finalize(FinArgs fa, const double* __restrict__ partials, Ctl* __restrict__ ct
       ctl->sigma_changes += 1;
     }
     while (ctl->next_update <= ctl->iter) {
-      const int nxt = (int)floor(1.2 * (double)ctl->gap) + ctl->cadence;
+      const int nxt = (int)floor(ctl->growth * (double)ctl->gap) + ctl->cadence;
       ctl->gap = nxt - nxt % ctl->cadence;
       ctl->next_update += ctl->gap;
     }

@@ -1,0 +1,49 @@
+"""Fixed-iteration runs of named workloads, for rocprofv3 kernel traces and
+counter collection:
+
+  rocprofv3 --kernel-trace --stats --output-format csv -d OUT -- \
+      python3 -m paper_2505_05424_amd.profile_run --workload 2d-32x64x64 --iters 500
+
+Workloads: 1d-16x32, 2d-32x64x64, 2d-64x256x256 (add --mixed for the
+mixed-precision mode)."""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import dotgen  # noqa: E402
+from paper_2505_05424_amd import binding as B  # noqa: E402
+
+WORKLOADS = {
+    "1d-16x32": dotgen.config1_instance,
+    "2d-32x64x64": dotgen.config2_instance,
+    "2d-64x256x256": dotgen.config3_instance,
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", action="append", required=True)
+    ap.add_argument("--iters", type=int, action="append")
+    ap.add_argument("--mixed", action="store_true")
+    a = ap.parse_args()
+    import torch
+    st = torch.cuda.current_stream().cuda_stream
+    iters = a.iters or [100] * len(a.workload)
+    for name, its in zip(a.workload, iters):
+        inst = WORKLOADS[name]()
+        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=-1.0, max_iter=its,
+                                 precision=B.DOT_MIXED if a.mixed else B.DOT_FP64)
+        s = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+        B.dot_state_reset(plan, s.data_ptr(), st)
+        r = B.dot_run(plan, s.data_ptr(), its, st)
+        torch.cuda.synchronize()
+        print(f"{name} iters={r.iters} eta={r.eta_dot:.3e}", flush=True)
+        plan.close()
+
+
+if __name__ == "__main__":
+    main()

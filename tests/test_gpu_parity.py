@@ -99,7 +99,7 @@ def test_step_update(name):
     B.dot_step_update(plan, pd.data_ptr(), qd.data_ptr(), ad.data_ptr(), bed.data_ptr(), sigma, tau,
                       qo.data_ptr(), wd.data_ptr(), st)
     S = O.State(phi, np.zeros_like(be), q, al, be, sigma)
-    # the oracle's update for a given phi: reuse iterate's lines 3-6 with phi fixed
+    # the oracle's z-step, q-step and multiplier steps for this phi
     z = O.proj_soc(O.step_cone_input(P, q, be, sigma))
     qn = O.step_q(P, phi, z, al, be, sigma)
     Aphi = O.grad(phi, g)
