@@ -25,8 +25,10 @@ k_divergence(Geo g, const T* __restrict__ q, const T* __restrict__ al, const dou
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nb) return;
   const int t = (int)(i / g.stride[0]);
-  const int64_t xs = i % g.stride[0];
-  b[i] = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, t, xs);
+  const uint32_t xs = (uint32_t)(i % g.stride[0]);
+  int x[kMaxAxes];
+  spatial_coords<D>(g, xs, x);
+  b[i] = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, t, xs, x);
 }
 
 namespace {
@@ -117,23 +119,35 @@ double dct_entry(int L, int k, int j) {
   return s * std::cos(M_PI * (double)m / (2.0 * L));
 }
 
-int pad_to(int v, int m) { return (v + m - 1) / m * m; }
+int ksteps(int n_in) { return ((n_in + 3) / 4 + kU - 1) / kU * kU; }
+
+// Fragment-major copy of an n_out x n_in matrix H in chunks of kU k-steps
+// (see AxisTab), with one trailing zero chunk per row block.
+template <typename T, typename F>
+void frag_major(std::vector<T>& out, int n_out, int n_in, F H) {
+  const int rb = (n_out + 15) / 16, nch = ksteps(n_in) / kU + 1;
+  const size_t base = out.size();
+  out.resize(base + (size_t)rb * nch * 64 * kU, T(0));
+  for (int m = 0; m < rb; ++m)
+    for (int ch = 0; ch < nch; ++ch)
+      for (int l = 0; l < 64; ++l)
+        for (int u = 0; u < kU; ++u) {
+          const int st = ch * kU + u;
+          const int r = m * 16 + l % 16, c = st * 4 + l / 16;
+          if (r < n_out && c < n_in)
+            out[base + (((size_t)m * nch + ch) * 64 + l) * kU + u] = (T)H(r, c);
+        }
+}
 
 template <typename T>
 int build_axis(dot_plan* P, int a, void** buf, AxisTab<T>* tab) {
   const int L = P->g.N[a];
   const int M = L / 2, ne = L - M, no = M;
-  const int nep = pad_to(std::max(ne, 1), kR), nop = pad_to(std::max(no, 1), kR);
-  std::vector<T> fe((size_t)ne * nep, T(0)), fo((size_t)std::max(no, 1) * nop, T(0));
-  std::vector<T> ie((size_t)ne * nep, T(0)), io((size_t)std::max(no, 1) * nop, T(0));
-  for (int j = 0; j < ne; ++j)
-    for (int k = 0; k < ne; ++k) fe[(size_t)j * nep + k] = (T)dct_entry(L, 2 * k, j);
-  for (int j = 0; j < no; ++j)
-    for (int k = 0; k < no; ++k) fo[(size_t)j * nop + k] = (T)dct_entry(L, 2 * k + 1, j);
-  for (int k = 0; k < ne; ++k)
-    for (int j = 0; j < ne; ++j) ie[(size_t)k * nep + j] = (T)dct_entry(L, 2 * k, j);
-  for (int k = 0; k < no; ++k)
-    for (int j = 0; j < no; ++j) io[(size_t)k * nop + j] = (T)dct_entry(L, 2 * k + 1, j);
+  std::vector<T> fe, fo, ie, io;
+  frag_major(fe, ne, ne, [&](int k, int j) { return dct_entry(L, 2 * k, j); });
+  frag_major(fo, no, no, [&](int k, int j) { return dct_entry(L, 2 * k + 1, j); });
+  frag_major(ie, ne, ne, [&](int j, int k) { return dct_entry(L, 2 * k, j); });
+  frag_major(io, no, no, [&](int j, int k) { return dct_entry(L, 2 * k + 1, j); });
   std::vector<T> all;
   all.insert(all.end(), fe.begin(), fe.end());
   all.insert(all.end(), fo.begin(), fo.end());
@@ -151,9 +165,28 @@ int build_axis(dot_plan* P, int a, void** buf, AxisTab<T>* tab) {
   tab->M = M;
   tab->ne = ne;
   tab->no = no;
-  tab->ne_pad = nep;
-  tab->no_pad = nop;
+  tab->rb_e = (ne + 15) / 16;
+  tab->rb_o = (no + 15) / 16;
+  tab->ks_e = ksteps(ne);
+  tab->ks_o = ksteps(no);
   return DOT_OK;
+}
+
+// Waves per workgroup of a transform pass: enough for every work item of the
+// axis to fit in MfmaOps<T>::kItems rounds.
+template <typename T>
+int pass_waves(int L) {
+  const int M = L / 2, ne = L - M, no = M;
+  const int items = 2 * ((ne + 15) / 16 + (no + 15) / 16);
+  const int w = (items + MfmaOps<T>::kItems - 1) / MfmaOps<T>::kItems;
+  return std::max(1, std::min(kMaxWaves, std::max(w, 4)));
+}
+
+template <typename T>
+bool axis_fits(int L) {
+  const int M = L / 2, ne = L - M, no = M;
+  const int items = 2 * ((ne + 15) / 16 + (no + 15) / 16);
+  return items <= MfmaOps<T>::kItems * kMaxWaves;
 }
 
 double axis_eig(int N, int nseg, int k) {
@@ -272,7 +305,7 @@ int launch_pass(const dot_plan* P, int a, T* pl, const T* q, const T* al, const 
                   : KIND == kInv         ? DOT_K_DCT_INV
                                          : (a == 0 ? DOT_K_DCT_FIRST : DOT_K_DCT_MID);
   ProfScope ps(P, cls, st);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(kDctWaves * 64), smem, st, g, pa, tab_of<T>(P, a), pl, q, al,
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(pass_waves<T>(g.N[a]) * 64), smem, st, g, pa, tab_of<T>(P, a), pl, q, al,
                      P->c_lo, P->c_hi, (const T*)P->lam_other, (const T*)P->lam_last, ctl, sigma);
   HIP_OK(hipGetLastError());
   return DOT_OK;
@@ -570,14 +603,15 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   }
   g.nb = s;
   g.nx = g.nb / g.N[0];
+  // kernels index planes with 32-bit offsets up to a few planes apart
+  if (g.nb > ((int64_t)1 << 28)) return fail(DOT_EINVAL, "a plane must hold at most 2^28 nodes");
   // LDS capacity of one transform tile
   int max_smem = 0;
   HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
   for (int a = 0; a <= D; ++a) {
     const size_t need = (size_t)g.N[a] * (kCW + 1) * P->scalar_bytes;
-    const int M = g.N[a] / 2;
-    const int blocks = pad_to(std::max(g.N[a] - M, 1), kR) / kR + pad_to(std::max(M, 1), kR) / kR;
-    if ((int64_t)need > max_smem || blocks > kMaxBlk * kDctWaves)
+    const bool fits = P->precision == DOT_FP64 ? axis_fits<double>(g.N[a]) : axis_fits<float>(g.N[a]);
+    if ((int64_t)need > max_smem || !fits)
       return fail(DOT_EINVAL, "axis of " + std::to_string(g.N[a]) + " nodes exceeds the transform tile capacity");
   }
   // problem data

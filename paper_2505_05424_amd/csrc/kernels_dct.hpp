@@ -3,37 +3,67 @@
 // eigenvectors are the orthonormal DCT-II basis of length N_d = n_d + 1.
 //
 // One pass transforms every line of one axis. A workgroup stages a tile of
-// kCW lines x L points in LDS (one line per lane), folds each line into its
-// symmetric and antisymmetric halves (x_j +- x_{L-1-j}), and multiplies the
-// halves by the even-row and odd-row halves of the transform matrix with
-// register blocks of kR outputs per lane. The matrix rows are the same for
-// all lanes of a wave, so they are read as wave-uniform (scalar) loads.
-// Passes work in place: a tile holds whole lines, so each workgroup reads and
-// writes only its own elements.
+// kCW lines x L points in LDS (one line per column), folds each line into its
+// symmetric and antisymmetric halves (x_j +- x_{L-1-j}), which the even-row
+// and odd-row halves of the transform matrix act on separately, and runs both
+// half-size products on the matrix cores (16x16x4 MFMA, FP64 or FP32): the
+// matrix is the A operand, streamed from a fragment-major table (one
+// coalesced element per lane per k-step, prefetched one step ahead), and the
+// folded lines are the B operand, read from LDS. Passes work in place: a tile
+// holds whole lines, so a workgroup reads and writes only its own elements.
 #pragma once
 #include "geometry.hpp"
 
 namespace dot {
 
-constexpr int kCW = 64;       // lines per tile (one per lane)
-constexpr int kR = 16;        // outputs per register block
-constexpr int kDctWaves = 8;  // waves per workgroup
-constexpr int kMaxBlk = 3;    // register blocks per wave
+constexpr int kCW = 64;        // lines per tile
+constexpr int kMaxWaves = 16;  // waves per workgroup (upper bound)
+constexpr int kU = 8;          // k-steps per prefetch chunk
 
-// Folded transform tables of one axis (device pointers).
-//   fe[j][k'] = C[2k'][j]   (j < ne inputs: u_0..u_{M-1}, then the middle point if L odd)
-//   fo[j][k'] = C[2k'+1][j] (j < M inputs v_j)
-//   ie[k'][j] = C[2k'][j]   (k' < ne inputs X_{2k'}, j < ne outputs E_j)
-//   io[k'][j] = C[2k'+1][j] (k' < M inputs X_{2k'+1}, j < M outputs O_j)
-// C[k][j] = s_k cos(pi k (2j+1) / (2L)), s_0 = sqrt(1/L), s_k = sqrt(2/L).
-// Rows are padded with zeros to ne_pad / no_pad columns (multiples of kR).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct MfmaOps;
+template <> struct MfmaOps<double> {
+  typedef dbl4 acc_t;
+  typedef double chunk_t __attribute__((ext_vector_type(kU)));
+  static constexpr int kItems = 3;  // work items per wave
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l is row (l / 16) + 4 v, column l % 16 (gfx950)
+  __device__ static int out_row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct MfmaOps<float> {
+  typedef flt4 acc_t;
+  typedef float chunk_t __attribute__((ext_vector_type(kU)));
+  static constexpr int kItems = 5;
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element v of lane l is row 4 (l / 16) + v, column l % 16 (gfx950)
+  __device__ static int out_row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+// Folded transform tables of one axis, fragment-major in chunks of kU
+// k-steps: for a half matrix H with rb row blocks and ks k-steps (a multiple
+// of kU), element (m, s, lane) sits at
+//   ((m * (ks / kU + 1) + s / kU) * 64 + lane) * kU + s % kU
+// and holds H[16 m + lane % 16][4 s + lane / 16] (zero outside H), so one
+// lane reads its kU fragments of a chunk as one contiguous vector; the extra
+// zero chunk per row block lets the prefetch run past the end unguarded. With C[k][j] = s_k cos(pi k (2j+1) / (2L)) the halves are
+//   forward even  H[k'][j] = C[2k'][j]    (j < ne: u_0..u_{M-1}, middle point)
+//   forward odd   H[k'][j] = C[2k'+1][j]  (j < no: v_j)
+//   inverse even  H[j][k'] = C[2k'][j]    (outputs E_j from X_{2k'})
+//   inverse odd   H[j][k'] = C[2k'+1][j]  (outputs O_j from X_{2k'+1})
 template <typename T>
 struct AxisTab {
   const T* fe;
   const T* fo;
   const T* ie;
   const T* io;
-  int L, M, ne, no, ne_pad, no_pad;
+  int L, M, ne, no;
+  int rb_e, rb_o, ks_e, ks_o;
 };
 
 enum PassKind { kFwd = 0, kInv = 1, kFwdScaleInv = 2 };
@@ -43,72 +73,90 @@ __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-// Multiply the folded halves held in the tile by the tables of one direction.
-// even_in(j) / odd_in(j) map an input index to its tile slot. Results stay in
-// registers: res[b][r] is output (blk*kR + r) of the b-th block of this wave.
-template <typename T, typename EvenSlot, typename OddSlot>
-__device__ __forceinline__ void dct_blocks(const T* __restrict__ tile, const T* __restrict__ te,
-                                           const T* __restrict__ to, int n_even_in, int n_odd_in,
-                                           int ne_pad, int no_pad, EvenSlot even_in, OddSlot odd_in,
-                                           T (&res)[kMaxBlk][kR]) {
-  const int lane = threadIdx.x & 63;
-  const int w = wave_id();
-  const int nwaves = blockDim.x >> 6;
-  const int nbe = ne_pad / kR;
-  const int nbt = nbe + no_pad / kR;
-#pragma unroll
-  for (int b = 0; b < kMaxBlk; ++b) {
-    const int blk = w + b * nwaves;
-    T acc[kR];
-#pragma unroll
-    for (int r = 0; r < kR; ++r) acc[r] = T(0);
-    if (blk < nbe) {
-      const T* col0 = te + blk * kR;
-      for (int j = 0; j < n_even_in; ++j) {
-        const T xv = tile[even_in(j) * (kCW + 1) + lane];
-        const T* c = col0 + (size_t)j * ne_pad;
-#pragma unroll
-        for (int r = 0; r < kR; ++r) acc[r] = fma(c[r], xv, acc[r]);
-      }
-    } else if (blk < nbt) {
-      const T* col0 = to + (blk - nbe) * kR;
-      for (int j = 0; j < n_odd_in; ++j) {
-        const T xv = tile[odd_in(j) * (kCW + 1) + lane];
-        const T* c = col0 + (size_t)j * no_pad;
-#pragma unroll
-        for (int r = 0; r < kR; ++r) acc[r] = fma(c[r], xv, acc[r]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kR; ++r) res[b][r] = acc[r];
-  }
+// Tile slot of input k of a half: forward even u_k / middle at k; forward odd
+// v_k at L-1-k; inverse even X_{2k} at 2k; inverse odd X_{2k+1} at 2k+1.
+__device__ __forceinline__ int in_slot(bool inv, bool odd, int L, int k) {
+  return inv ? (odd ? 2 * k + 1 : 2 * k) : (odd ? L - 1 - k : k);
+}
+// Tile slot of output r of a half: forward X_{2r} / X_{2r+1}; inverse E_r at r,
+// O_r at L-1-r.
+__device__ __forceinline__ int out_slot(bool inv, bool odd, int L, int r) {
+  return inv ? (odd ? L - 1 - r : r) : (odd ? 2 * r + 1 : 2 * r);
 }
 
-// Write the register results of dct_blocks to tile slots: even output k' of
-// the even half goes to slot even_out(k'), odd output to odd_out(k').
-template <typename T, typename EvenOut, typename OddOut>
-__device__ __forceinline__ void dct_store(T* __restrict__ tile, int ne, int no, int ne_pad, int no_pad,
-                                          EvenOut even_out, OddOut odd_out, const T (&res)[kMaxBlk][kR]) {
+// Both half-size products of one direction on the tile; results are written
+// back into the tile (natural order after a forward pass; E/O slots after an
+// inverse pass, combined by the caller).
+template <typename T>
+__device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv) {
+  typedef typename MfmaOps<T>::acc_t acc_t;
+  constexpr int KI = MfmaOps<T>::kItems;
   const int lane = threadIdx.x & 63;
   const int w = wave_id();
   const int nwaves = blockDim.x >> 6;
-  const int nbe = ne_pad / kR;
-  const int nbt = nbe + no_pad / kR;
+  const int nitems = 2 * (a.rb_e + a.rb_o);  // (row block, 32-column group)
+  const int L = a.L;
+  acc_t acc[KI][2];
 #pragma unroll
-  for (int b = 0; b < kMaxBlk; ++b) {
-    const int blk = w + b * nwaves;
-    if (blk >= nbt) continue;
+  for (int b = 0; b < KI; ++b) {
+    acc[b][0] = acc_t{0, 0, 0, 0};
+    acc[b][1] = acc_t{0, 0, 0, 0};
+    const int it = w + b * nwaves;
+    if (it >= nitems) continue;
+    const int rbi = it >> 1, g = it & 1;
+    const bool odd = rbi >= a.rb_e;
+    const int m = odd ? rbi - a.rb_e : rbi;
+    const int ks = odd ? a.ks_o : a.ks_e;
+    const int nin = odd ? a.no : a.ne;
+    typedef typename MfmaOps<T>::chunk_t chunk_t;
+    const chunk_t* tp = reinterpret_cast<const chunk_t*>(inv ? (odd ? a.io : a.ie) : (odd ? a.fo : a.fe)) +
+                        (size_t)m * (ks / kU + 1) * 64 + lane;
+    const int col = g * 32 + (lane & 15);
+    // coefficient fragments are prefetched one chunk of kU k-steps ahead
+    chunk_t cur = tp[0];
+    for (int st = 0; st < ks; st += kU) {
+      const chunk_t nxt = tp[(st / kU + 1) * 64];
+      // keep the prefetch ahead of this chunk's LDS reads and MFMAs
+      __builtin_amdgcn_sched_barrier(0);
+      T b0[kU], b1[kU];
 #pragma unroll
-    for (int r = 0; r < kR; ++r) {
-      if (blk < nbe) {
-        const int k = blk * kR + r;
-        if (k < ne) tile[even_out(k) * (kCW + 1) + lane] = res[b][r];
-      } else {
-        const int k = (blk - nbe) * kR + r;
-        if (k < no) tile[odd_out(k) * (kCW + 1) + lane] = res[b][r];
+      for (int u = 0; u < kU; ++u) {
+        int k = (st + u) * 4 + (lane >> 4);
+        k = k < nin ? k : nin - 1;  // padded inputs: zero coefficient, any finite value
+        const int sl = in_slot(inv, odd, L, k) * (kCW + 1) + col;
+        b0[u] = tile[sl];
+        b1[u] = tile[sl + 16];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        acc[b][0] = MfmaOps<T>::mma(cur[u], b0[u], acc[b][0]);
+        acc[b][1] = MfmaOps<T>::mma(cur[u], b1[u], acc[b][1]);
+      }
+      cur = nxt;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < KI; ++b) {
+    const int it = w + b * nwaves;
+    if (it >= nitems) continue;
+    const int rbi = it >> 1, g = it & 1;
+    const bool odd = rbi >= a.rb_e;
+    const int m = odd ? rbi - a.rb_e : rbi;
+    const int nout = odd ? a.no : a.ne;
+    const int col = g * 32 + (lane & 15);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = m * 16 + MfmaOps<T>::out_row(lane, v);
+      if (r < nout) {
+        const int sl = out_slot(inv, odd, L, r) * (kCW + 1) + col;
+        tile[sl] = acc[b][0][v];
+        tile[sl + 16] = acc[b][1][v];
       }
     }
   }
+  __syncthreads();
 }
 
 // Forward transform of the tile (input x in natural order, output X in
@@ -124,28 +172,16 @@ __device__ __forceinline__ void tile_forward(T* tile, const AxisTab<T>& a) {
     tile[(L - 1 - j) * (kCW + 1) + c] = x0 - x1;  // v_j
   }
   __syncthreads();
-  T res[kMaxBlk][kR];
-  dct_blocks(tile, a.fe, a.fo, a.ne, a.no, a.ne_pad, a.no_pad,
-             [](int j) { return j; }, [L](int j) { return L - 1 - j; }, res);
-  __syncthreads();
-  dct_store(tile, a.ne, a.no, a.ne_pad, a.no_pad,
-            [](int k) { return 2 * k; }, [](int k) { return 2 * k + 1; }, res);
-  __syncthreads();
+  tile_mfma(tile, a, false);
 }
 
 // Inverse transform (DCT-III, the transpose) of the tile, natural order in
-// and out.
+// and out: E_j = sum_k' C[2k'][j] X_{2k'}, O_j = sum_k' C[2k'+1][j] X_{2k'+1},
+// x_j = E_j + O_j, x_{L-1-j} = E_j - O_j.
 template <typename T>
 __device__ __forceinline__ void tile_inverse(T* tile, const AxisTab<T>& a) {
   const int L = a.L, M = a.M;
-  T res[kMaxBlk][kR];
-  dct_blocks(tile, a.ie, a.io, a.ne, a.no, a.ne_pad, a.no_pad,
-             [](int k) { return 2 * k; }, [](int k) { return 2 * k + 1; }, res);
-  __syncthreads();
-  // E_j -> slot j (j < ne), O_j -> slot L-1-j (j < M)
-  dct_store(tile, a.ne, a.no, a.ne_pad, a.no_pad,
-            [](int j) { return j; }, [L](int j) { return L - 1 - j; }, res);
-  __syncthreads();
+  tile_mfma(tile, a, true);
   for (int p = threadIdx.x; p < M * kCW; p += blockDim.x) {
     const int j = p / kCW, c = p % kCW;
     const T e = tile[j * (kCW + 1) + c];
@@ -156,31 +192,43 @@ __device__ __forceinline__ void tile_inverse(T* tile, const AxisTab<T>& a) {
   __syncthreads();
 }
 
-// Divergence b = A^*(q - alpha/sigma) - c/sigma at node (t, spatial index xs),
-// the right-hand side of the phi-step of Algorithm 2 (zero extension outside each staggered set).
+// Divergence b = A^*(q - alpha/sigma) - c/sigma at node (t, spatial index xs
+// with spatial coordinates x[1..D]), the right-hand side of the phi-step of
+// Algorithm 2 (zero extension outside each staggered set).
 template <typename T, int D>
 __device__ __forceinline__ T divergence_at(const Geo& g, const T* __restrict__ q, const T* __restrict__ al,
                                            const double* __restrict__ c_lo, const double* __restrict__ c_hi,
-                                           double inv_sigma, int t, int64_t xs) {
-  const int64_t nb = g.nb;
-  const int64_t i = (int64_t)t * g.stride[0] + xs;
+                                           double inv_sigma, int t, uint32_t xs, const int (&x)[kMaxAxes]) {
+  const uint32_t nb = (uint32_t)g.nb;
+  const uint32_t s0 = (uint32_t)g.stride[0];
+  const uint32_t i = (uint32_t)t * s0 + xs;
   double b = 0.0;
   // time axis: cells t-1 and t
-  if (t >= 1) b += ((double)q[i - g.stride[0]] - (double)al[i - g.stride[0]] * inv_sigma) * g.inv_h[0];
+  if (t >= 1) b += ((double)q[i - s0] - (double)al[i - s0] * inv_sigma) * g.inv_h[0];
   if (t < g.n[0]) b -= ((double)q[i] - (double)al[i] * inv_sigma) * g.inv_h[0];
-  int64_t r = xs;
 #pragma unroll
-  for (int d = D; d >= 1; --d) {
-    const int xd = (int)(r % g.N[d]);
-    r /= g.N[d];
+  for (int d = 1; d <= D; ++d) {
+    const uint32_t sd = (uint32_t)g.stride[d];
     const T* qd = q + d * nb;
     const T* ad = al + d * nb;
-    if (xd >= 1) b += ((double)qd[i - g.stride[d]] - (double)ad[i - g.stride[d]] * inv_sigma) * g.inv_h[d];
-    if (xd < g.n[d]) b -= ((double)qd[i] - (double)ad[i] * inv_sigma) * g.inv_h[d];
+    if (x[d] >= 1) b += ((double)qd[i - sd] - (double)ad[i - sd] * inv_sigma) * g.inv_h[d];
+    if (x[d] < g.n[d]) b -= ((double)qd[i] - (double)ad[i] * inv_sigma) * g.inv_h[d];
   }
   if (t == 0) b -= c_lo[xs] * inv_sigma;
   if (t == g.n[0]) b -= c_hi[xs] * inv_sigma;
   return (T)b;
+}
+
+// Spatial coordinates x[1..D] of spatial flat index xs.
+template <int D>
+__device__ __forceinline__ void spatial_coords(const Geo& g, uint32_t xs, int (&x)[kMaxAxes]) {
+  uint32_t r = xs;
+#pragma unroll
+  for (int d = D; d >= 1; --d) {
+    x[d] = (int)(r % (uint32_t)g.N[d]);
+    r /= (uint32_t)g.N[d];
+  }
+  x[0] = 0;
 }
 
 struct PassArgs {
@@ -192,7 +240,7 @@ struct PassArgs {
 // first pass) computes the divergence of (q, alpha) while loading. KIND =
 // kFwdScaleInv (last axis only) applies forward, 1/Lambda, inverse.
 template <typename T, int D, int KIND, int SRC>
-__global__ void __launch_bounds__(kDctWaves * 64)
+__global__ void __launch_bounds__(kMaxWaves * 64)
 k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
             const T* __restrict__ q, const T* __restrict__ al,
             const double* __restrict__ c_lo, const double* __restrict__ c_hi,
@@ -208,29 +256,36 @@ k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
   double inv_sigma = 0.0;
   if (SRC == kSrcDivergence) inv_sigma = 1.0 / (ctl ? ctl->sigma : sigma_arg);
 
-  // load
+  // load (32-bit index math: planes hold fewer than 2^31 elements)
+  const int nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63;
   if (inner == 1) {
+    const uint32_t base = (uint32_t)c0 * (uint32_t)L;
+    const uint32_t lim = (uint32_t)ncols * (uint32_t)L;
     for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
-      const int cl = e / L, j = e % L;
-      const int64_t c = c0 + cl;
+      const int cl = e / L, j = e - cl * L;
       T v = T(0);
-      if (c < ncols) v = plane[c * L + j];
+      if (base + e < lim) v = plane[base + e];
       tile[j * (kCW + 1) + cl] = v;
     }
   } else {
-    for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
-      const int j = e / kCW, cl = e % kCW;
-      const int64_t c = c0 + cl;
+    // one column per lane, rows spread over the waves
+    const int64_t c = c0 + lane;
+    const bool ok = c < ncols;
+    const uint32_t cu = (uint32_t)c;
+    const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
+    const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
+    int x[kMaxAxes] = {0, 0, 0, 0};
+    if (SRC == kSrcDivergence) spatial_coords<D>(g, cu, x);
+    for (int j = threadIdx.x >> 6; j < L; j += nw) {
       T v = T(0);
-      if (c < ncols) {
-        if (SRC == kSrcDivergence) {
-          v = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, j, c);
-        } else {
-          const int64_t o = c / inner, ii = c % inner;
-          v = plane[o * (int64_t)L * inner + (int64_t)j * inner + ii];
-        }
+      if (ok) {
+        if (SRC == kSrcDivergence)
+          v = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, j, cu, x);
+        else
+          v = plane[base + (uint32_t)j * (uint32_t)inner];
       }
-      tile[j * (kCW + 1) + cl] = v;
+      tile[j * (kCW + 1) + lane] = v;
     }
   }
   __syncthreads();
@@ -253,19 +308,19 @@ k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
 
   // store
   if (inner == 1) {
+    const uint32_t base = (uint32_t)c0 * (uint32_t)L;
+    const uint32_t lim = (uint32_t)ncols * (uint32_t)L;
     for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
-      const int cl = e / L, j = e % L;
-      const int64_t c = c0 + cl;
-      if (c < ncols) plane[c * L + j] = tile[j * (kCW + 1) + cl];
+      const int cl = e / L, j = e - cl * L;
+      if (base + e < lim) plane[base + e] = tile[j * (kCW + 1) + cl];
     }
   } else {
-    for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
-      const int j = e / kCW, cl = e % kCW;
-      const int64_t c = c0 + cl;
-      if (c < ncols) {
-        const int64_t o = c / inner, ii = c % inner;
-        plane[o * (int64_t)L * inner + (int64_t)j * inner + ii] = tile[j * (kCW + 1) + cl];
-      }
+    const int64_t c = c0 + lane;
+    if (c < ncols) {
+      const uint32_t cu = (uint32_t)c;
+      const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
+      const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
+      for (int j = threadIdx.x >> 6; j < L; j += nw) plane[base + (uint32_t)j * (uint32_t)inner] = tile[j * (kCW + 1) + lane];
     }
   }
 }
