@@ -32,8 +32,12 @@
  *     beta, z  : K = 4D+2 consecutive planes, component order
  *                [1 - q0 side, (d=1,v=1..4), ..., (d=D,v=1..4), 1 + q0 side]
  *                as in eq. bdd / eq. operBF.
- *   Scalars are double in DOT_FP64 mode; DOT_MIXED stores the bulk state as
- *   float (see dot_plan_info.scalar_bytes).
+ *   phi and the right-hand side b are always double planes. The bulk state
+ *   (q, alpha, beta, z and the cone workspace) is double in DOT_FP64 mode and
+ *   float in DOT_MIXED mode (dot_plan_info.scalar_bytes); in DOT_MIXED the
+ *   cosine transforms run in float on the correction of phi (defect
+ *   correction: A^*A dphi = b - A^*A phi, phi += dphi, in double), while the
+ *   cone projection, A phi and every reduction stay in double.
  *
  * Ownership: the caller owns every buffer it passes; the library keeps no
  * pointer to caller memory after a call returns. A dot_plan owns only small
@@ -103,10 +107,11 @@ typedef struct {
   int32_t n[4];
   int64_t nb;             /* scalars per plane */
   int32_t scalar_bytes;   /* 8 (FP64) or 4 (MIXED bulk) */
-  int32_t n_planes;       /* planes in the state buffer */
+  int32_t n_planes;       /* bulk-type planes in the state buffer */
   size_t state_bytes;     /* bytes the caller must provide for a state buffer */
-  /* plane offsets (in planes) inside a state buffer */
-  int32_t off_phi, off_q, off_qn, off_alpha, off_beta, off_w;
+  /* byte offsets inside a state buffer: phi (FP64 plane), transform scratch
+   * (mixed precision only), q, q_new, alpha, beta, W (bulk scalar type) */
+  uint64_t off_phi, off_scratch, off_q, off_qn, off_alpha, off_beta, off_w;
 } dot_plan_info;
 
 typedef struct dot_plan dot_plan;

@@ -81,12 +81,13 @@ class dot_plan_info(ctypes.Structure):
         ("scalar_bytes", ctypes.c_int32),
         ("n_planes", ctypes.c_int32),
         ("state_bytes", ctypes.c_size_t),
-        ("off_phi", ctypes.c_int32),
-        ("off_q", ctypes.c_int32),
-        ("off_qn", ctypes.c_int32),
-        ("off_alpha", ctypes.c_int32),
-        ("off_beta", ctypes.c_int32),
-        ("off_w", ctypes.c_int32),
+        ("off_phi", ctypes.c_uint64),
+        ("off_scratch", ctypes.c_uint64),
+        ("off_q", ctypes.c_uint64),
+        ("off_qn", ctypes.c_uint64),
+        ("off_alpha", ctypes.c_uint64),
+        ("off_beta", ctypes.c_uint64),
+        ("off_w", ctypes.c_uint64),
     ]
 
 

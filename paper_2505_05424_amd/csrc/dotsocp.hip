@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -21,7 +22,7 @@ namespace dot {
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 k_divergence(Geo g, const T* __restrict__ q, const T* __restrict__ al, const double* __restrict__ c_lo,
-             const double* __restrict__ c_hi, double inv_sigma, T* __restrict__ b) {
+             const double* __restrict__ c_hi, double inv_sigma, double* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.nb) return;
   const int t = (int)(i / g.stride[0]);
@@ -88,11 +89,13 @@ struct dot_plan {
   // scratch for step-level calls
   Ctl* step_ctl = nullptr;
   double* step_partials = nullptr;
-  Ctl* host_ctl = nullptr;  // pinned
-  // state layout
-  int n_planes = 0;
-  int off_phi = 0, off_q = 0, off_qn = 0, off_alpha = 0, off_beta = 0, off_w = 0;
-  size_t planes_bytes = 0, ctl_offset = 0, partials_offset = 0, state_bytes = 0;
+  void* step_scratch = nullptr;  // FP32 transform plane (mixed precision)
+  Ctl* host_ctl = nullptr;       // pinned
+  // state layout (byte offsets): phi (FP64) | transform scratch (mixed only) |
+  // q | q_new | alpha | beta | W (bulk scalar type) | control block | partials
+  int n_planes = 0;  // bulk-type planes
+  size_t off_phi = 0, off_scr = 0, off_q = 0, off_qn = 0, off_alpha = 0, off_beta = 0, off_w = 0;
+  size_t ctl_offset = 0, partials_offset = 0, state_bytes = 0;
   int device = 0;
   // measurement hook: events around launches of one kernel class
   int prof_class = -1;
@@ -223,8 +226,8 @@ int build_eigs(dot_plan* P) {
 }
 
 template <typename T>
-T* plane(void* state, const dot_plan* P, int idx) {
-  return reinterpret_cast<T*>(static_cast<char*>(state) + (size_t)idx * P->g.nb * sizeof(T));
+T* at(void* state, size_t byte_off) {
+  return reinterpret_cast<T*>(static_cast<char*>(state) + byte_off);
 }
 
 Ctl* state_ctl(void* state, const dot_plan* P) {
@@ -282,15 +285,15 @@ const AxisTab<double>& tab_of<double>(const dot_plan* P, int a) { return P->tab6
 template <>
 const AxisTab<float>& tab_of<float>(const dot_plan* P, int a) { return P->tab32[a]; }
 
-template <typename T, int D, int KIND, int SRC>
-int launch_pass(const dot_plan* P, int a, T* pl, const T* q, const T* al, const Ctl* ctl, double sigma,
-                hipStream_t st) {
+template <typename T, int D, int KIND, int SRC, int DST>
+int launch_pass(const dot_plan* P, int a, T* work, const T* q, const T* al, double* phi, const Ctl* ctl,
+                double sigma, hipStream_t st) {
   const Geo& g = P->g;
   PassArgs pa;
   pa.inner = g.stride[a];
   pa.ncols = g.nb / g.N[a];
   const size_t smem = (size_t)g.N[a] * (kCW + 1) * sizeof(T);
-  auto fn = k_axis_pass<T, D, KIND, SRC>;
+  auto fn = k_axis_pass<T, D, KIND, SRC, DST>;
   // the LDS opt-in is per kernel and process; set it once to the device maximum
   static int smem_set = 0;
   if (!smem_set) {
@@ -300,39 +303,63 @@ int launch_pass(const dot_plan* P, int a, T* pl, const T* q, const T* al, const 
     smem_set = 1;
   }
   const unsigned grid = (unsigned)((pa.ncols + kCW - 1) / kCW);
-  const int cls = SRC == kSrcDivergence ? DOT_K_DCT_FIRST
+  const int cls = SRC != kSrcPlane ? DOT_K_DCT_FIRST
                   : KIND == kFwdScaleInv ? DOT_K_DCT_LAST
                   : KIND == kInv         ? DOT_K_DCT_INV
                                          : (a == 0 ? DOT_K_DCT_FIRST : DOT_K_DCT_MID);
   ProfScope ps(P, cls, st);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(pass_waves<T>(g.N[a]) * 64), smem, st, g, pa, tab_of<T>(P, a), pl, q, al,
-                     P->c_lo, P->c_hi, (const T*)P->lam_other, (const T*)P->lam_last, ctl, sigma);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(pass_waves<T>(g.N[a]) * 64), smem, st, g, pa, tab_of<T>(P, a), work, q,
+                     al, phi, P->c_lo, P->c_hi, (const T*)P->lam_other, (const T*)P->lam_last, ctl, sigma);
   HIP_OK(hipGetLastError());
   return DOT_OK;
 }
 
-// a3 + a4 (divergence fused into the first pass when q != nullptr).
-template <typename T, int D>
-int run_poisson(const dot_plan* P, T* phi, const T* q, const T* al, const Ctl* ctl, double sigma,
-                hipStream_t st) {
+// The 2D+1 transform passes of one Poisson solve (a3 + a4): first pass on the
+// time axis loads according to SRC, forward passes on the middle axes, the
+// fused forward/scale/inverse pass on the last axis, inverse passes back to
+// the time axis, which stores according to DST.
+template <typename T, int D, int SRC, int DST>
+int run_passes(const dot_plan* P, T* work, const T* q, const T* al, double* phi, const Ctl* ctl, double sigma,
+               hipStream_t st) {
   int rc;
-  if (q)
-    rc = launch_pass<T, D, kFwd, kSrcDivergence>(P, 0, phi, q, al, ctl, sigma, st);
-  else
-    rc = launch_pass<T, D, kFwd, kSrcPlane>(P, 0, phi, nullptr, nullptr, ctl, sigma, st);
-  if (rc) return rc;
+  if ((rc = launch_pass<T, D, kFwd, SRC, kDstPlane>(P, 0, work, q, al, phi, ctl, sigma, st))) return rc;
   for (int a = 1; a < D; ++a)
-    if ((rc = launch_pass<T, D, kFwd, kSrcPlane>(P, a, phi, nullptr, nullptr, ctl, sigma, st))) return rc;
-  if ((rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane>(P, D, phi, nullptr, nullptr, ctl, sigma, st))) return rc;
-  for (int a = D - 1; a >= 0; --a)
-    if ((rc = launch_pass<T, D, kInv, kSrcPlane>(P, a, phi, nullptr, nullptr, ctl, sigma, st))) return rc;
-  return DOT_OK;
+    if ((rc = launch_pass<T, D, kFwd, kSrcPlane, kDstPlane>(P, a, work, q, al, phi, ctl, sigma, st))) return rc;
+  if ((rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane, kDstPlane>(P, D, work, q, al, phi, ctl, sigma, st))) return rc;
+  for (int a = D - 1; a >= 1; --a)
+    if ((rc = launch_pass<T, D, kInv, kSrcPlane, kDstPlane>(P, a, work, q, al, phi, ctl, sigma, st))) return rc;
+  return launch_pass<T, D, kInv, kSrcPlane, DST>(P, 0, work, q, al, phi, ctl, sigma, st);
+}
+
+// Poisson solve inside an iteration. FP64: the transforms run in place on
+// phi. Mixed: the FP32 transforms solve A^*A dphi = b - A^*A phi on the
+// scratch plane and the last pass adds dphi to the FP64 phi.
+template <typename T, int D>
+int poisson_iter(const dot_plan* P, double* phi, T* scratch, const T* q, const T* al, const Ctl* ctl, hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value)
+    return run_passes<double, D, kSrcDivergence, kDstPlane>(P, phi, q, al, phi, ctl, 0.0, st);
+  else
+    return run_passes<T, D, kSrcDefect, kDstPhiAdd>(P, scratch, q, al, phi, ctl, 0.0, st);
+}
+
+// Poisson solve of the step-level calls: from (q, alpha, sigma) if q is given,
+// else from the right-hand side already in phi; result in phi.
+template <typename T, int D>
+int poisson_step(const dot_plan* P, double* phi, const T* q, const T* al, double sigma, hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value) {
+    if (q) return run_passes<double, D, kSrcDivergence, kDstPlane>(P, phi, q, al, phi, nullptr, sigma, st);
+    return run_passes<double, D, kSrcPlane, kDstPlane>(P, phi, q, al, phi, nullptr, sigma, st);
+  } else {
+    T* scr = (T*)P->step_scratch;
+    if (q) return run_passes<T, D, kSrcDivergence, kDstPhiSet>(P, scr, q, al, phi, nullptr, sigma, st);
+    return run_passes<T, D, kSrcPlaneF64, kDstPhiSet>(P, scr, q, al, phi, nullptr, sigma, st);
+  }
 }
 
 unsigned grid_nb(const dot_plan* P) { return (unsigned)P->nblocks; }
 
 template <typename T, int D>
-int run_update(const dot_plan* P, const T* phi, const T* q, T* alpha, T* beta, T* qn, T* W, Ctl* ctl,
+int run_update(const dot_plan* P, const double* phi, const T* q, T* alpha, T* beta, T* qn, T* W, Ctl* ctl,
                double* partials, int check, hipStream_t st) {
   const Geo& g = P->g;
   {
@@ -365,7 +392,7 @@ FinArgs fin_args(const dot_plan* P) {
 }
 
 template <typename T, int D>
-int run_check(const dot_plan* P, const T* phi, const T* q, const T* alpha, const T* beta, Ctl* ctl,
+int run_check(const dot_plan* P, const double* phi, const T* q, const T* alpha, const T* beta, Ctl* ctl,
               double* partials, int update_ctl, hipStream_t st) {
   const Geo& g = P->g;
   {
@@ -390,19 +417,20 @@ int run_iters(dot_plan* P, void* state, int max_iters, hipStream_t st, dot_resul
   HIP_OK(hipStreamSynchronize(st));
   const int iter0 = P->host_ctl->iter;
   int stopped = P->host_ctl->stop;
-  T* phi = plane<T>(state, P, P->off_phi);
-  T* qa = plane<T>(state, P, P->off_q);
-  T* qb = plane<T>(state, P, P->off_qn);
-  T* alpha = plane<T>(state, P, P->off_alpha);
-  T* beta = plane<T>(state, P, P->off_beta);
-  T* W = plane<T>(state, P, P->off_w);
+  double* phi = at<double>(state, P->off_phi);
+  T* scr = at<T>(state, P->off_scr);
+  T* qa = at<T>(state, P->off_q);
+  T* qb = at<T>(state, P->off_qn);
+  T* alpha = at<T>(state, P->off_alpha);
+  T* beta = at<T>(state, P->off_beta);
+  T* W = at<T>(state, P->off_w);
   const int poll = 40;
   int rc;
   for (int j = 0; j < max_iters && !stopped; ++j) {
     const int it = iter0 + j;
     T* cur = (it % 2 == 0) ? qa : qb;
     T* nxt = (it % 2 == 0) ? qb : qa;
-    if ((rc = run_poisson<T, D>(P, phi, cur, alpha, ctl, 0.0, st))) return rc;
+    if ((rc = poisson_iter<T, D>(P, phi, scr, cur, alpha, ctl, st))) return rc;
     const int check = ((it + 1) % P->cadence) == 0;
     if ((rc = run_update<T, D>(P, phi, cur, alpha, beta, nxt, W, ctl, partials, check, st))) return rc;
     if (check && (rc = run_check<T, D>(P, phi, nxt, alpha, beta, ctl, partials, 1, st))) return rc;
@@ -465,7 +493,7 @@ template <typename T, int D>
 struct DivF {
   static int run(dot_plan* P, const void* q, const void* al, double sigma, void* b, hipStream_t st) {
     hipLaunchKernelGGL((k_divergence<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, P->g, (const T*)q,
-                       (const T*)al, P->c_lo, P->c_hi, 1.0 / sigma, (T*)b);
+                       (const T*)al, P->c_lo, P->c_hi, 1.0 / sigma, (double*)b);
     HIP_OK(hipGetLastError());
     return DOT_OK;
   }
@@ -474,7 +502,7 @@ struct DivF {
 template <typename T, int D>
 struct PoissonF {
   static int run(dot_plan* P, void* b, const void* q, const void* al, double sigma, hipStream_t st) {
-    return run_poisson<T, D>(P, (T*)b, (const T*)q, (const T*)al, nullptr, sigma, st);
+    return poisson_step<T, D>(P, (double*)b, (const T*)q, (const T*)al, sigma, st);
   }
 };
 
@@ -497,7 +525,7 @@ struct UpdateF {
     h.tau = tau;
     h.stop = 0;
     HIP_OK(hipMemcpyAsync(P->step_ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    int rc = run_update<T, D>(P, (const T*)phi, (const T*)q, (T*)alpha, (T*)beta, (T*)qn, (T*)W, P->step_ctl,
+    int rc = run_update<T, D>(P, (const double*)phi, (const T*)q, (T*)alpha, (T*)beta, (T*)qn, (T*)W, P->step_ctl,
                               P->step_partials, 0, st);
     if (rc) return rc;
     HIP_OK(hipStreamSynchronize(st));
@@ -512,7 +540,7 @@ struct ResidF {
     hipLaunchKernelGGL((k_zres<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, P->g, (const T*)z, (const T*)q,
                        P->sw_sp, P->step_partials);
     HIP_OK(hipGetLastError());
-    return run_check<T, D>(P, (const T*)phi, (const T*)q, (const T*)alpha, (const T*)beta, P->step_ctl,
+    return run_check<T, D>(P, (const double*)phi, (const T*)q, (const T*)alpha, (const T*)beta, P->step_ctl,
                            P->step_partials, 0, st);
   }
 };
@@ -562,6 +590,7 @@ void dot_plan_destroy(dot_plan* P) {
   for (auto* b : P->axis_buf) (void)hipFree(b);
   (void)hipFree(P->step_ctl);
   (void)hipFree(P->step_partials);
+  (void)hipFree(P->step_scratch);
   (void)hipHostFree(P->host_ctl);
   delete P;
 }
@@ -640,19 +669,22 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   }
   rc = P->precision == DOT_FP64 ? build_eigs<double>(P.get()) : build_eigs<float>(P.get());
   if (rc) return rc;
-  // state layout: phi | q (D+1) | qn (D+1) | alpha (D+1) | beta (K) | W (4D) | ctl | partials
+  // state layout: phi (FP64) | scratch (mixed) | q (D+1) | q_new (D+1) | alpha (D+1) | beta (K) | W (4D) |
+  // control block | partials
+  const size_t pb = (size_t)g.nb * P->scalar_bytes;
   P->off_phi = 0;
-  P->off_q = 1;
-  P->off_qn = P->off_q + D + 1;
-  P->off_alpha = P->off_qn + D + 1;
-  P->off_beta = P->off_alpha + D + 1;
-  P->off_w = P->off_beta + P->K;
-  P->n_planes = P->off_w + 4 * D;
+  P->off_scr = align256((size_t)g.nb * sizeof(double));
+  P->off_q = P->off_scr + (P->precision == DOT_MIXED ? align256(pb) : 0);
+  P->off_qn = P->off_q + (size_t)(D + 1) * pb;
+  P->off_alpha = P->off_qn + (size_t)(D + 1) * pb;
+  P->off_beta = P->off_alpha + (size_t)(D + 1) * pb;
+  P->off_w = P->off_beta + (size_t)P->K * pb;
+  P->n_planes = 3 * (D + 1) + P->K + 4 * D;
   P->nblocks = (g.nb + kBlock - 1) / kBlock;
-  P->planes_bytes = align256((size_t)P->n_planes * g.nb * P->scalar_bytes);
-  P->ctl_offset = P->planes_bytes;
+  P->ctl_offset = align256(P->off_w + (size_t)(4 * D) * pb);
   P->partials_offset = P->ctl_offset + align256(sizeof(Ctl));
   P->state_bytes = P->partials_offset + align256((size_t)P->nblocks * kNumSums * sizeof(double));
+  if (P->precision == DOT_MIXED) HIP_OK(hipMalloc(&P->step_scratch, pb));
   HIP_OK(hipMalloc((void**)&P->step_ctl, sizeof(Ctl)));
   HIP_OK(hipMalloc((void**)&P->step_partials, (size_t)P->nblocks * kNumSums * sizeof(double)));
   HIP_OK(hipMemset(P->step_partials, 0, (size_t)P->nblocks * kNumSums * sizeof(double)));
@@ -671,6 +703,7 @@ int dot_plan_get_info(const dot_plan* P, dot_plan_info* o) {
   o->n_planes = P->n_planes;
   o->state_bytes = P->state_bytes;
   o->off_phi = P->off_phi;
+  o->off_scratch = P->off_scr;
   o->off_q = P->off_q;
   o->off_qn = P->off_qn;
   o->off_alpha = P->off_alpha;
@@ -716,7 +749,7 @@ int dot_extract(dot_plan* P, const void* state, double* rho_out, double* m_out, 
   };
   const char* base = static_cast<const char*>(state);
   if (rho_out) {
-    HIP_OK(hipMemcpyAsync(buf.data(), base + (size_t)P->off_alpha * g.nb * sb, g.nb * sb, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha, g.nb * sb, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     const int64_t ncell = (int64_t)g.n[0] * g.nx;
     for (int64_t i = 0; i < ncell; ++i) rho_out[i] = get(i);
@@ -724,7 +757,7 @@ int dot_extract(dot_plan* P, const void* state, double* rho_out, double* m_out, 
   if (m_out) {
     size_t o = 0;
     for (int d = 1; d <= P->D; ++d) {
-      HIP_OK(hipMemcpyAsync(buf.data(), base + (size_t)(P->off_alpha + d) * g.nb * sb, g.nb * sb,
+      HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha + (size_t)d * g.nb * sb, g.nb * sb,
                             hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
       for (int64_t i = 0; i < g.nb; ++i) {

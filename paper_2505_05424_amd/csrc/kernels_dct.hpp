@@ -67,7 +67,16 @@ struct AxisTab {
 };
 
 enum PassKind { kFwd = 0, kInv = 1, kFwdScaleInv = 2 };
-enum PassSrc { kSrcPlane = 0, kSrcDivergence = 1 };
+// What the first (time-axis forward) pass loads:
+//   kSrcPlane       the work plane itself (in place)
+//   kSrcDivergence  b = A^*(q - alpha/sigma) - c/sigma, computed while loading
+//   kSrcDefect      b - A^*A phi for the FP64 plane phi (mixed precision: the
+//                   FP32 transforms then solve only for the correction)
+//   kSrcPlaneF64    an FP64 right-hand side plane (mixed precision step call)
+enum PassSrc { kSrcPlane = 0, kSrcDivergence = 1, kSrcDefect = 2, kSrcPlaneF64 = 3 };
+// Where the last (time-axis inverse) pass stores: the work plane, phi += result
+// (FP64), or phi = result (FP64).
+enum PassDst { kDstPlane = 0, kDstPhiAdd = 1, kDstPhiSet = 2 };
 
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -196,7 +205,7 @@ __device__ __forceinline__ void tile_inverse(T* tile, const AxisTab<T>& a) {
 // with spatial coordinates x[1..D]), the right-hand side of the phi-step of
 // Algorithm 2 (zero extension outside each staggered set).
 template <typename T, int D>
-__device__ __forceinline__ T divergence_at(const Geo& g, const T* __restrict__ q, const T* __restrict__ al,
+__device__ __forceinline__ double divergence_at(const Geo& g, const T* __restrict__ q, const T* __restrict__ al,
                                            const double* __restrict__ c_lo, const double* __restrict__ c_hi,
                                            double inv_sigma, int t, uint32_t xs, const int (&x)[kMaxAxes]) {
   const uint32_t nb = (uint32_t)g.nb;
@@ -216,7 +225,29 @@ __device__ __forceinline__ T divergence_at(const Geo& g, const T* __restrict__ q
   }
   if (t == 0) b -= c_lo[xs] * inv_sigma;
   if (t == g.n[0]) b -= c_hi[xs] * inv_sigma;
-  return (T)b;
+  return b;
+}
+
+// (A^*A phi) at node (t, xs): sum over axes of the path-graph Laplacian
+// stencil / h_d^2 (Neumann ends), in FP64.
+template <int D>
+__device__ __forceinline__ double laplacian_at(const Geo& g, const double* __restrict__ phi, int t, uint32_t xs,
+                                               const int (&x)[kMaxAxes]) {
+  const uint32_t s0 = (uint32_t)g.stride[0];
+  const uint32_t i = (uint32_t)t * s0 + xs;
+  const double c = phi[i];
+  const double w0 = g.inv_h[0] * g.inv_h[0];
+  double r = 0.0;
+  if (t >= 1) r += (c - phi[i - s0]) * w0;
+  if (t < g.n[0]) r -= (phi[i + s0] - c) * w0;
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    const uint32_t sd = (uint32_t)g.stride[d];
+    const double wd = g.inv_h[d] * g.inv_h[d];
+    if (x[d] >= 1) r += (c - phi[i - sd]) * wd;
+    if (x[d] < g.n[d]) r -= (phi[i + sd] - c) * wd;
+  }
+  return r;
 }
 
 // Spatial coordinates x[1..D] of spatial flat index xs.
@@ -236,13 +267,13 @@ struct PassArgs {
   int64_t ncols;   // number of lines = outer * inner
 };
 
-// One axis pass over a plane, in place. SRC = kSrcDivergence (time axis only,
-// first pass) computes the divergence of (q, alpha) while loading. KIND =
+// One axis pass over a plane, in place. SRC != kSrcPlane and DST != kDstPlane
+// occur on the time axis only (first forward / last inverse pass). KIND =
 // kFwdScaleInv (last axis only) applies forward, 1/Lambda, inverse.
-template <typename T, int D, int KIND, int SRC>
+template <typename T, int D, int KIND, int SRC, int DST>
 __global__ void __launch_bounds__(kMaxWaves * 64)
 k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
-            const T* __restrict__ q, const T* __restrict__ al,
+            const T* __restrict__ q, const T* __restrict__ al, double* __restrict__ phi,
             const double* __restrict__ c_lo, const double* __restrict__ c_hi,
             const T* __restrict__ lam_other, const T* __restrict__ lam_last,
             const Ctl* __restrict__ ctl, double sigma_arg) {
@@ -254,7 +285,7 @@ k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
   const int64_t inner = pa.inner;
   const int64_t ncols = pa.ncols;
   double inv_sigma = 0.0;
-  if (SRC == kSrcDivergence) inv_sigma = 1.0 / (ctl ? ctl->sigma : sigma_arg);
+  if (SRC == kSrcDivergence || SRC == kSrcDefect) inv_sigma = 1.0 / (ctl ? ctl->sigma : sigma_arg);
 
   // load (32-bit index math: planes hold fewer than 2^31 elements)
   const int nw = blockDim.x >> 6;
@@ -276,14 +307,21 @@ k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
     const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
     const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
     int x[kMaxAxes] = {0, 0, 0, 0};
-    if (SRC == kSrcDivergence) spatial_coords<D>(g, cu, x);
+    if (SRC == kSrcDivergence || SRC == kSrcDefect) spatial_coords<D>(g, cu, x);
     for (int j = threadIdx.x >> 6; j < L; j += nw) {
       T v = T(0);
       if (ok) {
-        if (SRC == kSrcDivergence)
-          v = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, j, cu, x);
-        else
-          v = plane[base + (uint32_t)j * (uint32_t)inner];
+        const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
+        if (SRC == kSrcDivergence) {
+          v = (T)divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, j, cu, x);
+        } else if (SRC == kSrcDefect) {
+          const double b = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, j, cu, x);
+          v = (T)(b - laplacian_at<D>(g, phi, j, cu, x));
+        } else if (SRC == kSrcPlaneF64) {
+          v = (T)phi[e];
+        } else {
+          v = plane[e];
+        }
       }
       tile[j * (kCW + 1) + lane] = v;
     }
@@ -320,7 +358,16 @@ k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
       const uint32_t cu = (uint32_t)c;
       const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
       const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
-      for (int j = threadIdx.x >> 6; j < L; j += nw) plane[base + (uint32_t)j * (uint32_t)inner] = tile[j * (kCW + 1) + lane];
+      for (int j = threadIdx.x >> 6; j < L; j += nw) {
+        const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
+        const T v = tile[j * (kCW + 1) + lane];
+        if (DST == kDstPhiAdd)
+          phi[e] += (double)v;
+        else if (DST == kDstPhiSet)
+          phi[e] = (double)v;
+        else
+          plane[e] = v;
+      }
     }
   }
 }

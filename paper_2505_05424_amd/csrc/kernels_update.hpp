@@ -86,7 +86,7 @@ __device__ __forceinline__ void soc_project(double (&y)[K]) {
 // ---------------------------------------------------------------------------
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
-k_cone_q0(Geo g, const T* __restrict__ phi, const T* __restrict__ q, T* __restrict__ alpha,
+k_cone_q0(Geo g, const double* __restrict__ phi, const T* __restrict__ q, T* __restrict__ alpha,
           const T* __restrict__ beta, const double* __restrict__ sw_sp, T* __restrict__ qn,
           T* __restrict__ W, const Ctl* __restrict__ ctl) {
   if (ctl->stop) return;
@@ -123,7 +123,7 @@ k_cone_q0(Geo g, const T* __restrict__ phi, const T* __restrict__ q, T* __restri
 // the adjacent cells (Prop. 3.2 with weights); alpha_d update.
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
-k_qd(Geo g, const T* __restrict__ phi, T* __restrict__ alpha, const double* __restrict__ om_sp,
+k_qd(Geo g, const double* __restrict__ phi, T* __restrict__ alpha, const double* __restrict__ om_sp,
      T* __restrict__ qn, const T* __restrict__ W, const Ctl* __restrict__ ctl) {
   if (ctl->stop) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,7 +246,7 @@ k_beta(Geo g, const T* __restrict__ q, const T* __restrict__ qn, T* __restrict__
 // 17 sum m^2 / r over r > 0. (4, 11, 12 are filled elsewhere.)
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
-k_resid(Geo g, const T* __restrict__ phi, const T* __restrict__ q, const T* __restrict__ alpha,
+k_resid(Geo g, const double* __restrict__ phi, const T* __restrict__ q, const T* __restrict__ alpha,
         const T* __restrict__ beta, const double* __restrict__ om_sp, const double* __restrict__ sw_sp,
         const double* __restrict__ c_lo, const double* __restrict__ c_hi, const Ctl* __restrict__ ctl,
         double* __restrict__ partials) {

@@ -48,22 +48,20 @@ def rel_err(a, b):
 
 
 class GpuState:
-    """A state buffer allocated with torch for one plan, with plane views."""
+    """A state buffer allocated with torch for one plan."""
 
     def __init__(self, plan):
         torch = torch_mod()
         self.plan = plan
-        info = plan.info
-        self.info = info
-        self.buf = torch.zeros(int(info.state_bytes), dtype=torch.uint8, device="cuda")
-        dt = torch.float64 if info.scalar_bytes == 8 else torch.float32
-        box = B.box_shape(plan.n)
-        nplanes_bytes = int(info.n_planes) * int(info.nb) * int(info.scalar_bytes)
-        self.planes = self.buf[:nplanes_bytes].view(dt).view((int(info.n_planes),) + box)
+        self.info = plan.info
+        self.buf = torch.zeros(int(self.info.state_bytes), dtype=torch.uint8, device="cuda")
 
     @property
     def ptr(self):
         return self.buf.data_ptr()
+
+    def raw(self):
+        return host(self.buf)
 
     def reset(self):
         B.dot_state_reset(self.plan, self.ptr, stream_handle())

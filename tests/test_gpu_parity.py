@@ -182,7 +182,7 @@ def test_run_is_deterministic():
         s = G.GpuState(plan)
         s.reset()
         s.run(25)
-        outs.append(G.host(s.planes).copy())
+        outs.append(s.raw().copy())
     assert np.array_equal(outs[0], outs[1])
 
 
@@ -196,7 +196,7 @@ def test_split_runs_equal_one_run():
     b = G.GpuState(plan)
     b.reset()
     b.run(37)
-    assert np.array_equal(G.host(a.planes), G.host(b.planes))
+    assert np.array_equal(a.raw(), b.raw())
 
 
 def test_dot_solve_one_shot():
