@@ -192,6 +192,31 @@ typedef enum {
 int dot_profile_select(dot_plan* plan, int32_t kernel_class);
 int dot_profile_read(dot_plan* plan, double* total_ms, int64_t* launches);
 
+/* ---- batches: many instances, one launch per kernel of an iteration ------ */
+/* A batch holds `count` problems with the same D, precision and check
+ * cadence but any grid sizes, masks and data. Every kernel of an iteration is
+ * launched once for all instances; per-instance descriptors (geometry, state
+ * pointers, tables) and block maps route each workgroup to its instance. Each
+ * instance keeps its own sigma, residuals and stop flag on the device, stops
+ * on its own, and gives bitwise the same iterates as a solve of that problem
+ * alone (same kernels, fixed-order reductions). The caller provides one device
+ * workspace of dot_batch_workspace_bytes. */
+typedef struct dot_batch dot_batch;
+int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out);
+void dot_batch_destroy(dot_batch* batch);
+size_t dot_batch_workspace_bytes(const dot_batch* batch);
+int32_t dot_batch_size(const dot_batch* batch);
+/* zero state, sigma0 and counters for every instance */
+int dot_batch_reset(dot_batch* batch, void* workspace, void* stream);
+/* up to max_iters iterations of all instances in lockstep (stopped instances
+ * do no work); blocks; fills results[count] (may be NULL) */
+int dot_batch_run(dot_batch* batch, void* workspace, int32_t max_iters, void* stream, dot_result* results);
+/* rho / m of instance `index`, as dot_extract */
+int dot_batch_extract(dot_batch* batch, const void* workspace, int32_t index, double* rho_out, double* m_out,
+                      void* stream);
+int dot_batch_profile_select(dot_batch* batch, int32_t kernel_class);
+int dot_batch_profile_read(dot_batch* batch, double* total_ms, int64_t* launches);
+
 /* One-shot, blocking: allocate, solve, copy rho/m out (either may be NULL),
  * free. rho_out: n0*prod(n_d+1); m_out: sum_d |G^s_d| doubles. */
 int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* res);

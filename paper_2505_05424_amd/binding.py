@@ -26,6 +26,8 @@ EXPORTED = [
     "dot_state_reset", "dot_run", "dot_extract",
     "dot_step_divergence", "dot_step_poisson", "dot_step_rhs_poisson", "dot_step_cone",
     "dot_step_update", "dot_step_residuals", "dot_profile_select", "dot_profile_read", "dot_solve",
+    "dot_batch_create", "dot_batch_destroy", "dot_batch_workspace_bytes", "dot_batch_size", "dot_batch_reset",
+    "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
 ]
 
 KERNEL_CLASSES = {"dct_first": 0, "dct_mid": 1, "dct_last": 2, "dct_inv": 3, "cone": 4, "qd": 5,
@@ -130,8 +132,22 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.dot_solve.argtypes = [ctypes.POINTER(dot_problem), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result)]
+    lib.dot_batch_create.argtypes = [ctypes.POINTER(dot_problem), i32, ctypes.POINTER(vp)]
+    lib.dot_batch_destroy.argtypes = [vp]
+    lib.dot_batch_destroy.restype = None
+    lib.dot_batch_workspace_bytes.argtypes = [vp]
+    lib.dot_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.dot_batch_size.argtypes = [vp]
+    lib.dot_batch_size.restype = i32
+    lib.dot_batch_reset.argtypes = [vp, vp, vp]
+    lib.dot_batch_run.argtypes = [vp, vp, i32, vp, ctypes.POINTER(dot_result)]
+    lib.dot_batch_extract.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_double), vp]
+    lib.dot_batch_profile_select.argtypes = [vp, i32]
+    lib.dot_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
-        if name not in ("dot_last_error", "dot_plan_destroy"):
+        if name not in ("dot_last_error", "dot_plan_destroy", "dot_batch_destroy", "dot_batch_workspace_bytes",
+                        "dot_batch_size"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -312,6 +328,91 @@ def dot_solve(D, n, rho0, rho1, mask=None, **kw):
         out.append(m[o:o + k].reshape(s))
         o += k
     return r, rho, out
+
+
+class Batch:
+    """Owns a dot_batch handle; instances are described by dotgen-like objects
+    with D, n, rho0, rho1, mask."""
+
+    def __init__(self, handle, insts):
+        self.handle = handle
+        self.insts = list(insts)
+
+    @property
+    def workspace_bytes(self):
+        return int(load().dot_batch_workspace_bytes(self.handle))
+
+    def close(self):
+        if self.handle:
+            load().dot_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dot_batch_create(insts, **kw) -> Batch:
+    """Batch of problems (objects with D, n, rho0, rho1, mask); kw as make_problem."""
+    lib = load()
+    structs, keep = [], []
+    for inst in insts:
+        p, k = make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, **kw)
+        structs.append(p)
+        keep.append(k)
+    arr = (dot_problem * len(structs))(*structs)
+    h = ctypes.c_void_p()
+    _check(lib.dot_batch_create(arr, len(structs), ctypes.byref(h)))
+    return Batch(h, insts)
+
+
+def dot_batch_destroy(batch: Batch):
+    batch.close()
+
+
+def dot_batch_reset(batch: Batch, ws_ptr: int, stream: int = 0):
+    _check(load().dot_batch_reset(batch.handle, ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_batch_run(batch: Batch, ws_ptr: int, max_iters: int, stream: int = 0):
+    n = len(batch.insts)
+    res = (dot_result * n)()
+    _check(load().dot_batch_run(batch.handle, ctypes.c_void_p(ws_ptr), int(max_iters), ctypes.c_void_p(stream), res))
+    return list(res)
+
+
+def dot_batch_extract(batch: Batch, ws_ptr: int, index: int, stream: int = 0):
+    inst = batch.insts[index]
+    D, n = inst.D, tuple(int(k) for k in inst.n)
+    sp = tuple(k + 1 for k in n[1:])
+    rho = np.zeros((n[0],) + sp)
+    shapes = []
+    for d in range(1, D + 1):
+        s = [n[0] + 1] + list(sp)
+        s[d] = n[d]
+        shapes.append(tuple(s))
+    m = np.zeros(sum(int(np.prod(s)) for s in shapes))
+    _check(load().dot_batch_extract(batch.handle, ctypes.c_void_p(ws_ptr), int(index), _dptr(rho), _dptr(m),
+                                    ctypes.c_void_p(stream)))
+    out, o = [], 0
+    for s in shapes:
+        k = int(np.prod(s))
+        out.append(m[o:o + k].reshape(s))
+        o += k
+    return rho, out
+
+
+def dot_batch_profile_select(batch: Batch, kernel_class: int):
+    _check(load().dot_batch_profile_select(batch.handle, int(kernel_class)))
+
+
+def dot_batch_profile_read(batch: Batch):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().dot_batch_profile_read(batch.handle, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
 
 
 # ---- padded-box marshalling (host side, numpy) -----------------------------

@@ -1,0 +1,132 @@
+// Descriptor-driven launches: every kernel of an iteration is one launch over
+// all instances of a batch (a single solve is a batch of one). Block b of a
+// launch serves instance map[b]; its block index inside that instance is
+// b minus the instance's first block in that launch's grid. Instances may
+// have different grids; each carries its own geometry, state pointers,
+// constant tables and control block (sigma, stop flag), so each converges and
+// stops on its own.
+#pragma once
+#include "geometry.hpp"
+#include "kernels_dct.hpp"
+#include "kernels_update.hpp"
+
+namespace dot {
+
+template <typename T>
+struct Inst {
+  Geo g;
+  double* phi;      // FP64 potential
+  T* work;          // transform work plane: phi itself (FP64) or the FP32 scratch
+  T* q[2];          // q and q_new, swapped every iteration (parity argument)
+  T* alpha;
+  T* beta;
+  T* W;
+  Ctl* ctl;         // nullptr for step-level calls (sigma from the argument)
+  double* partials;
+  const double* sw;
+  const double* om;
+  const double* c_lo;
+  const double* c_hi;
+  const T* lam_other;
+  const T* lam_last;
+  AxisTab<T> tab[kMaxAxes];
+  FinArgs fa;
+  uint32_t blk0;             // first block in the per-node grid
+  uint32_t tile0[kMaxAxes];  // first tile in each axis-pass grid
+};
+
+template <typename T>
+__device__ __forceinline__ bool stopped(const Inst<T>& s) {
+  return s.ctl && s.ctl->stop;
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_cone_q0(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+  const Inst<T>& s = I[map[blockIdx.x]];
+  if (stopped(s)) return;
+  cone_q0_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.sw, s.q[par ^ 1], s.W, s.ctl,
+                     (int64_t)blockIdx.x - s.blk0);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_qd(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+  const Inst<T>& s = I[map[blockIdx.x]];
+  if (stopped(s)) return;
+  qd_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.ctl, (int64_t)blockIdx.x - s.blk0);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_beta(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par, int check) {
+  const Inst<T>& s = I[map[blockIdx.x]];
+  if (stopped(s)) return;
+  beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, check,
+                  (int64_t)blockIdx.x - s.blk0);
+}
+
+// Residual partials at the iterate held in q[par] (the newest q).
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_resid(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+  const Inst<T>& s = I[map[blockIdx.x]];
+  if (stopped(s)) return;
+  resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials,
+                   (int64_t)blockIdx.x - s.blk0);
+}
+
+// One block per instance.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+kb_finalize(const Inst<T>* __restrict__ I, int update_ctl) {
+  const Inst<T>& s = I[blockIdx.x];
+  if (update_ctl && stopped(s)) return;
+  finalize_body(s.fa, s.partials, s.ctl, update_ctl);
+}
+
+template <typename T, int D, int KIND, int SRC, int DST>
+__global__ void __launch_bounds__(kMaxWaves * 64)
+kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int axis, int par,
+             double sigma_arg) {
+  const Inst<T>& s = I[map[blockIdx.x]];
+  if (stopped(s)) return;
+  PassArgs pa;
+  pa.inner = s.g.stride[axis];
+  pa.ncols = s.g.nb / s.g.N[axis];
+  axis_pass_body<T, D, KIND, SRC, DST>(s.g, pa, s.tab[axis], s.work, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi,
+                                       s.lam_other, s.lam_last, s.ctl, sigma_arg,
+                                       (int64_t)blockIdx.x - s.tile0[axis]);
+}
+
+// ---- step-level kernels (single instance, caller pointers) ----------------
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_cone_out(const Inst<T>* __restrict__ I, double inv_sigma, T* __restrict__ z) {
+  const Inst<T>& s = I[0];
+  cone_out_body<T, D>(s.g, s.q[0], s.beta, s.sw, inv_sigma, z, blockIdx.x);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_zres(const Inst<T>* __restrict__ I, const T* __restrict__ z) {
+  const Inst<T>& s = I[0];
+  zres_body<T, D>(s.g, z, s.q[0], s.sw, s.partials, blockIdx.x);
+}
+
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_divergence(const Inst<T>* __restrict__ I, double inv_sigma, double* __restrict__ b) {
+  const Inst<T>& s = I[0];
+  const Geo& g = s.g;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.nb) return;
+  const int t = (int)(i / g.stride[0]);
+  const uint32_t xs = (uint32_t)(i % g.stride[0]);
+  int x[kMaxAxes];
+  spatial_coords<D>(g, xs, x);
+  b[i] = divergence_at<T, D>(g, s.q[0], s.alpha, s.c_lo, s.c_hi, inv_sigma, t, xs, x);
+}
+
+}  // namespace dot

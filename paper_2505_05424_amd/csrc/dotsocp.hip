@@ -1,36 +1,30 @@
 // Host driver and C ABI of the gfx950 inexact proximal ALM for dynamic OT
 // (arXiv 2505.05424, Algorithm 2). See include/dotsocp.h for the contract.
+//
+// Every iteration is a fixed sequence of launches (2D+1 cosine-transform
+// passes, three update sweeps, and at residual checks two reduction kernels).
+// Each launch covers all instances of an executor: one plan (dot_run, a batch
+// of one) or a batch (dot_batch_run), through the descriptor arrays of
+// batch.hpp.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <type_traits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/dotsocp.h"
+#include "batch.hpp"
 #include "geometry.hpp"
 #include "kernels_dct.hpp"
 #include "kernels_update.hpp"
 
-namespace dot {
-
-template <typename T, int D>
-__global__ void __launch_bounds__(256)
-k_divergence(Geo g, const T* __restrict__ q, const T* __restrict__ al, const double* __restrict__ c_lo,
-             const double* __restrict__ c_hi, double inv_sigma, double* __restrict__ b) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.nb) return;
-  const int t = (int)(i / g.stride[0]);
-  const uint32_t xs = (uint32_t)(i % g.stride[0]);
-  int x[kMaxAxes];
-  spatial_coords<D>(g, xs, x);
-  b[i] = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, t, xs, x);
-}
+using namespace dot;
 
 namespace {
 
@@ -53,17 +47,56 @@ constexpr double kOmegaObstacle = 1e-6;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Device copy of the folded transform tables of one axis, in scalar type T.
-template <typename T>
-struct AxisDev {
-  T* buf = nullptr;
-  AxisTab<T> tab{};
+// Events around launches of one kernel class (the measurement hook).
+struct Prof {
+  int cls = -1;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t used = 0;
+  double ms = 0.0;
+  int64_t launches = 0;
+  ~Prof() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+  void collect() {
+    for (size_t k = 0; k + 1 < used; k += 2) {
+      float t = 0.f;
+      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) == hipSuccess) {
+        ms += t;
+        launches += 1;
+      }
+    }
+    used = 0;
+  }
+};
+
+struct ProfScope {
+  Prof* pr;
+  hipStream_t st;
+  bool on;
+  hipEvent_t stop = nullptr;
+  ProfScope(Prof* p, int cls, hipStream_t s) : pr(p), st(s), on(p && p->cls == cls) {
+    if (!on) return;
+    if (pr->used + 2 > pr->ev.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+          on = false;
+          return;
+        }
+        pr->ev.push_back(e);
+      }
+    }
+    hipEvent_t start = pr->ev[pr->used];
+    stop = pr->ev[pr->used + 1];
+    pr->used += 2;
+    (void)hipEventRecord(start, st);
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(stop, st);
+  }
 };
 
 }  // namespace
-}  // namespace dot
-
-using namespace dot;
 
 struct dot_plan {
   Geo g{};
@@ -76,6 +109,7 @@ struct dot_plan {
   double growth = 1.2;
   double vol = 1.0, c_norm2 = 0.0, d_norm2 = 0.0;
   int64_t nblocks = 0;  // blocks of kBlock over one plane
+  int64_t tiles[kMaxAxes] = {0, 0, 0, 0};
   // device constant tables
   double* sw_sp = nullptr;  // sqrt(omega/2) on spatial nodes
   double* om_sp = nullptr;  // omega on spatial nodes
@@ -83,10 +117,12 @@ struct dot_plan {
   double* c_hi = nullptr;   // c~ at t = n0
   void* lam_other = nullptr;
   void* lam_last = nullptr;
-  void* axis_buf[4] = {nullptr, nullptr, nullptr, nullptr};
-  AxisTab<double> tab64[4]{};
-  AxisTab<float> tab32[4]{};
-  // scratch for step-level calls
+  void* axis_buf[kMaxAxes] = {nullptr, nullptr, nullptr, nullptr};
+  AxisTab<double> tab64[kMaxAxes]{};
+  AxisTab<float> tab32[kMaxAxes]{};
+  // single-instance executor resources
+  void* d_inst = nullptr;  // two descriptor slots: [0] dot_run, [1] step calls
+  uint16_t* d_zero_map = nullptr;
   Ctl* step_ctl = nullptr;
   double* step_partials = nullptr;
   void* step_scratch = nullptr;  // FP32 transform plane (mixed precision)
@@ -97,12 +133,7 @@ struct dot_plan {
   size_t off_phi = 0, off_scr = 0, off_q = 0, off_qn = 0, off_alpha = 0, off_beta = 0, off_w = 0;
   size_t ctl_offset = 0, partials_offset = 0, state_bytes = 0;
   int device = 0;
-  // measurement hook: events around launches of one kernel class
-  int prof_class = -1;
-  std::vector<hipEvent_t> prof_ev;  // pairs (start, stop)
-  size_t prof_used = 0;
-  double prof_ms = 0.0;
-  int64_t prof_launches = 0;
+  Prof prof;
 };
 
 namespace {
@@ -137,8 +168,7 @@ void frag_major(std::vector<T>& out, int n_out, int n_in, F H) {
         for (int u = 0; u < kU; ++u) {
           const int st = ch * kU + u;
           const int r = m * 16 + l % 16, c = st * 4 + l / 16;
-          if (r < n_out && c < n_in)
-            out[base + (((size_t)m * nch + ch) * 64 + l) * kU + u] = (T)H(r, c);
+          if (r < n_out && c < n_in) out[base + (((size_t)m * nch + ch) * 64 + l) * kU + u] = (T)H(r, c);
         }
 }
 
@@ -175,8 +205,8 @@ int build_axis(dot_plan* P, int a, void** buf, AxisTab<T>* tab) {
   return DOT_OK;
 }
 
-// Waves per workgroup of a transform pass: enough for every work item of the
-// axis to fit in MfmaOps<T>::kItems rounds.
+// Waves per workgroup of a transform pass over an axis of L points: enough
+// for every work item of the axis in MfmaOps<T>::kItems rounds.
 template <typename T>
 int pass_waves(int L) {
   const int M = L / 2, ne = L - M, no = M;
@@ -226,56 +256,8 @@ int build_eigs(dot_plan* P) {
 }
 
 template <typename T>
-T* at(void* state, size_t byte_off) {
-  return reinterpret_cast<T*>(static_cast<char*>(state) + byte_off);
-}
-
-Ctl* state_ctl(void* state, const dot_plan* P) {
-  return reinterpret_cast<Ctl*>(static_cast<char*>(state) + P->ctl_offset);
-}
-
-double* state_partials(void* state, const dot_plan* P) {
-  return reinterpret_cast<double*>(static_cast<char*>(state) + P->partials_offset);
-}
-
-// Event bracket for the measurement hook; a no-op unless `cls` is selected.
-struct ProfScope {
-  dot_plan* P;
-  hipStream_t st;
-  bool on;
-  hipEvent_t stop = nullptr;
-  ProfScope(const dot_plan* Pc, int cls, hipStream_t s) : P(const_cast<dot_plan*>(Pc)), st(s), on(Pc->prof_class == cls) {
-    if (!on) return;
-    if (P->prof_used + 2 > P->prof_ev.size()) {
-      for (int k = 0; k < 64; ++k) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) {
-          on = false;
-          return;
-        }
-        P->prof_ev.push_back(e);
-      }
-    }
-    hipEvent_t start = P->prof_ev[P->prof_used];
-    stop = P->prof_ev[P->prof_used + 1];
-    P->prof_used += 2;
-    (void)hipEventRecord(start, st);
-  }
-  ~ProfScope() {
-    if (on) (void)hipEventRecord(stop, st);
-  }
-};
-
-// Sum the recorded event pairs (the stream must be synchronised).
-void prof_collect(dot_plan* P) {
-  for (size_t k = 0; k + 1 < P->prof_used; k += 2) {
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, P->prof_ev[k], P->prof_ev[k + 1]) == hipSuccess) {
-      P->prof_ms += ms;
-      P->prof_launches += 1;
-    }
-  }
-  P->prof_used = 0;
+T* at(void* base, size_t byte_off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + byte_off);
 }
 
 template <typename T>
@@ -284,103 +266,6 @@ template <>
 const AxisTab<double>& tab_of<double>(const dot_plan* P, int a) { return P->tab64[a]; }
 template <>
 const AxisTab<float>& tab_of<float>(const dot_plan* P, int a) { return P->tab32[a]; }
-
-template <typename T, int D, int KIND, int SRC, int DST>
-int launch_pass(const dot_plan* P, int a, T* work, const T* q, const T* al, double* phi, const Ctl* ctl,
-                double sigma, hipStream_t st) {
-  const Geo& g = P->g;
-  PassArgs pa;
-  pa.inner = g.stride[a];
-  pa.ncols = g.nb / g.N[a];
-  const size_t smem = (size_t)g.N[a] * (kCW + 1) * sizeof(T);
-  auto fn = k_axis_pass<T, D, KIND, SRC, DST>;
-  // the LDS opt-in is per kernel and process; set it once to the device maximum
-  static int smem_set = 0;
-  if (!smem_set) {
-    int max_smem = 0;
-    HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
-    HIP_OK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_smem));
-    smem_set = 1;
-  }
-  const unsigned grid = (unsigned)((pa.ncols + kCW - 1) / kCW);
-  const int cls = SRC != kSrcPlane ? DOT_K_DCT_FIRST
-                  : KIND == kFwdScaleInv ? DOT_K_DCT_LAST
-                  : KIND == kInv         ? DOT_K_DCT_INV
-                                         : (a == 0 ? DOT_K_DCT_FIRST : DOT_K_DCT_MID);
-  ProfScope ps(P, cls, st);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(pass_waves<T>(g.N[a]) * 64), smem, st, g, pa, tab_of<T>(P, a), work, q,
-                     al, phi, P->c_lo, P->c_hi, (const T*)P->lam_other, (const T*)P->lam_last, ctl, sigma);
-  HIP_OK(hipGetLastError());
-  return DOT_OK;
-}
-
-// The 2D+1 transform passes of one Poisson solve (a3 + a4): first pass on the
-// time axis loads according to SRC, forward passes on the middle axes, the
-// fused forward/scale/inverse pass on the last axis, inverse passes back to
-// the time axis, which stores according to DST.
-template <typename T, int D, int SRC, int DST>
-int run_passes(const dot_plan* P, T* work, const T* q, const T* al, double* phi, const Ctl* ctl, double sigma,
-               hipStream_t st) {
-  int rc;
-  if ((rc = launch_pass<T, D, kFwd, SRC, kDstPlane>(P, 0, work, q, al, phi, ctl, sigma, st))) return rc;
-  for (int a = 1; a < D; ++a)
-    if ((rc = launch_pass<T, D, kFwd, kSrcPlane, kDstPlane>(P, a, work, q, al, phi, ctl, sigma, st))) return rc;
-  if ((rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane, kDstPlane>(P, D, work, q, al, phi, ctl, sigma, st))) return rc;
-  for (int a = D - 1; a >= 1; --a)
-    if ((rc = launch_pass<T, D, kInv, kSrcPlane, kDstPlane>(P, a, work, q, al, phi, ctl, sigma, st))) return rc;
-  return launch_pass<T, D, kInv, kSrcPlane, DST>(P, 0, work, q, al, phi, ctl, sigma, st);
-}
-
-// Poisson solve inside an iteration. FP64: the transforms run in place on
-// phi. Mixed: the FP32 transforms solve A^*A dphi = b - A^*A phi on the
-// scratch plane and the last pass adds dphi to the FP64 phi.
-template <typename T, int D>
-int poisson_iter(const dot_plan* P, double* phi, T* scratch, const T* q, const T* al, const Ctl* ctl, hipStream_t st) {
-  if constexpr (std::is_same<T, double>::value)
-    return run_passes<double, D, kSrcDivergence, kDstPlane>(P, phi, q, al, phi, ctl, 0.0, st);
-  else
-    return run_passes<T, D, kSrcDefect, kDstPhiAdd>(P, scratch, q, al, phi, ctl, 0.0, st);
-}
-
-// Poisson solve of the step-level calls: from (q, alpha, sigma) if q is given,
-// else from the right-hand side already in phi; result in phi.
-template <typename T, int D>
-int poisson_step(const dot_plan* P, double* phi, const T* q, const T* al, double sigma, hipStream_t st) {
-  if constexpr (std::is_same<T, double>::value) {
-    if (q) return run_passes<double, D, kSrcDivergence, kDstPlane>(P, phi, q, al, phi, nullptr, sigma, st);
-    return run_passes<double, D, kSrcPlane, kDstPlane>(P, phi, q, al, phi, nullptr, sigma, st);
-  } else {
-    T* scr = (T*)P->step_scratch;
-    if (q) return run_passes<T, D, kSrcDivergence, kDstPhiSet>(P, scr, q, al, phi, nullptr, sigma, st);
-    return run_passes<T, D, kSrcPlaneF64, kDstPhiSet>(P, scr, q, al, phi, nullptr, sigma, st);
-  }
-}
-
-unsigned grid_nb(const dot_plan* P) { return (unsigned)P->nblocks; }
-
-template <typename T, int D>
-int run_update(const dot_plan* P, const double* phi, const T* q, T* alpha, T* beta, T* qn, T* W, Ctl* ctl,
-               double* partials, int check, hipStream_t st) {
-  const Geo& g = P->g;
-  {
-    ProfScope ps(P, DOT_K_CONE, st);
-    hipLaunchKernelGGL((k_cone_q0<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, q, alpha, beta,
-                       P->sw_sp, qn, W, ctl);
-  }
-  HIP_OK(hipGetLastError());
-  {
-    ProfScope ps(P, DOT_K_QD, st);
-    hipLaunchKernelGGL((k_qd<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, alpha, P->om_sp, qn, W, ctl);
-  }
-  HIP_OK(hipGetLastError());
-  {
-    ProfScope ps(P, DOT_K_BETA, st);
-    hipLaunchKernelGGL((k_beta<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, q, qn, beta, P->sw_sp, ctl,
-                       partials, check);
-  }
-  HIP_OK(hipGetLastError());
-  return DOT_OK;
-}
 
 FinArgs fin_args(const dot_plan* P) {
   FinArgs fa;
@@ -391,89 +276,223 @@ FinArgs fin_args(const dot_plan* P) {
   return fa;
 }
 
+// Descriptor of one instance with caller planes: phi / b (FP64), q, q_new,
+// alpha, beta, W (bulk type), transform work plane, control block, partials.
+template <typename T>
+Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, T* alpha, T* beta, T* W, Ctl* ctl,
+                double* partials) {
+  Inst<T> s{};
+  s.g = P->g;
+  s.phi = phi;
+  s.work = std::is_same<T, double>::value ? reinterpret_cast<T*>(phi) : scr;
+  s.q[0] = q;
+  s.q[1] = qn;
+  s.alpha = alpha;
+  s.beta = beta;
+  s.W = W;
+  s.ctl = ctl;
+  s.partials = partials;
+  s.sw = P->sw_sp;
+  s.om = P->om_sp;
+  s.c_lo = P->c_lo;
+  s.c_hi = P->c_hi;
+  s.lam_other = (const T*)P->lam_other;
+  s.lam_last = (const T*)P->lam_last;
+  for (int a = 0; a < kMaxAxes; ++a) s.tab[a] = tab_of<T>(P, a);
+  s.fa = fin_args(P);
+  return s;
+}
+
+// Descriptor of an instance whose state buffer (plan layout) is at `state`
+// and whose control block is at `ctl`.
+template <typename T>
+Inst<T> state_inst(const dot_plan* P, void* state, Ctl* ctl) {
+  return inst_of<T>(P, at<double>(state, P->off_phi), at<T>(state, P->off_scr), at<T>(state, P->off_q),
+                    at<T>(state, P->off_qn), at<T>(state, P->off_alpha), at<T>(state, P->off_beta),
+                    at<T>(state, P->off_w), ctl, at<double>(state, P->partials_offset));
+}
+
+Ctl initial_ctl(const dot_plan* P) {
+  Ctl h{};
+  h.sigma = P->sigma0;
+  h.tau = P->tau;
+  h.tol = P->tol;
+  h.next_update = P->gap0;
+  h.gap = P->gap0;
+  h.growth = P->growth;
+  h.adapt = P->adapt;
+  h.cadence = P->cadence;
+  return h;
+}
+
+// Launch geometry of one executor: the descriptor array, block maps and,
+// per phase, grid size, LDS bytes and waves.
+struct Exec {
+  int D = 0, precision = 0, ninst = 0, cadence = 5;
+  void* d_inst = nullptr;
+  const uint16_t* map_nodes = nullptr;
+  const uint16_t* map_axis[kMaxAxes] = {nullptr, nullptr, nullptr, nullptr};
+  unsigned grid_nodes = 0;
+  unsigned grid_axis[kMaxAxes] = {0, 0, 0, 0};
+  size_t smem_axis[kMaxAxes] = {0, 0, 0, 0};
+  int waves_axis[kMaxAxes] = {0, 0, 0, 0};
+  Prof* prof = nullptr;
+  int device = 0;
+};
+
+template <typename T, int D, int KIND, int SRC, int DST>
+int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
+  auto fn = kb_axis_pass<T, D, KIND, SRC, DST>;
+  // the LDS opt-in is per kernel and process; set it once to the device maximum
+  static int smem_set = 0;
+  if (!smem_set) {
+    int max_smem = 0;
+    HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, E.device));
+    HIP_OK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_smem));
+    smem_set = 1;
+  }
+  const int cls = SRC != kSrcPlane ? DOT_K_DCT_FIRST
+                  : KIND == kFwdScaleInv ? DOT_K_DCT_LAST
+                  : KIND == kInv         ? DOT_K_DCT_INV
+                                         : (a == 0 ? DOT_K_DCT_FIRST : DOT_K_DCT_MID);
+  ProfScope ps(E.prof, cls, st);
+  hipLaunchKernelGGL(fn, dim3(E.grid_axis[a]), dim3(E.waves_axis[a] * 64), E.smem_axis[a], st,
+                     (const Inst<T>*)E.d_inst, E.map_axis[a], a, par, sigma);
+  HIP_OK(hipGetLastError());
+  return DOT_OK;
+}
+
+// The 2D+1 transform passes of one Poisson solve (a3 + a4): first pass on the
+// time axis loads according to SRC, forward passes on the middle axes, the
+// fused forward/scale/inverse pass on the last axis, inverse passes back to
+// the time axis, which stores according to DST.
+template <typename T, int D, int SRC, int DST>
+int run_passes(const Exec& E, int par, double sigma, hipStream_t st) {
+  int rc;
+  if ((rc = launch_pass<T, D, kFwd, SRC, kDstPlane>(E, 0, par, sigma, st))) return rc;
+  for (int a = 1; a < D; ++a)
+    if ((rc = launch_pass<T, D, kFwd, kSrcPlane, kDstPlane>(E, a, par, sigma, st))) return rc;
+  if ((rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane, kDstPlane>(E, D, par, sigma, st))) return rc;
+  for (int a = D - 1; a >= 1; --a)
+    if ((rc = launch_pass<T, D, kInv, kSrcPlane, kDstPlane>(E, a, par, sigma, st))) return rc;
+  return launch_pass<T, D, kInv, kSrcPlane, DST>(E, 0, par, sigma, st);
+}
+
+// Poisson solve inside an iteration. FP64: the transforms run in place on
+// phi. Mixed: the FP32 transforms solve A^*A dphi = b - A^*A phi on the
+// scratch plane and the last pass adds dphi to the FP64 phi.
 template <typename T, int D>
-int run_check(const dot_plan* P, const double* phi, const T* q, const T* alpha, const T* beta, Ctl* ctl,
-              double* partials, int update_ctl, hipStream_t st) {
-  const Geo& g = P->g;
+int poisson_iter(const Exec& E, int par, hipStream_t st) {
+  if constexpr (std::is_same<T, double>::value)
+    return run_passes<double, D, kSrcDivergence, kDstPlane>(E, par, 0.0, st);
+  else
+    return run_passes<T, D, kSrcDefect, kDstPhiAdd>(E, par, 0.0, st);
+}
+
+template <typename T, int D>
+int update_iter(const Exec& E, int par, int check, hipStream_t st) {
+  const Inst<T>* I = (const Inst<T>*)E.d_inst;
   {
-    ProfScope ps(P, DOT_K_RESID, st);
-    hipLaunchKernelGGL((k_resid<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, g, phi, q, alpha, beta, P->om_sp,
-                       P->sw_sp, P->c_lo, P->c_hi, update_ctl ? ctl : nullptr, partials);
+    ProfScope ps(E.prof, DOT_K_CONE, st);
+    hipLaunchKernelGGL((kb_cone_q0<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
   }
   HIP_OK(hipGetLastError());
   {
-    ProfScope ps(P, DOT_K_FINAL, st);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, st, fin_args(P), partials, ctl, update_ctl);
+    ProfScope ps(E.prof, DOT_K_QD, st);
+    hipLaunchKernelGGL((kb_qd<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
+  }
+  HIP_OK(hipGetLastError());
+  {
+    ProfScope ps(E.prof, DOT_K_BETA, st);
+    hipLaunchKernelGGL((kb_beta<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par, check);
   }
   HIP_OK(hipGetLastError());
   return DOT_OK;
 }
 
+// Residual partials at the iterate in q[qpar], then one finalize block per
+// instance.
 template <typename T, int D>
-int run_iters(dot_plan* P, void* state, int max_iters, hipStream_t st, dot_result* res) {
-  Ctl* ctl = state_ctl(state, P);
-  double* partials = state_partials(state, P);
-  HIP_OK(hipMemcpyAsync(P->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-  HIP_OK(hipStreamSynchronize(st));
-  const int iter0 = P->host_ctl->iter;
-  int stopped = P->host_ctl->stop;
-  double* phi = at<double>(state, P->off_phi);
-  T* scr = at<T>(state, P->off_scr);
-  T* qa = at<T>(state, P->off_q);
-  T* qb = at<T>(state, P->off_qn);
-  T* alpha = at<T>(state, P->off_alpha);
-  T* beta = at<T>(state, P->off_beta);
-  T* W = at<T>(state, P->off_w);
+int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
+  const Inst<T>* I = (const Inst<T>*)E.d_inst;
+  {
+    ProfScope ps(E.prof, DOT_K_RESID, st);
+    hipLaunchKernelGGL((kb_resid<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, qpar);
+  }
+  HIP_OK(hipGetLastError());
+  {
+    ProfScope ps(E.prof, DOT_K_FINAL, st);
+    hipLaunchKernelGGL((kb_finalize<T>), dim3(E.ninst), dim3(1024), 0, st, I, update_ctl);
+  }
+  HIP_OK(hipGetLastError());
+  return DOT_OK;
+}
+
+// Run up to max_iters iterations of every instance of E in lockstep starting
+// at iteration it0 (same for all instances); ctl_host (pinned, ninst entries
+// at stride ctl_stride) is refreshed from ctl_dev every `poll` iterations and
+// the loop ends once every instance has stopped.
+template <typename T, int D>
+int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t ctl_stride, void* ctl_host,
+              hipStream_t st, int* done_iters) {
   const int poll = 40;
-  int rc;
-  for (int j = 0; j < max_iters && !stopped; ++j) {
-    const int it = iter0 + j;
-    T* cur = (it % 2 == 0) ? qa : qb;
-    T* nxt = (it % 2 == 0) ? qb : qa;
-    if ((rc = poisson_iter<T, D>(P, phi, scr, cur, alpha, ctl, st))) return rc;
-    const int check = ((it + 1) % P->cadence) == 0;
-    if ((rc = run_update<T, D>(P, phi, cur, alpha, beta, nxt, W, ctl, partials, check, st))) return rc;
-    if (check && (rc = run_check<T, D>(P, phi, nxt, alpha, beta, ctl, partials, 1, st))) return rc;
-    if ((j + 1) % poll == 0 || j + 1 == max_iters) {
-      HIP_OK(hipMemcpyAsync(P->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  auto all_stopped = [&]() {
+    for (int i = 0; i < E.ninst; ++i)
+      if (!reinterpret_cast<const Ctl*>(static_cast<const char*>(ctl_host) + i * ctl_stride)->stop) return false;
+    return true;
+  };
+  int j = 0;
+  while (j < max_iters) {
+    const int it = it0 + j;
+    const int par = it & 1;
+    int rc;
+    if ((rc = poisson_iter<T, D>(E, par, st))) return rc;
+    const int check = ((it + 1) % E.cadence) == 0;
+    if ((rc = update_iter<T, D>(E, par, check, st))) return rc;
+    if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
+    ++j;
+    if (j % poll == 0 || j == max_iters) {
+      HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * E.ninst, hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
-      prof_collect(P);
-      stopped = P->host_ctl->stop;
+      if (E.prof) E.prof->collect();
+      if (all_stopped()) break;
     }
   }
-  HIP_OK(hipMemcpyAsync(P->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * E.ninst, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  prof_collect(P);
-  if (res) {
-    const Ctl& c = *P->host_ctl;
-    res->objective = c.objective;
-    res->dual_objective = c.dual_objective;
-    res->eta_dot = c.eta[0];
-    res->eta_p = c.eta[1];
-    res->eta_d = c.eta[2];
-    res->eta_c = c.eta[3];
-    res->eta_p_soc = c.eta[4];
-    res->eta_d_soc = c.eta[5];
-    res->sigma = c.sigma;
-    res->iters = c.iter;
-    res->checks = c.checks;
-    res->sigma_changes = c.sigma_changes;
-    res->term = c.stop == 1 ? DOT_CONVERGED : (c.stop == 3 ? DOT_DIVERGED : DOT_MAXITER);
-  }
+  if (E.prof) E.prof->collect();
+  if (done_iters) *done_iters = j;
   return DOT_OK;
+}
+
+void fill_result(const Ctl& c, dot_result* res) {
+  if (!res) return;
+  res->objective = c.objective;
+  res->dual_objective = c.dual_objective;
+  res->eta_dot = c.eta[0];
+  res->eta_p = c.eta[1];
+  res->eta_d = c.eta[2];
+  res->eta_c = c.eta[3];
+  res->eta_p_soc = c.eta[4];
+  res->eta_d_soc = c.eta[5];
+  res->sigma = c.sigma;
+  res->iters = c.iter;
+  res->checks = c.checks;
+  res->sigma_changes = c.sigma_changes;
+  res->term = c.stop == 1 ? DOT_CONVERGED : (c.stop == 3 ? DOT_DIVERGED : DOT_MAXITER);
 }
 
 // Dispatch on (scalar type, D).
 template <template <typename, int> class F, typename... A>
-int dispatch(const dot_plan* P, A&&... args) {
-  if (P->precision == DOT_FP64) {
-    switch (P->D) {
+int dispatch(int precision, int D, A&&... args) {
+  if (precision == DOT_FP64) {
+    switch (D) {
       case 1: return F<double, 1>::run(std::forward<A>(args)...);
       case 2: return F<double, 2>::run(std::forward<A>(args)...);
       case 3: return F<double, 3>::run(std::forward<A>(args)...);
     }
   } else {
-    switch (P->D) {
+    switch (D) {
       case 1: return F<float, 1>::run(std::forward<A>(args)...);
       case 2: return F<float, 2>::run(std::forward<A>(args)...);
       case 3: return F<float, 3>::run(std::forward<A>(args)...);
@@ -482,35 +501,102 @@ int dispatch(const dot_plan* P, A&&... args) {
   return fail(DOT_EINVAL, "unsupported D");
 }
 
+size_t inst_slot_bytes() { return align256(std::max(sizeof(Inst<double>), sizeof(Inst<float>))); }
+
+// Single-instance executor of a plan; descriptor slot 0 (run) or 1 (steps).
+Exec plan_exec(dot_plan* P, int slot) {
+  Exec E;
+  E.D = P->D;
+  E.precision = P->precision;
+  E.ninst = 1;
+  E.cadence = P->cadence;
+  E.d_inst = static_cast<char*>(P->d_inst) + slot * inst_slot_bytes();
+  E.map_nodes = P->d_zero_map;
+  E.grid_nodes = (unsigned)P->nblocks;
+  for (int a = 0; a <= P->D; ++a) {
+    E.map_axis[a] = P->d_zero_map;
+    E.grid_axis[a] = (unsigned)P->tiles[a];
+    E.smem_axis[a] = (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes;
+    E.waves_axis[a] = P->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a]) : pass_waves<float>(P->g.N[a]);
+  }
+  E.prof = &P->prof;
+  E.device = P->device;
+  return E;
+}
+
+template <typename T>
+int upload_inst(const Exec& E, const Inst<T>& s, hipStream_t st) {
+  HIP_OK(hipMemcpyAsync(E.d_inst, &s, sizeof(s), hipMemcpyHostToDevice, st));
+  return DOT_OK;
+}
+
 template <typename T, int D>
 struct RunF {
   static int run(dot_plan* P, void* state, int max_iters, hipStream_t st, dot_result* res) {
-    return run_iters<T, D>(P, state, max_iters, st, res);
+    Ctl* ctl = at<Ctl>(state, P->ctl_offset);
+    HIP_OK(hipMemcpyAsync(P->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const int it0 = P->host_ctl->iter;
+    Exec E = plan_exec(P, 0);
+    int rc = upload_inst(E, state_inst<T>(P, state, ctl), st);
+    if (rc) return rc;
+    if (!P->host_ctl->stop) {
+      rc = run_iters<T, D>(E, it0, max_iters, ctl, sizeof(Ctl), P->host_ctl, st, nullptr);
+      if (rc) return rc;
+    }
+    fill_result(*P->host_ctl, res);
+    return DOT_OK;
   }
 };
+
+// Step-level calls: a descriptor with the caller's planes in slot 1.
+template <typename T>
+Inst<T> step_inst(dot_plan* P, const void* phi, const void* q, const void* alpha, const void* beta, void* q_out,
+                  void* W, Ctl* ctl) {
+  return inst_of<T>(P, (double*)phi, (T*)P->step_scratch, (T*)q, (T*)q_out, (T*)alpha, (T*)beta, (T*)W, ctl,
+                    P->step_partials);
+}
 
 template <typename T, int D>
 struct DivF {
   static int run(dot_plan* P, const void* q, const void* al, double sigma, void* b, hipStream_t st) {
-    hipLaunchKernelGGL((k_divergence<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, P->g, (const T*)q,
-                       (const T*)al, P->c_lo, P->c_hi, 1.0 / sigma, (double*)b);
+    Exec E = plan_exec(P, 1);
+    int rc = upload_inst(E, step_inst<T>(P, nullptr, q, al, nullptr, nullptr, nullptr, nullptr), st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((kb_divergence<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+                       1.0 / sigma, (double*)b);
     HIP_OK(hipGetLastError());
     return DOT_OK;
   }
 };
 
+// Poisson solve of the step-level calls: from (q, alpha, sigma) if q is given,
+// else from the right-hand side already in phi; result in phi.
 template <typename T, int D>
 struct PoissonF {
-  static int run(dot_plan* P, void* b, const void* q, const void* al, double sigma, hipStream_t st) {
-    return poisson_step<T, D>(P, (double*)b, (const T*)q, (const T*)al, sigma, st);
+  static int run(dot_plan* P, void* phi, const void* q, const void* al, double sigma, hipStream_t st) {
+    Exec E = plan_exec(P, 1);
+    E.prof = nullptr;
+    int rc = upload_inst(E, step_inst<T>(P, phi, q, al, nullptr, nullptr, nullptr, nullptr), st);
+    if (rc) return rc;
+    if constexpr (std::is_same<T, double>::value) {
+      if (q) return run_passes<double, D, kSrcDivergence, kDstPlane>(E, 0, sigma, st);
+      return run_passes<double, D, kSrcPlane, kDstPlane>(E, 0, sigma, st);
+    } else {
+      if (q) return run_passes<T, D, kSrcDivergence, kDstPhiSet>(E, 0, sigma, st);
+      return run_passes<T, D, kSrcPlaneF64, kDstPhiSet>(E, 0, sigma, st);
+    }
   }
 };
 
 template <typename T, int D>
 struct ConeF {
   static int run(dot_plan* P, const void* q, const void* beta, double sigma, void* z, hipStream_t st) {
-    hipLaunchKernelGGL((k_cone_out<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, P->g, (const T*)q,
-                       (const T*)beta, P->sw_sp, 1.0 / sigma, (T*)z);
+    Exec E = plan_exec(P, 1);
+    int rc = upload_inst(E, step_inst<T>(P, nullptr, q, nullptr, beta, nullptr, nullptr, nullptr), st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((kb_cone_out<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+                       1.0 / sigma, (T*)z);
     HIP_OK(hipGetLastError());
     return DOT_OK;
   }
@@ -518,15 +604,17 @@ struct ConeF {
 
 template <typename T, int D>
 struct UpdateF {
-  static int run(dot_plan* P, const void* phi, const void* q, void* alpha, void* beta, double sigma,
-                 double tau, void* qn, void* W, hipStream_t st) {
+  static int run(dot_plan* P, const void* phi, const void* q, void* alpha, void* beta, double sigma, double tau,
+                 void* qn, void* W, hipStream_t st) {
+    Exec E = plan_exec(P, 1);
+    E.prof = nullptr;
     Ctl h{};
     h.sigma = sigma;
     h.tau = tau;
-    h.stop = 0;
     HIP_OK(hipMemcpyAsync(P->step_ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    int rc = run_update<T, D>(P, (const double*)phi, (const T*)q, (T*)alpha, (T*)beta, (T*)qn, (T*)W, P->step_ctl,
-                              P->step_partials, 0, st);
+    int rc = upload_inst(E, step_inst<T>(P, phi, q, alpha, beta, qn, W, P->step_ctl), st);
+    if (rc) return rc;
+    rc = update_iter<T, D>(E, 0, 0, st);
     if (rc) return rc;
     HIP_OK(hipStreamSynchronize(st));
     return DOT_OK;
@@ -535,13 +623,18 @@ struct UpdateF {
 
 template <typename T, int D>
 struct ResidF {
-  static int run(dot_plan* P, const void* phi, const void* z, const void* q, const void* alpha,
-                 const void* beta, hipStream_t st) {
-    hipLaunchKernelGGL((k_zres<T, D>), dim3(grid_nb(P)), dim3(kBlock), 0, st, P->g, (const T*)z, (const T*)q,
-                       P->sw_sp, P->step_partials);
+  static int run(dot_plan* P, const void* phi, const void* z, const void* q, const void* alpha, const void* beta,
+                 hipStream_t st) {
+    Exec E = plan_exec(P, 1);
+    E.prof = nullptr;
+    Ctl h{};  // stop = 0: the finalize block fills the residuals only
+    HIP_OK(hipMemcpyAsync(P->step_ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    int rc = upload_inst(E, step_inst<T>(P, phi, q, alpha, beta, nullptr, nullptr, P->step_ctl), st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((kb_zres<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+                       (const T*)z);
     HIP_OK(hipGetLastError());
-    return run_check<T, D>(P, (const double*)phi, (const T*)q, (const T*)alpha, (const T*)beta, P->step_ctl,
-                           P->step_partials, 0, st);
+    return check_iter<T, D>(E, 0, 0, st);
   }
 };
 
@@ -572,6 +665,88 @@ int validate(const dot_problem* p) {
   return DOT_OK;
 }
 
+int extract_impl(dot_plan* P, const void* state, double* rho_out, double* m_out, hipStream_t st) {
+  const Geo& g = P->g;
+  const size_t sb = P->scalar_bytes;
+  std::vector<unsigned char> buf(g.nb * sb);
+  auto get = [&](size_t i) -> double {
+    return sb == 8 ? reinterpret_cast<const double*>(buf.data())[i] : reinterpret_cast<const float*>(buf.data())[i];
+  };
+  const char* base = static_cast<const char*>(state);
+  if (rho_out) {
+    HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha, g.nb * sb, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    const int64_t ncell = (int64_t)g.n[0] * g.nx;
+    for (int64_t i = 0; i < ncell; ++i) rho_out[i] = get(i);
+  }
+  if (m_out) {
+    size_t o = 0;
+    for (int d = 1; d <= P->D; ++d) {
+      HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha + (size_t)d * g.nb * sb, g.nb * sb,
+                            hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      for (int64_t i = 0; i < g.nb; ++i) {
+        const int64_t r = i / g.stride[d];
+        const int xd = (int)(r % g.N[d]);
+        if (xd < g.n[d]) m_out[o++] = get(i);
+      }
+    }
+  }
+  return DOT_OK;
+}
+
+}  // namespace
+
+// A batch: one plan per instance, all instance states in one caller workspace
+// (control blocks first, contiguous, so one copy polls every stop flag), and
+// one executor whose launches cover every instance.
+struct dot_batch {
+  std::vector<dot_plan*> plans;
+  int D = 0, precision = 0, cadence = 5;
+  size_t ctl_stride = 256;
+  std::vector<size_t> state_off;  // byte offset of each instance state in the workspace
+  size_t ws_bytes = 0;
+  void* d_inst = nullptr;
+  uint16_t* d_maps = nullptr;  // node map, then one map per axis
+  Exec E;
+  Ctl* host_ctl = nullptr;     // pinned, one entry per instance at ctl_stride
+  int it = 0;                  // iterations done (all instances in lockstep)
+  Prof prof;
+};
+
+namespace {
+
+template <typename T>
+int batch_descriptors(dot_batch* B, void* ws, hipStream_t st) {
+  const int count = (int)B->plans.size();
+  std::vector<Inst<T>> host(count);
+  uint32_t blk = 0;
+  uint32_t tile[kMaxAxes] = {0, 0, 0, 0};
+  for (int i = 0; i < count; ++i) {
+    dot_plan* P = B->plans[i];
+    Ctl* ctl = reinterpret_cast<Ctl*>(static_cast<char*>(ws) + (size_t)i * B->ctl_stride);
+    host[i] = state_inst<T>(P, static_cast<char*>(ws) + B->state_off[i], ctl);
+    host[i].blk0 = blk;
+    blk += (uint32_t)P->nblocks;
+    for (int a = 0; a <= B->D; ++a) {
+      host[i].tile0[a] = tile[a];
+      tile[a] += (uint32_t)P->tiles[a];
+    }
+  }
+  HIP_OK(hipMemcpyAsync(B->d_inst, host.data(), sizeof(Inst<T>) * count, hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return DOT_OK;
+}
+
+template <typename T, int D>
+struct BatchRunF {
+  static int run(dot_batch* B, void* ws, int max_iters, hipStream_t st, int* done) {
+    int rc = batch_descriptors<T>(B, ws, st);
+    if (rc) return rc;
+    return run_iters<T, D>(B->E, B->it, max_iters, ws, B->ctl_stride, B->host_ctl, st, done);
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -580,7 +755,6 @@ const char* dot_last_error(void) { return g_err.c_str(); }
 
 void dot_plan_destroy(dot_plan* P) {
   if (!P) return;
-  for (auto e : P->prof_ev) (void)hipEventDestroy(e);
   (void)hipFree(P->sw_sp);
   (void)hipFree(P->om_sp);
   (void)hipFree(P->c_lo);
@@ -588,6 +762,8 @@ void dot_plan_destroy(dot_plan* P) {
   (void)hipFree(P->lam_other);
   (void)hipFree(P->lam_last);
   for (auto* b : P->axis_buf) (void)hipFree(b);
+  (void)hipFree(P->d_inst);
+  (void)hipFree(P->d_zero_map);
   (void)hipFree(P->step_ctl);
   (void)hipFree(P->step_partials);
   (void)hipFree(P->step_scratch);
@@ -642,6 +818,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
     const bool fits = P->precision == DOT_FP64 ? axis_fits<double>(g.N[a]) : axis_fits<float>(g.N[a]);
     if ((int64_t)need > max_smem || !fits)
       return fail(DOT_EINVAL, "axis of " + std::to_string(g.N[a]) + " nodes exceeds the transform tile capacity");
+    P->tiles[a] = (g.nb / g.N[a] + kCW - 1) / kCW;
   }
   // problem data
   const int64_t nx = g.nx;
@@ -689,6 +866,11 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   HIP_OK(hipMalloc((void**)&P->step_partials, (size_t)P->nblocks * kNumSums * sizeof(double)));
   HIP_OK(hipMemset(P->step_partials, 0, (size_t)P->nblocks * kNumSums * sizeof(double)));
   HIP_OK(hipHostMalloc((void**)&P->host_ctl, sizeof(Ctl), hipHostMallocDefault));
+  HIP_OK(hipMalloc(&P->d_inst, 2 * inst_slot_bytes()));
+  int64_t maxgrid = P->nblocks;
+  for (int a = 0; a <= D; ++a) maxgrid = std::max(maxgrid, P->tiles[a]);
+  HIP_OK(hipMalloc((void**)&P->d_zero_map, (size_t)maxgrid * sizeof(uint16_t)));
+  HIP_OK(hipMemset(P->d_zero_map, 0, (size_t)maxgrid * sizeof(uint16_t)));
   *out = P.release();
   return DOT_OK;
 }
@@ -716,123 +898,82 @@ int dot_state_reset(dot_plan* P, void* state, void* stream) {
   if (!P || !state) return fail(DOT_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
   HIP_OK(hipMemsetAsync(state, 0, P->ctl_offset, st));
-  Ctl h{};
-  h.sigma = P->sigma0;
-  h.tau = P->tau;
-  h.tol = P->tol;
-  h.iter = 0;
-  h.stop = 0;
-  h.next_update = P->gap0;
-  h.gap = P->gap0;
-  h.growth = P->growth;
-  h.adapt = P->adapt;
-  h.cadence = P->cadence;
-  *P->host_ctl = h;
-  HIP_OK(hipMemcpyAsync(state_ctl(state, P), P->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  *P->host_ctl = initial_ctl(P);
+  HIP_OK(hipMemcpyAsync(at<Ctl>(state, P->ctl_offset), P->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
   return DOT_OK;
 }
 
 int dot_run(dot_plan* P, void* state, int32_t max_iters, void* stream, dot_result* res) {
   if (!P || !state || max_iters < 0) return fail(DOT_EINVAL, "bad argument");
-  return dispatch<RunF>(P, P, state, (int)max_iters, (hipStream_t)stream, res);
+  return dispatch<RunF>(P->precision, P->D, P, state, (int)max_iters, (hipStream_t)stream, res);
 }
 
 int dot_extract(dot_plan* P, const void* state, double* rho_out, double* m_out, void* stream) {
   if (!P || !state) return fail(DOT_EINVAL, "null argument");
-  hipStream_t st = (hipStream_t)stream;
-  const Geo& g = P->g;
-  const size_t sb = P->scalar_bytes;
-  std::vector<unsigned char> buf(g.nb * sb);
-  auto get = [&](size_t i) -> double {
-    return sb == 8 ? reinterpret_cast<const double*>(buf.data())[i] : reinterpret_cast<const float*>(buf.data())[i];
-  };
-  const char* base = static_cast<const char*>(state);
-  if (rho_out) {
-    HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha, g.nb * sb, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
-    const int64_t ncell = (int64_t)g.n[0] * g.nx;
-    for (int64_t i = 0; i < ncell; ++i) rho_out[i] = get(i);
-  }
-  if (m_out) {
-    size_t o = 0;
-    for (int d = 1; d <= P->D; ++d) {
-      HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha + (size_t)d * g.nb * sb, g.nb * sb,
-                            hipMemcpyDeviceToHost, st));
-      HIP_OK(hipStreamSynchronize(st));
-      for (int64_t i = 0; i < g.nb; ++i) {
-        int64_t r = i / g.stride[d];
-        const int xd = (int)(r % g.N[d]);
-        if (xd < g.n[d]) m_out[o++] = get(i);
-      }
-    }
-  }
-  return DOT_OK;
+  return extract_impl(P, state, rho_out, m_out, (hipStream_t)stream);
 }
 
 int dot_step_divergence(dot_plan* P, const void* q, const void* alpha, double sigma, void* b, void* stream) {
   if (!P || !q || !alpha || !b || !(sigma > 0)) return fail(DOT_EINVAL, "bad argument");
-  return dispatch<DivF>(P, P, q, alpha, sigma, b, (hipStream_t)stream);
+  return dispatch<DivF>(P->precision, P->D, P, q, alpha, sigma, b, (hipStream_t)stream);
 }
 
 int dot_step_poisson(dot_plan* P, void* b, void* stream) {
   if (!P || !b) return fail(DOT_EINVAL, "bad argument");
-  return dispatch<PoissonF>(P, P, b, (const void*)nullptr, (const void*)nullptr, 1.0, (hipStream_t)stream);
+  return dispatch<PoissonF>(P->precision, P->D, P, b, (const void*)nullptr, (const void*)nullptr, 1.0,
+                            (hipStream_t)stream);
 }
 
 int dot_step_rhs_poisson(dot_plan* P, const void* q, const void* alpha, double sigma, void* phi, void* stream) {
   if (!P || !q || !alpha || !phi || !(sigma > 0)) return fail(DOT_EINVAL, "bad argument");
-  return dispatch<PoissonF>(P, P, phi, q, alpha, sigma, (hipStream_t)stream);
+  return dispatch<PoissonF>(P->precision, P->D, P, phi, q, alpha, sigma, (hipStream_t)stream);
 }
 
 int dot_step_cone(dot_plan* P, const void* q, const void* beta, double sigma, void* z, void* stream) {
   if (!P || !q || !beta || !z || !(sigma > 0)) return fail(DOT_EINVAL, "bad argument");
-  return dispatch<ConeF>(P, P, q, beta, sigma, z, (hipStream_t)stream);
+  return dispatch<ConeF>(P->precision, P->D, P, q, beta, sigma, z, (hipStream_t)stream);
 }
 
 int dot_step_update(dot_plan* P, const void* phi, const void* q, void* alpha, void* beta, double sigma, double tau,
                     void* q_out, void* w_scratch, void* stream) {
   if (!P || !phi || !q || !alpha || !beta || !q_out || !w_scratch || !(sigma > 0) || !(tau > 0))
     return fail(DOT_EINVAL, "bad argument");
-  return dispatch<UpdateF>(P, P, phi, q, alpha, beta, sigma, tau, q_out, w_scratch, (hipStream_t)stream);
+  return dispatch<UpdateF>(P->precision, P->D, P, phi, q, alpha, beta, sigma, tau, q_out, w_scratch,
+                           (hipStream_t)stream);
 }
 
 int dot_step_residuals(dot_plan* P, const void* phi, const void* z, const void* q, const void* alpha,
                        const void* beta, dot_result* res, void* stream) {
   if (!P || !phi || !z || !q || !alpha || !beta || !res) return fail(DOT_EINVAL, "bad argument");
   hipStream_t st = (hipStream_t)stream;
-  int rc = dispatch<ResidF>(P, P, phi, z, q, alpha, beta, st);
+  int rc = dispatch<ResidF>(P->precision, P->D, P, phi, z, q, alpha, beta, st);
   if (rc) return rc;
   HIP_OK(hipMemcpyAsync(P->host_ctl, P->step_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  const Ctl& c = *P->host_ctl;
   std::memset(res, 0, sizeof(*res));
-  res->objective = c.objective;
-  res->dual_objective = c.dual_objective;
-  res->eta_dot = c.eta[0];
-  res->eta_p = c.eta[1];
-  res->eta_d = c.eta[2];
-  res->eta_c = c.eta[3];
-  res->eta_p_soc = c.eta[4];
-  res->eta_d_soc = c.eta[5];
+  fill_result(*P->host_ctl, res);
+  res->iters = 0;
+  res->checks = 0;
+  res->term = DOT_RUNNING;
   return DOT_OK;
 }
 
 int dot_profile_select(dot_plan* P, int32_t kernel_class) {
   if (!P || kernel_class < -1 || kernel_class > DOT_K_FINAL) return fail(DOT_EINVAL, "bad kernel class");
-  P->prof_class = kernel_class;
-  P->prof_used = 0;
-  P->prof_ms = 0.0;
-  P->prof_launches = 0;
+  P->prof.cls = kernel_class;
+  P->prof.used = 0;
+  P->prof.ms = 0.0;
+  P->prof.launches = 0;
   return DOT_OK;
 }
 
 int dot_profile_read(dot_plan* P, double* total_ms, int64_t* launches) {
   if (!P) return fail(DOT_EINVAL, "null plan");
-  if (total_ms) *total_ms = P->prof_ms;
-  if (launches) *launches = P->prof_launches;
-  P->prof_ms = 0.0;
-  P->prof_launches = 0;
+  if (total_ms) *total_ms = P->prof.ms;
+  if (launches) *launches = P->prof.launches;
+  P->prof.ms = 0.0;
+  P->prof.launches = 0;
   return DOT_OK;
 }
 
@@ -852,6 +993,137 @@ int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* 
   (void)hipFree(state);
   dot_plan_destroy(P);
   return rc;
+}
+
+// ---- batches ---------------------------------------------------------------
+
+void dot_batch_destroy(dot_batch* B) {
+  if (!B) return;
+  for (auto* p : B->plans) dot_plan_destroy(p);
+  (void)hipFree(B->d_inst);
+  (void)hipFree(B->d_maps);
+  (void)hipHostFree(B->host_ctl);
+  delete B;
+}
+
+int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
+  if (!out || !probs || count < 1 || count > 65535) return fail(DOT_EINVAL, "bad batch arguments");
+  *out = nullptr;
+  std::unique_ptr<dot_batch, void (*)(dot_batch*)> B(new (std::nothrow) dot_batch(), dot_batch_destroy);
+  if (!B) return fail(DOT_ENOMEM, "host allocation failed");
+  auto cad = [](const dot_problem& p) { return p.check_every > 0 ? p.check_every : 5; };
+  for (int i = 0; i < count; ++i) {
+    if (probs[i].D != probs[0].D || probs[i].precision != probs[0].precision || cad(probs[i]) != cad(probs[0]))
+      return fail(DOT_EINVAL, "all problems of a batch need the same D, precision and check cadence");
+    dot_plan* P = nullptr;
+    int rc = dot_plan_create(&probs[i], &P);
+    if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
+    B->plans.push_back(P);
+  }
+  const int D = probs[0].D;
+  B->D = D;
+  B->precision = probs[0].precision;
+  B->cadence = B->plans[0]->cadence;
+  B->ctl_stride = align256(sizeof(Ctl));
+  size_t off = align256(B->ctl_stride * count);
+  for (auto* P : B->plans) {
+    B->state_off.push_back(off);
+    off += align256(P->state_bytes);
+  }
+  B->ws_bytes = off;
+  // block maps (block -> instance): node grid first, then one per axis
+  std::vector<uint16_t> maps;
+  Exec& E = B->E;
+  E.D = D;
+  E.precision = B->precision;
+  E.ninst = count;
+  E.cadence = B->cadence;
+  E.device = B->plans[0]->device;
+  for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)B->plans[i]->nblocks, (uint16_t)i);
+  E.grid_nodes = (unsigned)maps.size();
+  size_t map_off[kMaxAxes] = {0, 0, 0, 0};
+  for (int a = 0; a <= D; ++a) {
+    map_off[a] = maps.size();
+    size_t smem = 0;
+    int waves = 1;
+    for (int i = 0; i < count; ++i) {
+      dot_plan* P = B->plans[i];
+      maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)i);
+      smem = std::max(smem, (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes);
+      waves = std::max(waves, B->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a]) : pass_waves<float>(P->g.N[a]));
+    }
+    E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);
+    E.smem_axis[a] = smem;
+    E.waves_axis[a] = waves;
+  }
+  HIP_OK(hipMalloc((void**)&B->d_maps, maps.size() * sizeof(uint16_t)));
+  HIP_OK(hipMemcpy(B->d_maps, maps.data(), maps.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  E.map_nodes = B->d_maps;
+  for (int a = 0; a <= D; ++a) E.map_axis[a] = B->d_maps + map_off[a];
+  const size_t isz = B->precision == DOT_FP64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
+  HIP_OK(hipMalloc(&B->d_inst, isz * count));
+  E.d_inst = B->d_inst;
+  E.prof = &B->prof;
+  HIP_OK(hipHostMalloc((void**)&B->host_ctl, B->ctl_stride * count, hipHostMallocDefault));
+  *out = B.release();
+  return DOT_OK;
+}
+
+size_t dot_batch_workspace_bytes(const dot_batch* B) { return B ? B->ws_bytes : 0; }
+
+int32_t dot_batch_size(const dot_batch* B) { return B ? (int32_t)B->plans.size() : 0; }
+
+int dot_batch_reset(dot_batch* B, void* ws, void* stream) {
+  if (!B || !ws) return fail(DOT_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const int count = (int)B->plans.size();
+  for (int i = 0; i < count; ++i) {
+    dot_plan* P = B->plans[i];
+    HIP_OK(hipMemsetAsync(static_cast<char*>(ws) + B->state_off[i], 0, P->ctl_offset, st));
+    *reinterpret_cast<Ctl*>(reinterpret_cast<char*>(B->host_ctl) + (size_t)i * B->ctl_stride) = initial_ctl(P);
+  }
+  HIP_OK(hipMemcpyAsync(ws, B->host_ctl, B->ctl_stride * count, hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  B->it = 0;
+  return DOT_OK;
+}
+
+int dot_batch_run(dot_batch* B, void* ws, int32_t max_iters, void* stream, dot_result* results) {
+  if (!B || !ws || max_iters < 0) return fail(DOT_EINVAL, "bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  int done = 0;
+  int rc = dispatch<BatchRunF>(B->precision, B->D, B, ws, (int)max_iters, st, &done);
+  if (rc) return rc;
+  B->it += done;
+  if (results)
+    for (size_t i = 0; i < B->plans.size(); ++i)
+      fill_result(*reinterpret_cast<const Ctl*>(reinterpret_cast<char*>(B->host_ctl) + i * B->ctl_stride),
+                  &results[i]);
+  return DOT_OK;
+}
+
+int dot_batch_extract(dot_batch* B, const void* ws, int32_t index, double* rho_out, double* m_out, void* stream) {
+  if (!B || !ws || index < 0 || index >= (int)B->plans.size()) return fail(DOT_EINVAL, "bad argument");
+  return extract_impl(B->plans[index], static_cast<const char*>(ws) + B->state_off[index], rho_out, m_out,
+                      (hipStream_t)stream);
+}
+
+int dot_batch_profile_select(dot_batch* B, int32_t kernel_class) {
+  if (!B || kernel_class < -1 || kernel_class > DOT_K_FINAL) return fail(DOT_EINVAL, "bad kernel class");
+  B->prof.cls = kernel_class;
+  B->prof.used = 0;
+  B->prof.ms = 0.0;
+  B->prof.launches = 0;
+  return DOT_OK;
+}
+
+int dot_batch_profile_read(dot_batch* B, double* total_ms, int64_t* launches) {
+  if (!B) return fail(DOT_EINVAL, "null batch");
+  if (total_ms) *total_ms = B->prof.ms;
+  if (launches) *launches = B->prof.launches;
+  B->prof.ms = 0.0;
+  B->prof.launches = 0;
+  return DOT_OK;
 }
 
 }  // extern "C"

@@ -271,17 +271,16 @@ struct PassArgs {
 // occur on the time axis only (first forward / last inverse pass). KIND =
 // kFwdScaleInv (last axis only) applies forward, 1/Lambda, inverse.
 template <typename T, int D, int KIND, int SRC, int DST>
-__global__ void __launch_bounds__(kMaxWaves * 64)
-k_axis_pass(Geo g, PassArgs pa, AxisTab<T> a, T* __restrict__ plane,
-            const T* __restrict__ q, const T* __restrict__ al, double* __restrict__ phi,
-            const double* __restrict__ c_lo, const double* __restrict__ c_hi,
-            const T* __restrict__ lam_other, const T* __restrict__ lam_last,
-            const Ctl* __restrict__ ctl, double sigma_arg) {
+__device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa, const AxisTab<T>& a,
+                                               T* __restrict__ plane, const T* __restrict__ q,
+                                               const T* __restrict__ al, double* __restrict__ phi,
+                                               const double* __restrict__ c_lo, const double* __restrict__ c_hi,
+                                               const T* __restrict__ lam_other, const T* __restrict__ lam_last,
+                                               const Ctl* __restrict__ ctl, double sigma_arg, int64_t blk) {
   extern __shared__ unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
-  if (ctl && ctl->stop) return;
   const int L = a.L;
-  const int64_t c0 = (int64_t)blockIdx.x * kCW;
+  const int64_t c0 = blk * kCW;
   const int64_t inner = pa.inner;
   const int64_t ncols = pa.ncols;
   double inv_sigma = 0.0;

@@ -85,13 +85,12 @@ __device__ __forceinline__ void soc_project(double (&y)[K]) {
 // the weighted components sqrt(omega/2) w_{d,v} go to W for the q_d update.
 // ---------------------------------------------------------------------------
 template <typename T, int D>
-__global__ void __launch_bounds__(256)
-k_cone_q0(Geo g, const double* __restrict__ phi, const T* __restrict__ q, T* __restrict__ alpha,
-          const T* __restrict__ beta, const double* __restrict__ sw_sp, T* __restrict__ qn,
-          T* __restrict__ W, const Ctl* __restrict__ ctl) {
-  if (ctl->stop) return;
+__device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restrict__ phi, const T* __restrict__ q,
+                                             T* __restrict__ alpha, const T* __restrict__ beta,
+                                             const double* __restrict__ sw_sp, T* __restrict__ qn, T* __restrict__ W,
+                                             const Ctl* __restrict__ ctl, int64_t blk) {
   constexpr int K = 4 * D + 2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blk * blockDim.x + threadIdx.x;
   const int64_t ncell = (int64_t)g.n[0] * g.stride[0];
   if (i >= ncell) return;
   const double sigma = ctl->sigma, tau = ctl->tau, inv_sigma = 1.0 / sigma;
@@ -122,11 +121,10 @@ k_cone_q0(Geo g, const double* __restrict__ phi, const T* __restrict__ q, T* __r
 // adjacent cells' weighted w components; diagonal 1 + 1/2 sum of omega over
 // the adjacent cells (Prop. 3.2 with weights); alpha_d update.
 template <typename T, int D>
-__global__ void __launch_bounds__(256)
-k_qd(Geo g, const double* __restrict__ phi, T* __restrict__ alpha, const double* __restrict__ om_sp,
-     T* __restrict__ qn, const T* __restrict__ W, const Ctl* __restrict__ ctl) {
-  if (ctl->stop) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__ phi, T* __restrict__ alpha,
+                                        const double* __restrict__ om_sp, T* __restrict__ qn, const T* __restrict__ W,
+                                        const Ctl* __restrict__ ctl, int64_t blk) {
+  const int64_t i = blk * blockDim.x + threadIdx.x;
   if (i >= g.nb) return;
   const double sigma = ctl->sigma, tau = ctl->tau, inv_sigma = 1.0 / sigma;
   int x[kMaxAxes];
@@ -180,12 +178,12 @@ __device__ __forceinline__ void block_partials(double (&s)[NS], double* __restri
 // beta += tau sigma (z - B F q_new - d); at residual checks the block sums of
 // |z - B F q_new - d|^2 go to partials slot 11. Block 0 counts the iteration.
 template <typename T, int D>
-__global__ void __launch_bounds__(256)
-k_beta(Geo g, const T* __restrict__ q, const T* __restrict__ qn, T* __restrict__ beta,
-       const double* __restrict__ sw_sp, Ctl* __restrict__ ctl, double* __restrict__ partials, int check) {
-  if (ctl->stop) return;
+__device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q, const T* __restrict__ qn,
+                                          T* __restrict__ beta, const double* __restrict__ sw_sp,
+                                          Ctl* __restrict__ ctl, double* __restrict__ partials, int check,
+                                          int64_t blk) {
   constexpr int K = 4 * D + 2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blk * blockDim.x + threadIdx.x;
   const int64_t ncell = (int64_t)g.n[0] * g.stride[0];
   const double sigma = ctl->sigma, tau = ctl->tau, inv_sigma = 1.0 / sigma;
   double ssq = 0.0;
@@ -232,10 +230,10 @@ k_beta(Geo g, const T* __restrict__ q, const T* __restrict__ qn, T* __restrict__
     if (threadIdx.x == 0) {
       double tot = 0.0;
       for (int j = 0; j < nw; ++j) tot += red1[j];
-      partials[(int64_t)blockIdx.x * kNumSums + 11] = tot;
+      partials[blk * kNumSums + 11] = tot;
     }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->iter += 1;
+  if (blk == 0 && threadIdx.x == 0) ctl->iter += 1;
 }
 
 // Partial sums for the residuals of Sec. 5.3 at (phi, q, alpha, beta), one
@@ -245,17 +243,16 @@ k_beta(Geo g, const T* __restrict__ q, const T* __restrict__ qn, T* __restrict__
 // 13 |F^*B^*beta + alpha|^2, 14 |F^*B^*beta|^2, 15 |alpha|^2, 16 <c, phi>,
 // 17 sum m^2 / r over r > 0. (4, 11, 12 are filled elsewhere.)
 template <typename T, int D>
-__global__ void __launch_bounds__(256)
-k_resid(Geo g, const double* __restrict__ phi, const T* __restrict__ q, const T* __restrict__ alpha,
-        const T* __restrict__ beta, const double* __restrict__ om_sp, const double* __restrict__ sw_sp,
-        const double* __restrict__ c_lo, const double* __restrict__ c_hi, const Ctl* __restrict__ ctl,
-        double* __restrict__ partials) {
-  if (ctl && ctl->stop) return;
+__device__ __forceinline__ void resid_body(const Geo& g, const double* __restrict__ phi, const T* __restrict__ q,
+                                           const T* __restrict__ alpha, const T* __restrict__ beta,
+                                           const double* __restrict__ om_sp, const double* __restrict__ sw_sp,
+                                           const double* __restrict__ c_lo, const double* __restrict__ c_hi,
+                                           double* __restrict__ partials, int64_t blk) {
   constexpr int K = 4 * D + 2;
   double s[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) s[k] = 0.0;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blk * blockDim.x + threadIdx.x;
   if (i < g.nb) {
     int x[kMaxAxes];
     node_coords<D>(g, i, x);
@@ -345,7 +342,7 @@ k_resid(Geo g, const double* __restrict__ phi, const T* __restrict__ q, const T*
       if (r > 0.0) s[17] += ad * ad / r;
     }
   }
-  block_partials<kNumSums>(s, partials + (int64_t)blockIdx.x * kNumSums, 11);
+  block_partials<kNumSums>(s, partials + blk * kNumSums, 11);
 }
 
 // Scalars the finalize step needs besides the partials.
@@ -361,10 +358,10 @@ __device__ __forceinline__ double eta_ratio(double num2, double a2, double b2, d
 }
 
 // Sums the block partials in a fixed order, forms the residuals, applies the
-// sigma rule of Sec. 5.3 on its schedule and sets the stop flag. One block.
-__global__ void __launch_bounds__(1024)
-k_finalize(FinArgs fa, const double* __restrict__ partials, Ctl* __restrict__ ctl, int update_ctl) {
-  if (update_ctl && ctl->stop) return;
+// sigma rule of Sec. 5.3 on its schedule and sets the stop flag. One block
+// per instance.
+__device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* __restrict__ partials,
+                                              Ctl* __restrict__ ctl, int update_ctl) {
   __shared__ double acc[1024 / 64][kNumSums];
   __shared__ double tot[kNumSums];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -433,11 +430,11 @@ k_finalize(FinArgs fa, const double* __restrict__ partials, Ctl* __restrict__ ct
 // ---- standalone step kernels (step-level entry points) --------------------
 
 template <typename T, int D>
-__global__ void __launch_bounds__(256)
-k_cone_out(Geo g, const T* __restrict__ q, const T* __restrict__ beta, const double* __restrict__ sw_sp,
-           double inv_sigma, T* __restrict__ z) {
+__device__ __forceinline__ void cone_out_body(const Geo& g, const T* __restrict__ q, const T* __restrict__ beta,
+                                              const double* __restrict__ sw_sp, double inv_sigma, T* __restrict__ z,
+                                              int64_t blk) {
   constexpr int K = 4 * D + 2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blk * blockDim.x + threadIdx.x;
   if (i >= g.nb) return;
   const int64_t nb = g.nb;
   if (i >= (int64_t)g.n[0] * g.stride[0]) {
@@ -456,11 +453,11 @@ k_cone_out(Geo g, const T* __restrict__ q, const T* __restrict__ beta, const dou
 
 // |z - B F q - d|^2 block sums into partials slot 11 (z given).
 template <typename T, int D>
-__global__ void __launch_bounds__(256)
-k_zres(Geo g, const T* __restrict__ z, const T* __restrict__ q, const double* __restrict__ sw_sp,
-       double* __restrict__ partials) {
+__device__ __forceinline__ void zres_body(const Geo& g, const T* __restrict__ z, const T* __restrict__ q,
+                                          const double* __restrict__ sw_sp, double* __restrict__ partials,
+                                          int64_t blk) {
   constexpr int K = 4 * D + 2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t i = blk * blockDim.x + threadIdx.x;
   double ssq = 0.0;
   if (i < (int64_t)g.n[0] * g.stride[0]) {
     int x[kMaxAxes];
@@ -497,7 +494,7 @@ k_zres(Geo g, const T* __restrict__ z, const T* __restrict__ q, const double* __
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int j = 0; j < nw; ++j) tot += red1[j];
-    partials[(int64_t)blockIdx.x * kNumSums + 11] = tot;
+    partials[blk * kNumSums + 11] = tot;
   }
 }
 

@@ -1,0 +1,86 @@
+"""Batches: heterogeneous instances in one launch per kernel give bitwise the
+same iterates as each instance solved alone, stop independently, and match
+the oracle."""
+import numpy as np
+import pytest
+
+import dotgen
+from oracle import dot_oracle as O
+from paper_2505_05424_amd import binding as B
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _insts():
+    out = [dotgen.tiny_instance(2, (8, 20, 24), seed=41, floor=0.0, masked=True),
+           dotgen.tiny_instance(2, (12, 70, 45), seed=42, floor=0.0, n_comp=3),
+           dotgen.tiny_instance(2, (3, 9, 5), seed=43, floor=0.02),
+           dotgen.tiny_instance(2, (16, 33, 17), seed=44, floor=0.0, masked=True)]
+    out += dotgen.config4_instances(4, seed=4100)
+    return out
+
+
+def _alone(inst, iters, prec, **kw):
+    plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=prec, **kw)
+    s = G.GpuState(plan)
+    s.reset()
+    r = s.run(iters)
+    rho, m = s.extract()
+    return r, rho, m
+
+
+def _torch_ws(nbytes):
+    torch = G.torch_mod()
+    return torch.zeros(int(nbytes), dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
+def test_batch_equals_each_instance_alone(prec):
+    insts = _insts()
+    print(f"[case] batch of {len(insts)} precision={prec}", flush=True)
+    batch = B.dot_batch_create(insts, tol=-1.0, max_iter=100000, precision=prec)
+    ws = _torch_ws(batch.workspace_bytes)
+    st = G.stream_handle()
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    iters = 60
+    res = B.dot_batch_run(batch, ws.data_ptr(), iters, st)
+    for i, inst in enumerate(insts):
+        r, rho, m = _alone(inst, iters, prec, tol=-1.0, max_iter=100000)
+        rb, mb = B.dot_batch_extract(batch, ws.data_ptr(), i, st)
+        assert res[i].iters == r.iters == iters
+        assert res[i].objective == r.objective, (i, res[i].objective, r.objective)
+        assert res[i].eta_dot == r.eta_dot
+        assert np.array_equal(rb, rho)
+        for a, b in zip(mb, m):
+            assert np.array_equal(a, b)
+
+
+def test_batch_instances_stop_independently_and_match_oracle():
+    insts = [dotgen.tiny_instance(2, (6, 10, 12), seed=51, floor=0.05),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=52, floor=0.0, masked=True),
+             dotgen.tiny_instance(2, (4, 7, 9), seed=53, floor=0.02)]
+    tol = 1e-7
+    batch = B.dot_batch_create(insts, tol=tol, max_iter=100000)
+    ws = _torch_ws(batch.workspace_bytes)
+    st = G.stream_handle()
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    res = B.dot_batch_run(batch, ws.data_ptr(), 30000, st)
+    iters = [r.iters for r in res]
+    assert len(set(iters)) > 1  # different stopping points
+    for i, inst in enumerate(insts):
+        assert B.TERM_NAMES[res[i].term] == "converged"
+        r, rho, _ = _alone(inst, 30000, B.DOT_FP64, tol=tol, max_iter=100000)
+        assert res[i].iters == r.iters
+        assert res[i].objective == r.objective
+        P = O.make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask)
+        ref = O.solve(P, tol=tol, max_iter=30000)
+        assert abs(res[i].objective - ref.objective) <= 1e-8 * ref.objective
+        assert abs(res[i].iters - ref.iters) <= 5
+
+
+def test_batch_rejects_mixed_dimensions():
+    a = dotgen.tiny_instance(2, (3, 4, 4), seed=1)
+    b = dotgen.tiny_instance(1, (3, 4), seed=2)
+    with pytest.raises(B.DotError):
+        B.dot_batch_create([a, b])
