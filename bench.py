@@ -31,6 +31,11 @@ from paper_2505_05424_amd import perfmodel as PM  # noqa: E402
 
 TOL = 1e-6
 MAX_ITER = 100000
+BATCH_MAX_ITER = 40000  # cap per instance in the batched section
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_model():
@@ -76,13 +81,120 @@ def cpu_baseline(inst, iters_per_solve, budget_s=15.0):
     }
 
 
+def solve_plain(plan, ptr, st, cap=MAX_ITER):
+    B.dot_state_reset(plan, ptr, st)
+    return B.dot_run(plan, ptr, cap, st)
+
+
+def time_solves(plan, ptr, st, k, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [solve_plain(plan, ptr, st) for _ in range(k)]
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, res
+
+
+def kernel_breakdown(plan, ptr, st):
+    """Per-class event times over one solve (graphs are off while timing)."""
+    out = {}
+    for name, cls in B.KERNEL_CLASSES.items():
+        B.dot_profile_select(plan, cls)
+        solve_plain(plan, ptr, st)
+        ms, cnt = B.dot_profile_read(plan)
+        if cnt:
+            out[name] = {"ms_total": ms, "launches": cnt, "us_per_launch": 1e3 * ms / cnt}
+    B.dot_profile_select(plan, -1)
+    return out
+
+
+def batched_section(torch, st, count, sample, seed=4000):
+    """Config-4-like batch: `count` instances (grid sides from {32..128}, n0
+    from {16, 32, 64}, half masked), mixed precision, one launch per kernel
+    for all instances, to eta_dot <= 1e-6; plus `sample` of the same
+    instances solved one at a time in FP64 and in mixed precision."""
+    insts = dotgen.config4_instances(count, seed=seed)
+    batch = B.dot_batch_create(insts, tol=TOL, max_iter=BATCH_MAX_ITER, precision=B.DOT_MIXED)
+    ws = torch.zeros(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    log(f"batched: {count} instances, workspace {batch.workspace_bytes / 2**30:.2f} GiB")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < BATCH_MAX_ITER:
+        res = B.dot_batch_run(batch, ws.data_ptr(), 5000, st)
+        done += 5000
+        conv = sum(1 for r in res if B.TERM_NAMES[r.term] == "converged")
+        log(f"batched: {done} iterations, {conv}/{count} converged, {time.perf_counter() - t0:.1f} s")
+        if conv == count:
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    conv = sum(1 for r in res if B.TERM_NAMES[r.term] == "converged")
+    inst_iters = sum(r.iters for r in res)
+    nodes = sum(int(np.prod([k + 1 for k in i.n])) for i in insts)
+    # dominant kernel of the batch, timed with events in a second run
+    log("batched: beta-kernel timing")
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    B.dot_batch_profile_select(batch, B.KERNEL_CLASSES["beta"])
+    B.dot_batch_run(batch, ws.data_ptr(), 400, st)
+    ms, cnt = B.dot_batch_profile_read(batch)
+    B.dot_batch_profile_select(batch, -1)
+    kb = sum(PM.kernel_bytes(i.D, i.n, 4)["beta"] for i in insts)
+    avg_us = 1e3 * ms / max(cnt, 1)
+    out = {
+        "workload": f"{count} 2D instances, sides {{32,48,64,96,128}}, n0 {{16,32,64}}, half masked, mixed precision",
+        "instances": count,
+        "converged": conv,
+        "seconds": el,
+        "solves_per_s": conv / el,
+        "instance_iters_per_s": inst_iters / el,
+        "max_iters": max(r.iters for r in res),
+        "iteration_cap": BATCH_MAX_ITER,
+        "mean_iters": inst_iters / count,
+        "nodes_total": nodes,
+        "beta_kernel": {"avg_launch_us_first_400_iters": avg_us, "algorithmic_bytes": kb,
+                        "achieved_GBs": kb / (avg_us * 1e-6) / 1e9,
+                        "frac_of_hbm_peak": kb / (avg_us * 1e-6) / 1e9 / PM.HBM_PEAK_GBS},
+    }
+    plain = {}
+    for prec, label in ((B.DOT_FP64, "fp64"), (B.DOT_MIXED, "mixed")):
+        t_tot, its = 0.0, 0
+        for inst in insts[:sample]:
+            log(f"plain {label}: {inst.label}")
+            plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=TOL,
+                                     max_iter=BATCH_MAX_ITER, precision=prec)
+            buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+            el1, r = time_solves(plan, buf.data_ptr(), st, 1, torch)
+            t_tot += el1
+            its += r[0].iters
+            plan.close()
+        plain[label] = {"instances": sample, "seconds": t_tot, "solves_per_s": sample / t_tot,
+                        "iters_per_s": its / t_tot}
+    out["plain_one_at_a_time_sample"] = plain
+    # the same sample inside a batch of its own, for a like-for-like ratio
+    log("batched sample")
+    sub = B.dot_batch_create(insts[:sample], tol=TOL, max_iter=BATCH_MAX_ITER, precision=B.DOT_MIXED)
+    ws2 = torch.zeros(sub.workspace_bytes, dtype=torch.uint8, device="cuda")
+    B.dot_batch_reset(sub, ws2.data_ptr(), st)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r2 = B.dot_batch_run(sub, ws2.data_ptr(), BATCH_MAX_ITER, st)
+    torch.cuda.synchronize()
+    el2 = time.perf_counter() - t0
+    out["batched_sample"] = {"instances": sample, "seconds": el2, "solves_per_s": sample / el2}
+    out["speedup_batched_mixed_vs_plain_fp64_same_sample"] = (sample / el2) / plain["fp64"]["solves_per_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--batch", type=int, default=64, help="instances of the batched section (0: skip)")
+    ap.add_argument("--plain-sample", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -97,53 +209,37 @@ def main():
     inst = dotgen.config2_instance()
     D, n = inst.D, inst.n
     plan = B.dot_plan_create(D, n, inst.rho0, inst.rho1, inst.mask, tol=TOL, max_iter=MAX_ITER)
-    info = plan.info
-    w = int(info.scalar_bytes)
-    state = torch.zeros(int(info.state_bytes), dtype=torch.uint8, device="cuda")
+    w = int(plan.info.scalar_bytes)
+    state = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
     ptr = state.data_ptr()
 
-    def solve():
-        B.dot_state_reset(plan, ptr, st)
-        return B.dot_run(plan, ptr, MAX_ITER, st)
-
-    # untimed pre-pass: per-class kernel time over one solve, to name the dominant kernel
-    kb = PM.kernel_bytes(D, n, w)
-    breakdown = {}
-    for name, cls in B.KERNEL_CLASSES.items():
-        B.dot_profile_select(plan, cls)
-        solve()
-        ms, cnt = B.dot_profile_read(plan)
-        if cnt:
-            breakdown[name] = {"ms_total": ms, "launches": cnt, "us_per_launch": 1e3 * ms / cnt}
-    B.dot_profile_select(plan, -1)
-    dominant = max(breakdown, key=lambda k: breakdown[k]["ms_total"])
-
+    log("warmup")
     for _ in range(args.warmup):
-        solve()
+        solve_plain(plan, ptr, st)
+    log("timed solves")
 
-    # timed region: K complete solves, events around the dominant kernel
-    B.dot_profile_select(plan, B.KERNEL_CLASSES[dominant])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = [solve() for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dom_ms, dom_cnt = B.dot_profile_read(plan)
-    B.dot_profile_select(plan, -1)
-
-    el = t1 - t0
+    # timed region: K complete solves, graphs on, no events
+    el, results = time_solves(plan, ptr, st, args.steps, torch)
     iters = [r.iters for r in results]
     assert all(B.TERM_NAMES[r.term] == "converged" for r in results), [r.term for r in results]
     last = results[-1]
-    solves_per_s = args.steps / el
+
+    # roofline: the same solves again with events around the dominant kernel
+    log("kernel breakdown")
+    breakdown = kernel_breakdown(plan, ptr, st)
+    dominant = max(breakdown, key=lambda k: breakdown[k]["ms_total"])
+    B.dot_profile_select(plan, B.KERNEL_CLASSES[dominant])
+    el_ev, _ = time_solves(plan, ptr, st, args.steps, torch)
+    dom_ms, dom_cnt = B.dot_profile_read(plan)
+    B.dot_profile_select(plan, -1)
+    kb = PM.kernel_bytes(D, n, w)
     avg_us = 1e3 * dom_ms / max(dom_cnt, 1)
     achieved = kb[dominant] / (avg_us * 1e-6) / 1e9
     it_min = PM.iteration_min_bytes(D, n, w)
-    iter_s = sum(iters) / el
 
     out = {
         "metric": "solves/s at KKT residual 1e-6 (plain FP64, one instance)",
-        "value": solves_per_s,
+        "value": args.steps / el,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -155,8 +251,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"2d-{n[0]}x{n[1]}x{n[2]}-gaussmix3-fp64", "D": D, "n": list(n),
-                   "tol": TOL, "precision": "fp64", "instances": 1, "parallelism": "single instance"},
-        "palm_iters_per_s": iter_s,
+                   "tol": TOL, "precision": "fp64", "instances": 1, "hip_graphs": True},
+        "palm_iters_per_s": sum(iters) / el,
         "iters_per_solve": iters[0],
         "eta_dot": last.eta_dot,
         "objective": last.objective,
@@ -172,6 +268,8 @@ def main():
             "algorithmic_bytes_per_launch": kb[dominant],
             "avg_launch_us": avg_us,
             "launches": dom_cnt,
+            "timed_region": f"{args.steps} further solves of the same instance with HIP events around every "
+                            f"launch of this kernel on the solver's stream (graphs off), {el_ev:.2f} s",
         },
         "iteration": {
             "us_per_iter": 1e6 * el / sum(iters),
@@ -180,7 +278,10 @@ def main():
         },
         "kernel_breakdown_one_solve": breakdown,
     }
+    if args.batch > 0:
+        out["batched"] = batched_section(torch, st, args.batch, args.plain_sample)
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(inst, iters[0], args.cpu_budget)
     print(json.dumps(out))
 

@@ -83,7 +83,7 @@ typedef struct {
   int32_t max_iter;       /* iteration cap (> 0) */
   int32_t precision;      /* dot_precision */
   double tau;             /* dual step in (0, 2); 0 selects 1.9 */
-  double sigma0;          /* initial penalty; 0 selects 1.0 */
+  double sigma0;          /* initial penalty; 0 selects 30 */
   int32_t check_every;    /* residual-check cadence; 0 selects 5 */
   int32_t adapt_sigma;    /* 1: sigma rule of Sec. 5.3 on the growing schedule */
   int32_t sigma_gap0;     /* first sigma decision after this many iterations; 0 selects 10 */
@@ -216,6 +216,12 @@ int dot_batch_extract(dot_batch* batch, const void* workspace, int32_t index, do
                       void* stream);
 int dot_batch_profile_select(dot_batch* batch, int32_t kernel_class);
 int dot_batch_profile_read(dot_batch* batch, double* total_ms, int64_t* launches);
+
+/* Replay captured HIP graphs of 10 iterations inside dot_run / dot_batch_run
+ * (default on; off runs the same launches one by one; results are bitwise
+ * identical). Graphs are not used while a kernel class is being timed. */
+int dot_plan_set_graphs(dot_plan* plan, int32_t enable);
+int dot_batch_set_graphs(dot_batch* batch, int32_t enable);
 
 /* One-shot, blocking: allocate, solve, copy rho/m out (either may be NULL),
  * free. rho_out: n0*prod(n_d+1); m_out: sum_d |G^s_d| doubles. */

@@ -19,7 +19,8 @@ time node t and at the staggered point s+1/2 on axis d.
 Readings of points the paper leaves open (each is a parameter here):
   * data scaling: c~ = c/(h0 h1...hD), so alpha0 and alpha_bar come out as
     density and momentum density; objective = -(h0...hD) <c~, phi>.
-  * sigma0 = 1, tau = 1.9, zero initial point; residuals checked every 5
+  * sigma0 = 30 (the penalty acts on data scaled to density units), tau = 1.9,
+    zero initial point; residuals checked every 5
     iterations (after iterations 5, 10, 15, ...); sigma reconsidered only at
     the checks listed by sigma_update_points (gaps 10, 15, 20, 25, 35, ...
     growing by about 1.2x), since changing sigma at every check stalls the
@@ -384,7 +385,7 @@ class State:
     k: int = 0  # iterations done
 
 
-def zero_state(P: Problem, sigma0=1.0) -> State:
+def zero_state(P: Problem, sigma0=30.0) -> State:
     g = P.g
     q = [np.zeros(g.cell_shape)] + [np.zeros(g.q_shape(d)) for d in range(1, g.D + 1)]
     alpha = [np.zeros_like(a) for a in q]
@@ -463,7 +464,7 @@ class SolveResult:
     seconds: float
 
 
-def solve(P: Problem, tol=1e-6, max_iter=10000, tau=1.9, sigma0=1.0, check_every=5,
+def solve(P: Problem, tol=1e-6, max_iter=10000, tau=1.9, sigma0=30.0, check_every=5,
           adapt_sigma=True, state: Optional[State] = None, on_check=None,
           sigma_gap0=10, sigma_growth=1.2) -> SolveResult:
     """Run Algorithm 2 from zero (or `state`), checking eta_dot and adapting
@@ -500,7 +501,7 @@ def solve(P: Problem, tol=1e-6, max_iter=10000, tau=1.9, sigma0=1.0, check_every
                        dual_objective(P, S.alpha), hist, secs)
 
 
-def run_fixed(P: Problem, iters, tau=1.9, sigma0=1.0, check_every=5, adapt_sigma=True,
+def run_fixed(P: Problem, iters, tau=1.9, sigma0=30.0, check_every=5, adapt_sigma=True,
               sigma_gap0=10, sigma_growth=1.2) -> SolveResult:
     """Exactly `iters` iterations with the same check/sigma schedule and no stop."""
     return solve(P, tol=-1.0, max_iter=iters, tau=tau, sigma0=sigma0, check_every=check_every,

@@ -28,6 +28,7 @@ EXPORTED = [
     "dot_step_update", "dot_step_residuals", "dot_profile_select", "dot_profile_read", "dot_solve",
     "dot_batch_create", "dot_batch_destroy", "dot_batch_workspace_bytes", "dot_batch_size", "dot_batch_reset",
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
+    "dot_plan_set_graphs", "dot_batch_set_graphs",
 ]
 
 KERNEL_CLASSES = {"dct_first": 0, "dct_mid": 1, "dct_last": 2, "dct_inv": 3, "cone": 4, "qd": 5,
@@ -143,6 +144,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_batch_run.argtypes = [vp, vp, i32, vp, ctypes.POINTER(dot_result)]
     lib.dot_batch_extract.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(ctypes.c_double), vp]
+    lib.dot_plan_set_graphs.argtypes = [vp, i32]
+    lib.dot_batch_set_graphs.argtypes = [vp, i32]
     lib.dot_batch_profile_select.argtypes = [vp, i32]
     lib.dot_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
@@ -294,6 +297,14 @@ def dot_step_residuals(plan, phi_ptr, z_ptr, q_ptr, alpha_ptr, beta_ptr, stream=
                                      ctypes.c_void_p(q_ptr), ctypes.c_void_p(alpha_ptr), ctypes.c_void_p(beta_ptr),
                                      ctypes.byref(r), ctypes.c_void_p(stream)))
     return r
+
+
+def dot_plan_set_graphs(plan, enable: bool):
+    _check(load().dot_plan_set_graphs(plan.handle, int(bool(enable))))
+
+
+def dot_batch_set_graphs(batch, enable: bool):
+    _check(load().dot_batch_set_graphs(batch.handle, int(bool(enable))))
 
 
 def dot_profile_select(plan, kernel_class: int):

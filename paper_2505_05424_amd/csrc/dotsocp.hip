@@ -96,6 +96,23 @@ struct ProfScope {
   }
 };
 
+// A captured block of kGraphIters iterations starting at a multiple of 10
+// (the parity of q and the positions of the residual checks repeat with
+// period 10, so one graph serves every such block). Capture happens only
+// after plain launches have run once (one-time kernel attribute calls stay
+// outside any capture).
+constexpr int kGraphIters = 10;
+struct GraphCache {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap = nullptr;  // private capture stream (default priority)
+  bool enabled = true;
+  bool warm = false;
+  ~GraphCache() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
 }  // namespace
 
 struct dot_plan {
@@ -104,7 +121,7 @@ struct dot_plan {
   int scalar_bytes = 8;
   int D = 0, K = 0;
   int n[4] = {0, 0, 0, 0};
-  double tau = 1.9, sigma0 = 1.0, tol = 1e-6;
+  double tau = 1.9, sigma0 = 30.0, tol = 1e-6;
   int max_iter = 1000, cadence = 5, adapt = 1, gap0 = 10;
   double growth = 1.2;
   double vol = 1.0, c_norm2 = 0.0, d_norm2 = 0.0;
@@ -134,6 +151,7 @@ struct dot_plan {
   size_t ctl_offset = 0, partials_offset = 0, state_bytes = 0;
   int device = 0;
   Prof prof;
+  GraphCache graphs;
 };
 
 namespace {
@@ -338,6 +356,7 @@ struct Exec {
   int waves_axis[kMaxAxes] = {0, 0, 0, 0};
   Prof* prof = nullptr;
   int device = 0;
+  struct GraphCache* graphs = nullptr;  // captured 10-iteration blocks (nullptr: plain launches)
 };
 
 template <typename T, int D, int KIND, int SRC, int DST>
@@ -433,6 +452,49 @@ int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
 // at stride ctl_stride) is refreshed from ctl_dev every `poll` iterations and
 // the loop ends once every instance has stopped.
 template <typename T, int D>
+int one_iter(const Exec& E, int it, hipStream_t st) {
+  const int par = it & 1;
+  int rc;
+  if ((rc = poisson_iter<T, D>(E, par, st))) return rc;
+  const int check = ((it + 1) % E.cadence) == 0;
+  if ((rc = update_iter<T, D>(E, par, check, st))) return rc;
+  if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
+  return DOT_OK;
+}
+
+// Capture kGraphIters iterations starting at an iteration count it (it % 10
+// == 0 keeps the check positions aligned) into a graph, on the cache's own
+// stream (the caller's stream may be the legacy default stream, which cannot
+// be captured); the graph is then launched on the caller's stream.
+template <typename T, int D>
+int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
+  Exec Ec = E;
+  Ec.prof = nullptr;  // no events inside a captured graph
+  if (!E.graphs->cap) HIP_OK(hipStreamCreateWithFlags(&E.graphs->cap, hipStreamNonBlocking));
+  hipStream_t st = E.graphs->cap;
+  hipGraph_t graph = nullptr;
+  HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  int rc = DOT_OK;
+  for (int k = 0; k < kGraphIters && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st);
+  hipError_t e = hipStreamEndCapture(st, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(DOT_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(DOT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  return DOT_OK;
+}
+
+// Run up to max_iters iterations of every instance of E in lockstep starting
+// at iteration it0 (same for all instances); ctl_host (pinned, ninst entries
+// at stride ctl_stride) is refreshed from ctl_dev every `poll` iterations and
+// the loop ends once every instance has stopped. Whole blocks of 10
+// iterations that start at a multiple of 10 replay a captured graph when the
+// executor has a graph cache and no kernel class is being timed.
+template <typename T, int D>
 int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t ctl_stride, void* ctl_host,
               hipStream_t st, int* done_iters) {
   const int poll = 40;
@@ -441,17 +503,26 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
       if (!reinterpret_cast<const Ctl*>(static_cast<const char*>(ctl_host) + i * ctl_stride)->stop) return false;
     return true;
   };
+  const bool graphs = E.graphs && E.graphs->enabled && !(E.prof && E.prof->cls >= 0) && E.cadence == 5;
   int j = 0;
+  int since_poll = 0;
   while (j < max_iters) {
     const int it = it0 + j;
-    const int par = it & 1;
     int rc;
-    if ((rc = poisson_iter<T, D>(E, par, st))) return rc;
-    const int check = ((it + 1) % E.cadence) == 0;
-    if ((rc = update_iter<T, D>(E, par, check, st))) return rc;
-    if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
-    ++j;
-    if (j % poll == 0 || j == max_iters) {
+    if (graphs && E.graphs->warm && it % kGraphIters == 0 && max_iters - j >= kGraphIters) {
+      hipGraphExec_t& ex = E.graphs->exec;
+      if (!ex && (rc = capture_block<T, D>(E, it, &ex))) return rc;
+      HIP_OK(hipGraphLaunch(ex, st));
+      j += kGraphIters;
+      since_poll += kGraphIters;
+    } else {
+      if ((rc = one_iter<T, D>(E, it, st))) return rc;
+      if (E.graphs) E.graphs->warm = true;
+      ++j;
+      ++since_poll;
+    }
+    if (since_poll >= poll || j == max_iters) {
+      since_poll = 0;
       HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * E.ninst, hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
       if (E.prof) E.prof->collect();
@@ -521,6 +592,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   }
   E.prof = &P->prof;
   E.device = P->device;
+  E.graphs = slot == 0 ? &P->graphs : nullptr;
   return E;
 }
 
@@ -712,6 +784,7 @@ struct dot_batch {
   Ctl* host_ctl = nullptr;     // pinned, one entry per instance at ctl_stride
   int it = 0;                  // iterations done (all instances in lockstep)
   Prof prof;
+  GraphCache graphs;
 };
 
 namespace {
@@ -784,7 +857,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   P->precision = p->precision;
   P->scalar_bytes = p->precision == DOT_FP64 ? 8 : 4;
   P->tau = p->tau > 0 ? p->tau : 1.9;
-  P->sigma0 = p->sigma0 > 0 ? p->sigma0 : 1.0;
+  P->sigma0 = p->sigma0 > 0 ? p->sigma0 : 30.0;
   P->tol = p->tol;
   P->max_iter = p->max_iter;
   P->cadence = p->check_every > 0 ? p->check_every : 5;
@@ -977,6 +1050,12 @@ int dot_profile_read(dot_plan* P, double* total_ms, int64_t* launches) {
   return DOT_OK;
 }
 
+int dot_plan_set_graphs(dot_plan* P, int32_t enable) {
+  if (!P) return fail(DOT_EINVAL, "null plan");
+  P->graphs.enabled = enable != 0;
+  return DOT_OK;
+}
+
 int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* res) {
   dot_plan* P = nullptr;
   int rc = dot_plan_create(p, &P);
@@ -1064,6 +1143,7 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
   HIP_OK(hipMalloc(&B->d_inst, isz * count));
   E.d_inst = B->d_inst;
   E.prof = &B->prof;
+  E.graphs = &B->graphs;
   HIP_OK(hipHostMalloc((void**)&B->host_ctl, B->ctl_stride * count, hipHostMallocDefault));
   *out = B.release();
   return DOT_OK;
@@ -1106,6 +1186,12 @@ int dot_batch_extract(dot_batch* B, const void* ws, int32_t index, double* rho_o
   if (!B || !ws || index < 0 || index >= (int)B->plans.size()) return fail(DOT_EINVAL, "bad argument");
   return extract_impl(B->plans[index], static_cast<const char*>(ws) + B->state_off[index], rho_out, m_out,
                       (hipStream_t)stream);
+}
+
+int dot_batch_set_graphs(dot_batch* B, int32_t enable) {
+  if (!B) return fail(DOT_EINVAL, "null batch");
+  B->graphs.enabled = enable != 0;
+  return DOT_OK;
 }
 
 int dot_batch_profile_select(dot_batch* B, int32_t kernel_class) {

@@ -207,3 +207,19 @@ def test_dot_solve_one_shot():
     assert B.TERM_NAMES[r.term] == "converged"
     assert abs(r.objective - ref.objective) <= 1e-6 * ref.objective
     assert np.max(np.abs(rho - ref.state.alpha[0])) < 1e-4
+
+
+@pytest.mark.parametrize("name,iters", [("2d-mask-8x20x24", 137), ("3d-6x9x10x7", 64)])
+def test_graph_replay_equals_plain_launches(name, iters):
+    """Captured 10-iteration graphs replayed many times, with host polls and
+    syncs between replays, give bitwise the iterates of plain launches."""
+    inst, P, plan = _setup(name)
+    states = []
+    for graphs in (False, True):
+        B.dot_plan_set_graphs(plan, graphs)
+        s = G.GpuState(plan)
+        s.reset()
+        s.run(33)
+        s.run(iters - 33)
+        states.append(s.raw().copy())
+    assert np.array_equal(states[0], states[1])
