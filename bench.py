@@ -186,6 +186,94 @@ def batched_section(torch, st, count, sample, seed=4000):
     return out
 
 
+def serving_section(torch, rate, seconds, drain_s, seed=5000):
+    """Serving stream: Poisson arrivals at `rate` requests/s for `seconds` of
+    2D solves (sides log-uniform in [32, 256], n0 from {16, 32, 64}, every
+    second one masked) and 10% 3D solves (32 x 64^3), mixed precision, tol
+    1e-6; continuous batching with admission by HBM footprint and backfill
+    (one context per D, each on its own thread and stream). Latency is
+    arrival -> result in host memory. Requests still running `drain_s` after
+    the last arrival are reported as unfinished (their latency is censored)."""
+    from paper_2505_05424_amd.serving import Server
+    rng = np.random.default_rng(seed)
+    t_arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 2) + 10))
+    t_arr = t_arr[t_arr < seconds]
+    log(f"serving: generating {len(t_arr)} requests (rate {rate:.3f}/s over {seconds:.0f} s)")
+    reqs = [dotgen.serving_request(i, seed=seed) for i in range(len(t_arr))]
+    srv = Server(precision=B.DOT_MIXED, budgets={2: 96 << 30, 3: 64 << 30}, slots={2: 160, 3: 32},
+                 step_iters=40, tol=TOL, max_iter=BATCH_MAX_ITER)
+    # warm-up: one small request per context (first launches, module loads)
+    warm = [srv.submit(dotgen.tiny_instance(2, (8, 16, 16), seed=1)),
+            srv.submit(dotgen.tiny_instance(3, (4, 8, 8, 8), seed=2))]
+    for w in warm:
+        w.done.wait(120)
+    srv.check()
+    lanes = {D: (ln.steps, ln.active_sum) for D, ln in srv.lanes.items()}
+    log("serving: arrivals start")
+    handles = []
+    t0 = time.perf_counter()
+    last_log = t0
+    for i, ta in enumerate(t_arr):
+        while True:
+            now = time.perf_counter()
+            if now - t0 >= ta:
+                break
+            time.sleep(min(0.01, ta - (now - t0)))
+        h = srv.submit(reqs[i])
+        h.t_arrival = t0 + ta  # scheduled arrival time
+        handles.append(h)
+        if now - last_log > 10:
+            last_log = now
+            log(f"serving: t={now - t0:.0f} s, submitted {len(handles)}, "
+                f"done {sum(x.done.is_set() for x in handles)}, in flight {srv.in_flight()}")
+        srv.check()
+    t_end_arr = time.perf_counter()
+    while time.perf_counter() - t_end_arr < drain_s and not all(h.done.is_set() for h in handles):
+        time.sleep(0.05)
+        now = time.perf_counter()
+        if now - last_log > 10:
+            last_log = now
+            log(f"serving: draining, t={now - t0:.0f} s, done {sum(x.done.is_set() for x in handles)} "
+                f"of {len(handles)}")
+    t_stop = time.perf_counter()
+    stats_lanes = {D: {"steps": ln.steps - lanes[D][0],
+                       "mean_active": (ln.active_sum - lanes[D][1]) / max(1, ln.steps - lanes[D][0])}
+                   for D, ln in srv.lanes.items()}
+    srv.abandon()
+    fin = [h for h in handles if h.done.is_set() and h.result is not None]
+    conv = [h for h in fin if B.TERM_NAMES[h.result.term] == "converged"]
+    lat = np.array([h.latency for h in fin]) if fin else np.zeros(1)
+    wall = (max(h.t_done for h in fin) if fin else t_stop) - t0
+    by_d = {}
+    for D in (2, 3):
+        hs = [h for h in fin if h.inst.D == D]
+        if hs:
+            ld = np.array([h.latency for h in hs])
+            by_d[f"{D}d"] = {"finished": len(hs), "p50_s": float(np.percentile(ld, 50)),
+                             "p99_s": float(np.percentile(ld, 99)),
+                             "mean_iters": float(np.mean([h.result.iters for h in hs]))}
+    return {
+        "workload": ("Poisson arrivals; 2D sides log-uniform in [32,256], n0 {16,32,64}, every second 2D "
+                     "request masked; 10% 3D 32x64^3; mixed precision; tol 1e-6"),
+        "rate_per_s": rate,
+        "arrival_window_s": seconds,
+        "submitted": len(handles),
+        "finished": len(fin),
+        "converged": len(conv),
+        "hit_iteration_cap": len(fin) - len(conv),
+        "unfinished_at_cutoff": len(handles) - len(fin),
+        "iteration_cap": BATCH_MAX_ITER,
+        "wall_s": wall,
+        "solves_per_s": len(conv) / wall,
+        "instance_iters_per_s": sum(h.result.iters for h in fin) / wall,
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "latency_note": "over finished requests; unfinished ones are censored (p99 is then a lower bound)",
+        "by_dimension": by_d,
+        "lanes": stats_lanes,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -195,6 +283,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched section (0: skip)")
     ap.add_argument("--plain-sample", type=int, default=4)
+    ap.add_argument("--serve-seconds", type=float, default=45.0, help="serving arrival window (0: skip)")
+    ap.add_argument("--serve-drain", type=float, default=60.0)
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="arrivals/s (0: 80%% of the batched section's solves/s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -280,6 +372,11 @@ def main():
     }
     if args.batch > 0:
         out["batched"] = batched_section(torch, st, args.batch, args.plain_sample)
+    if args.serve_seconds > 0:
+        rate = args.serve_rate
+        if rate <= 0:
+            rate = 0.8 * out["batched"]["solves_per_s"] if "batched" in out else 0.5
+        out["serving"] = serving_section(torch, rate, args.serve_seconds, args.serve_drain)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(inst, iters[0], args.cpu_budget)

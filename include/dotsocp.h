@@ -227,6 +227,48 @@ int dot_batch_set_graphs(dot_batch* batch, int32_t enable);
  * free. rho_out: n0*prod(n_d+1); m_out: sum_d |G^s_d| doubles. */
 int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* res);
 
+/* ---- serving: continuous batching under an HBM budget --------------------- */
+/* A serving context holds one device arena of hbm_budget_bytes and up to
+ * max_slots running instances of one D and precision. Requests queue in
+ * arrival order. dot_ctx_step admits queued requests while a slot and arena
+ * space exist (first fit; the queue head waits for space, later requests do
+ * not overtake it), runs `iters` iterations of every running instance (one
+ * launch per kernel over all of them, Algorithm 2 as in dot_batch_run), then
+ * retires every instance that converged, diverged or reached its max_iter:
+ * its rho / m and result are copied to host memory inside the context and its
+ * arena block and slot are freed for the next admissions. Admissions happen
+ * at multiples of 10 iterations of the context's counter, so each request
+ * follows exactly the iterates of a solve of that problem alone (dot_run with
+ * the same settings): same result fields, bitwise. Requests need the default
+ * check cadence (5) and a max_iter that is a multiple of 5. Not thread-safe:
+ * one context per host thread. */
+typedef struct dot_ctx dot_ctx;
+typedef enum { DOT_REQ_QUEUED = 0, DOT_REQ_RUNNING = 1, DOT_REQ_DONE = 2 } dot_req_status;
+/* Device bytes one instance of p's D, n and precision takes in the arena
+ * (state, control block and reduction partials); 0 for an invalid D. Pure host
+ * arithmetic; the rho/mask pointers of p are not read. */
+size_t dot_footprint_bytes(const dot_problem* p);
+/* Reserves the arena (DOT_ENOMEM if the device cannot hold it). */
+int dot_ctx_create(int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_t max_slots, dot_ctx** out);
+/* Frees the arena and every request, finished or not. */
+void dot_ctx_destroy(dot_ctx* ctx);
+/* Validates p (as dot_plan_create), builds its constant tables and queues it;
+ * *ticket identifies it until dot_ctx_fetch. DOT_EBUSY if its footprint
+ * exceeds the whole budget; DOT_EINVAL if D / precision differ from the
+ * context's. The host arrays of p are copied before return. */
+int dot_ctx_submit(dot_ctx* ctx, const dot_problem* p, uint64_t* ticket);
+/* Admit, run iters (a multiple of 10) iterations, retire; blocks until the
+ * work is done. Optional outputs: running and queued counts after the step.
+ * With nothing running, only admission happens. */
+int dot_ctx_step(dot_ctx* ctx, int32_t iters, void* stream, int32_t* n_active, int32_t* n_queued);
+/* *status = dot_req_status of the request. */
+int dot_ctx_poll(dot_ctx* ctx, uint64_t ticket, int32_t* status);
+/* Copies a finished request's rho / m (host, shapes as dot_solve; either may
+ * be NULL) and result, then forgets the ticket. DOT_EINVAL if not finished. */
+int dot_ctx_fetch(dot_ctx* ctx, uint64_t ticket, double* rho_out, double* m_out, dot_result* res);
+/* Free arena bytes and the counts of admitted and retired requests. */
+int dot_ctx_stats(const dot_ctx* ctx, size_t* free_bytes, int64_t* admitted, int64_t* retired);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,11 @@ EXPORTED = [
     "dot_batch_create", "dot_batch_destroy", "dot_batch_workspace_bytes", "dot_batch_size", "dot_batch_reset",
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
     "dot_plan_set_graphs", "dot_batch_set_graphs",
+    "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_step", "dot_ctx_poll",
+    "dot_ctx_fetch", "dot_ctx_stats",
 ]
+
+CTX_QUEUED, CTX_RUNNING, CTX_DONE = 0, 1, 2
 
 KERNEL_CLASSES = {"dct_first": 0, "dct_mid": 1, "dct_last": 2, "dct_inv": 3, "cone": 4, "qd": 5,
                   "beta": 6, "resid": 7, "final": 8}
@@ -148,9 +152,21 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_batch_set_graphs.argtypes = [vp, i32]
     lib.dot_batch_profile_select.argtypes = [vp, i32]
     lib.dot_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.dot_footprint_bytes.argtypes = [ctypes.POINTER(dot_problem)]
+    lib.dot_footprint_bytes.restype = ctypes.c_size_t
+    lib.dot_ctx_create.argtypes = [i32, i32, ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+    lib.dot_ctx_destroy.argtypes = [vp]
+    lib.dot_ctx_destroy.restype = None
+    lib.dot_ctx_submit.argtypes = [vp, ctypes.POINTER(dot_problem), ctypes.POINTER(ctypes.c_uint64)]
+    lib.dot_ctx_step.argtypes = [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.dot_ctx_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32)]
+    lib.dot_ctx_fetch.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result)]
+    lib.dot_ctx_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64)]
     for name in EXPORTED:
         if name not in ("dot_last_error", "dot_plan_destroy", "dot_batch_destroy", "dot_batch_workspace_bytes",
-                        "dot_batch_size"):
+                        "dot_batch_size", "dot_footprint_bytes", "dot_ctx_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -424,6 +440,113 @@ def dot_batch_profile_read(batch: Batch):
     n = ctypes.c_int64()
     _check(load().dot_batch_profile_read(batch.handle, ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+def _solution_buffers(D, n):
+    """Host buffers for (rho, packed m) in the paper's shapes, and the m shapes."""
+    n = tuple(int(k) for k in n[:D + 1])
+    sp = tuple(k + 1 for k in n[1:])
+    rho = np.zeros((n[0],) + sp)
+    shapes = []
+    for d in range(1, D + 1):
+        s = [n[0] + 1] + list(sp)
+        s[d] = n[d]
+        shapes.append(tuple(s))
+    m = np.zeros(sum(int(np.prod(s)) for s in shapes))
+    return rho, m, shapes
+
+
+def _split(m, shapes):
+    out, o = [], 0
+    for s in shapes:
+        k = int(np.prod(s))
+        out.append(m[o:o + k].reshape(s))
+        o += k
+    return out
+
+
+# ---- serving context ---------------------------------------------------------
+def dot_footprint_bytes(D, n, precision=DOT_FP64) -> int:
+    """Device bytes one instance of this size takes in a serving context."""
+    p = dot_problem()
+    p.D = D
+    for i in range(4):
+        p.n[i] = int(n[i]) if i <= D else 0
+    p.precision = precision
+    return int(load().dot_footprint_bytes(ctypes.byref(p)))
+
+
+class Ctx:
+    """Owns a dot_ctx handle and the shapes of the requests submitted to it."""
+
+    def __init__(self, handle, D, precision):
+        self.handle = handle
+        self.D = D
+        self.precision = precision
+        self.shapes = {}
+
+    def close(self):
+        if self.handle:
+            load().dot_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dot_ctx_create(D, precision, hbm_budget_bytes, max_slots) -> Ctx:
+    h = ctypes.c_void_p()
+    _check(load().dot_ctx_create(int(D), int(precision), int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+    return Ctx(h, D, precision)
+
+
+def dot_ctx_destroy(ctx: Ctx):
+    ctx.close()
+
+
+def dot_ctx_submit(ctx: Ctx, inst, **kw) -> int:
+    """Queue one problem (object with D, n, rho0, rho1, mask); returns its ticket."""
+    p, keep = make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=ctx.precision, **kw)
+    t = ctypes.c_uint64()
+    _check(load().dot_ctx_submit(ctx.handle, ctypes.byref(p), ctypes.byref(t)))
+    ctx.shapes[t.value] = (inst.D, tuple(int(k) for k in inst.n))
+    return t.value
+
+
+def dot_ctx_step(ctx: Ctx, iters: int, stream: int = 0):
+    """Admit, run `iters` iterations (a multiple of 10), retire; returns (active, queued)."""
+    a = ctypes.c_int32()
+    q = ctypes.c_int32()
+    _check(load().dot_ctx_step(ctx.handle, int(iters), ctypes.c_void_p(stream), ctypes.byref(a), ctypes.byref(q)))
+    return a.value, q.value
+
+
+def dot_ctx_poll(ctx: Ctx, ticket: int) -> int:
+    s = ctypes.c_int32()
+    _check(load().dot_ctx_poll(ctx.handle, ctypes.c_uint64(ticket), ctypes.byref(s)))
+    return s.value
+
+
+def dot_ctx_fetch(ctx: Ctx, ticket: int):
+    """Result of a finished request as (dot_result, rho, [m_d]); releases the ticket."""
+    D, n = ctx.shapes[ticket]
+    rho, m, shapes = _solution_buffers(D, n)
+    r = dot_result()
+    _check(load().dot_ctx_fetch(ctx.handle, ctypes.c_uint64(ticket), _dptr(rho), _dptr(m), ctypes.byref(r)))
+    del ctx.shapes[ticket]
+    return r, rho, _split(m, shapes)
+
+
+def dot_ctx_stats(ctx: Ctx):
+    """(free arena bytes, admitted, retired)."""
+    f = ctypes.c_size_t()
+    a = ctypes.c_int64()
+    r = ctypes.c_int64()
+    _check(load().dot_ctx_stats(ctx.handle, ctypes.byref(f), ctypes.byref(a), ctypes.byref(r)))
+    return f.value, a.value, r.value
 
 
 # ---- padded-box marshalling (host side, numpy) -----------------------------

