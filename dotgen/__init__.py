@@ -31,6 +31,7 @@ __all__ = [
     "config2_instance",
     "config3_instance",
     "config4_instances",
+    "serving_3d_instance",
     "serving_request",
     "tiny_instance",
 ]
@@ -175,6 +176,12 @@ def config2_instance(seed: int = 2000, n0: int = 32, n1: int = 64) -> Instance:
 def config3_instance(seed: int = 3000, n0: int = 64, n1: int = 256) -> Instance:
     """2D, 256x256 segments, 64 time steps, 5-component mixtures, no floor."""
     return _mixture_pair(2, (n0, n1, n1), seed, 5)
+
+
+def serving_3d_instance(seed: int = 5003) -> Instance:
+    """The 3D request shape of the serving stream: 64^3 segments, 32 time
+    steps, 3-component mixtures in [0,1]^3, no floor."""
+    return _mixture_pair(3, (32, 64, 64, 64), seed, 3)
 
 
 def config4_instances(count: int = 64, seed: int = 4000,

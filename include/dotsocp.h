@@ -173,7 +173,7 @@ int dot_step_residuals(dot_plan* plan, const void* phi, const void* z, const voi
 /* ---- measurement hook ---------------------------------------------------- */
 /* Kernel classes of one iteration, for dot_profile_select. */
 typedef enum {
-  DOT_K_DCT_FIRST = 0, /* time-axis forward pass with the divergence fused in */
+  DOT_K_DCT_FIRST = 0, /* time-axis forward pass */
   DOT_K_DCT_MID = 1,   /* forward passes on the middle spatial axes */
   DOT_K_DCT_LAST = 2,  /* last axis: forward, 1/Lambda, inverse */
   DOT_K_DCT_INV = 3,   /* inverse passes on the other axes */
@@ -182,6 +182,7 @@ typedef enum {
   DOT_K_BETA = 6,      /* beta update */
   DOT_K_RESID = 7,     /* residual partial sums (checks only) */
   DOT_K_FINAL = 8,     /* residual finalize + sigma rule (checks only) */
+  DOT_K_RHS = 9,       /* right-hand side A^*(q - alpha/sigma) - c/sigma (mixed: its defect) */
   DOT_K_NONE = -1
 } dot_kernel_class;
 

@@ -35,7 +35,7 @@ EXPORTED = [
 
 CTX_QUEUED, CTX_RUNNING, CTX_DONE = 0, 1, 2
 
-KERNEL_CLASSES = {"dct_first": 0, "dct_mid": 1, "dct_last": 2, "dct_inv": 3, "cone": 4, "qd": 5,
+KERNEL_CLASSES = {"rhs": 9, "dct_first": 0, "dct_mid": 1, "dct_last": 2, "dct_inv": 3, "cone": 4, "qd": 5,
                   "beta": 6, "resid": 7, "final": 8}
 
 

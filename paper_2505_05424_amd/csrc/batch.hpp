@@ -1,7 +1,8 @@
 // Descriptor-driven launches: every kernel of an iteration is one launch over
-// all instances of a batch (a single solve is a batch of one). Block b of a
-// launch serves instance map[b]; its block index inside that instance is
-// b minus the instance's first block in that launch's grid. Instances may
+// all instances of a batch (a single solve is a batch of one). Workgroup b of
+// a launch takes the logical index L = xcd_remap(b) and serves instance
+// map[L]; its block index inside that instance is L minus the instance's
+// first block in that launch's grid. Instances may
 // have different grids; each carries its own geometry, state pointers,
 // constant tables and control block (sigma, stop flag), so each converges and
 // stops on its own.
@@ -43,37 +44,50 @@ __device__ __forceinline__ bool stopped(const Inst<T>& s) {
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_cone_q0(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
-  const Inst<T>& s = I[map[blockIdx.x]];
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
   if (stopped(s)) return;
-  cone_q0_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.sw, s.q[par ^ 1], s.W, s.ctl,
-                     (int64_t)blockIdx.x - s.blk0);
+  cone_q0_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.sw, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_qd(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
-  const Inst<T>& s = I[map[blockIdx.x]];
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
   if (stopped(s)) return;
-  qd_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.ctl, (int64_t)blockIdx.x - s.blk0);
+  qd_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_beta(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par, int check) {
-  const Inst<T>& s = I[map[blockIdx.x]];
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
   if (stopped(s)) return;
-  beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, check,
-                  (int64_t)blockIdx.x - s.blk0);
+  beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, check, L - s.blk0);
+}
+
+// Right-hand side (or its defect against phi) of the Poisson solve into the
+// transform work plane, from (q[par], alpha).
+template <typename T, int D, bool DEFECT>
+__global__ void __launch_bounds__(256)
+kb_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par, double sigma_arg) {
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
+  if (stopped(s)) return;
+  const double inv_sigma = 1.0 / (s.ctl ? glob(s.ctl)->sigma : sigma_arg);
+  rhs_body<T, D, DEFECT>(s.g, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
 }
 
 // Residual partials at the iterate held in q[par] (the newest q).
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_resid(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
-  const Inst<T>& s = I[map[blockIdx.x]];
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
   if (stopped(s)) return;
-  resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials,
-                   (int64_t)blockIdx.x - s.blk0);
+  resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials, L - s.blk0);
 }
 
 // One block per instance.
@@ -89,14 +103,15 @@ template <typename T, int D, int KIND, int SRC, int DST>
 __global__ void __launch_bounds__(kMaxWaves * 64)
 kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int axis, int par,
              double sigma_arg) {
-  const Inst<T>& s = I[map[blockIdx.x]];
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
   if (stopped(s)) return;
   PassArgs pa;
   pa.inner = s.g.stride[axis];
   pa.ncols = s.g.nb / s.g.N[axis];
   axis_pass_body<T, D, KIND, SRC, DST>(s.g, pa, s.tab[axis], s.work, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi,
                                        s.lam_other, s.lam_last, s.ctl, sigma_arg,
-                                       (int64_t)blockIdx.x - s.tile0[axis]);
+                                       (int64_t)(L - s.tile0[axis]));
 }
 
 // ---- step-level kernels (single instance, caller pointers) ----------------
@@ -112,7 +127,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_zres(const Inst<T>* __restrict__ I, const T* __restrict__ z) {
   const Inst<T>& s = I[0];
-  zres_body<T, D>(s.g, z, s.q[0], s.sw, s.partials, blockIdx.x);
+  zres_body<T, D>(s.g, z, s.q[0], s.sw, s.partials, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 template <typename T, int D>

@@ -42,7 +42,6 @@ int fail(int code, const std::string& msg) {
       return fail(DOT_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
   } while (0)
 
-constexpr int kBlock = 256;
 constexpr double kOmegaObstacle = 1e-6;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -125,7 +124,8 @@ struct dot_plan {
   int max_iter = 1000, cadence = 5, adapt = 1, gap0 = 10;
   double growth = 1.2;
   double vol = 1.0, c_norm2 = 0.0, d_norm2 = 0.0;
-  int64_t nblocks = 0;  // blocks of kBlock over one plane
+  int64_t nblocks = 0;       // workgroups of one node sweep (g.nsweep)
+  int64_t partial_rows = 0;  // capacity of the partial-sum rows (nsweep at one slice per workgroup)
   int64_t tiles[kMaxAxes] = {0, 0, 0, 0};
   // device constant tables
   double* sw_sp = nullptr;  // sqrt(omega/2) on spatial nodes
@@ -223,14 +223,20 @@ int build_axis(dot_plan* P, int a, void** buf, AxisTab<T>* tab) {
   return DOT_OK;
 }
 
-// Waves per workgroup of a transform pass over an axis of L points: enough
-// for every work item of the axis in MfmaOps<T>::kItems rounds.
+// Waves per workgroup of a transform pass over an axis of L points. A launch
+// with few tiles (fewer than kManyTiles workgroups) gives each work item its
+// own wave, so the coefficient streams of all items run concurrently; with
+// many tiles each wave takes up to MfmaOps<T>::kItems items and more
+// workgroups share a CU.
+constexpr int64_t kManyTiles = 1024;
 template <typename T>
-int pass_waves(int L) {
+int pass_waves(int L, int64_t tiles) {
   const int M = L / 2, ne = L - M, no = M;
   const int items = 2 * ((ne + 15) / 16 + (no + 15) / 16);
-  const int w = (items + MfmaOps<T>::kItems - 1) / MfmaOps<T>::kItems;
-  return std::max(1, std::min(kMaxWaves, std::max(w, 4)));
+  const int rounds = (items + MfmaOps<T>::kItems - 1) / MfmaOps<T>::kItems;
+  // many tiles: small workgroups, several per CU; few tiles: spread the items
+  const int w = (tiles >= kManyTiles || items > kMaxWaves) ? rounds : items;
+  return std::max(4, std::min(kMaxWaves, w));
 }
 
 template <typename T>
@@ -284,6 +290,23 @@ template <>
 const AxisTab<double>& tab_of<double>(const dot_plan* P, int a) { return P->tab64[a]; }
 template <>
 const AxisTab<float>& tab_of<float>(const dot_plan* P, int a) { return P->tab32[a]; }
+
+// Time slices per workgroup of the node sweeps: enough workgroups to fill the
+// chip (about 4096 per instance) when the grid allows, up to 16 slices each.
+int default_tc(int64_t nx, int N0) {
+  const int64_t nxb = (nx + kBlock - 1) / kBlock;
+  const int64_t tc = (int64_t)N0 * nxb / 4096;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(16, tc));
+}
+
+void set_sweep(Geo& g, int tc) {
+  g.tc = tc;
+  g.nxb = (uint32_t)((g.nx + kBlock - 1) / kBlock);
+  g.nsweep = g.nxb * (uint32_t)((g.N[0] + tc - 1) / tc);
+}
+
+// Workgroups of a flat sweep (one lane per plane entry).
+unsigned flat_grid(const dot_plan* P) { return (unsigned)((P->g.nb + kBlock - 1) / kBlock); }
 
 FinArgs fin_args(const dot_plan* P) {
   FinArgs fa;
@@ -374,8 +397,7 @@ int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
   // the LDS opt-in is per kernel and process: set once (thread-safe static)
   static const int smem_rc = set_max_lds((const void*)fn, E.device);
   if (smem_rc) return smem_rc;
-  const int cls = SRC != kSrcPlane ? DOT_K_DCT_FIRST
-                  : KIND == kFwdScaleInv ? DOT_K_DCT_LAST
+  const int cls = KIND == kFwdScaleInv ? DOT_K_DCT_LAST
                   : KIND == kInv         ? DOT_K_DCT_INV
                                          : (a == 0 ? DOT_K_DCT_FIRST : DOT_K_DCT_MID);
   ProfScope ps(E.prof, cls, st);
@@ -404,12 +426,26 @@ int run_passes(const Exec& E, int par, double sigma, hipStream_t st) {
 // Poisson solve inside an iteration. FP64: the transforms run in place on
 // phi. Mixed: the FP32 transforms solve A^*A dphi = b - A^*A phi on the
 // scratch plane and the last pass adds dphi to the FP64 phi.
+template <typename T, int D, bool DEFECT>
+int launch_rhs(const Exec& E, int par, double sigma, hipStream_t st) {
+  {
+    ProfScope ps(E.prof, DOT_K_RHS, st);
+    hipLaunchKernelGGL((kb_rhs<T, D, DEFECT>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+                       E.map_nodes, par, sigma);
+  }
+  HIP_OK(hipGetLastError());
+  return DOT_OK;
+}
+
 template <typename T, int D>
 int poisson_iter(const Exec& E, int par, hipStream_t st) {
-  if constexpr (std::is_same<T, double>::value)
-    return run_passes<double, D, kSrcDivergence, kDstPlane>(E, par, 0.0, st);
+  constexpr bool kMixed = !std::is_same<T, double>::value;
+  int rc = launch_rhs<T, D, kMixed>(E, par, 0.0, st);
+  if (rc) return rc;
+  if constexpr (kMixed)
+    return run_passes<T, D, kSrcPlane, kDstPhiAdd>(E, par, 0.0, st);
   else
-    return run_passes<T, D, kSrcDefect, kDstPhiAdd>(E, par, 0.0, st);
+    return run_passes<double, D, kSrcPlane, kDstPlane>(E, par, 0.0, st);
 }
 
 template <typename T, int D>
@@ -591,7 +627,8 @@ Exec plan_exec(dot_plan* P, int slot) {
     E.map_axis[a] = P->d_zero_map;
     E.grid_axis[a] = (unsigned)P->tiles[a];
     E.smem_axis[a] = (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes;
-    E.waves_axis[a] = P->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a]) : pass_waves<float>(P->g.N[a]);
+    E.waves_axis[a] = P->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], P->tiles[a])
+                                               : pass_waves<float>(P->g.N[a], P->tiles[a]);
   }
   E.prof = &P->prof;
   E.device = P->device;
@@ -638,7 +675,7 @@ struct DivF {
     Exec E = plan_exec(P, 1);
     int rc = upload_inst(E, step_inst<T>(P, nullptr, q, al, nullptr, nullptr, nullptr, nullptr), st);
     if (rc) return rc;
-    hipLaunchKernelGGL((kb_divergence<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+    hipLaunchKernelGGL((kb_divergence<T, D>), dim3(flat_grid(P)), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
                        1.0 / sigma, (double*)b);
     HIP_OK(hipGetLastError());
     return DOT_OK;
@@ -654,11 +691,11 @@ struct PoissonF {
     E.prof = nullptr;
     int rc = upload_inst(E, step_inst<T>(P, phi, q, al, nullptr, nullptr, nullptr, nullptr), st);
     if (rc) return rc;
+    if (q && (rc = launch_rhs<T, D, false>(E, 0, sigma, st))) return rc;
     if constexpr (std::is_same<T, double>::value) {
-      if (q) return run_passes<double, D, kSrcDivergence, kDstPlane>(E, 0, sigma, st);
       return run_passes<double, D, kSrcPlane, kDstPlane>(E, 0, sigma, st);
     } else {
-      if (q) return run_passes<T, D, kSrcDivergence, kDstPhiSet>(E, 0, sigma, st);
+      if (q) return run_passes<T, D, kSrcPlane, kDstPhiSet>(E, 0, sigma, st);
       return run_passes<T, D, kSrcPlaneF64, kDstPhiSet>(E, 0, sigma, st);
     }
   }
@@ -670,7 +707,7 @@ struct ConeF {
     Exec E = plan_exec(P, 1);
     int rc = upload_inst(E, step_inst<T>(P, nullptr, q, nullptr, beta, nullptr, nullptr, nullptr), st);
     if (rc) return rc;
-    hipLaunchKernelGGL((kb_cone_out<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+    hipLaunchKernelGGL((kb_cone_out<T, D>), dim3(flat_grid(P)), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
                        1.0 / sigma, (T*)z);
     HIP_OK(hipGetLastError());
     return DOT_OK;
@@ -933,17 +970,19 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   P->off_beta = P->off_alpha + (size_t)(D + 1) * pb;
   P->off_w = P->off_beta + (size_t)P->K * pb;
   P->n_planes = 3 * (D + 1) + P->K + 4 * D;
-  P->nblocks = (g.nb + kBlock - 1) / kBlock;
+  set_sweep(g, default_tc(g.nx, g.N[0]));
+  P->nblocks = g.nsweep;
+  P->partial_rows = (int64_t)g.nxb * g.N[0];
   P->ctl_offset = align256(P->off_w + (size_t)(4 * D) * pb);
   P->partials_offset = P->ctl_offset + align256(sizeof(Ctl));
-  P->state_bytes = P->partials_offset + align256((size_t)P->nblocks * kNumSums * sizeof(double));
+  P->state_bytes = P->partials_offset + align256((size_t)P->partial_rows * kNumSums * sizeof(double));
   if (P->precision == DOT_MIXED) HIP_OK(hipMalloc(&P->step_scratch, pb));
   HIP_OK(hipMalloc((void**)&P->step_ctl, sizeof(Ctl)));
-  HIP_OK(hipMalloc((void**)&P->step_partials, (size_t)P->nblocks * kNumSums * sizeof(double)));
-  HIP_OK(hipMemset(P->step_partials, 0, (size_t)P->nblocks * kNumSums * sizeof(double)));
+  HIP_OK(hipMalloc((void**)&P->step_partials, (size_t)P->partial_rows * kNumSums * sizeof(double)));
+  HIP_OK(hipMemset(P->step_partials, 0, (size_t)P->partial_rows * kNumSums * sizeof(double)));
   HIP_OK(hipHostMalloc((void**)&P->host_ctl, sizeof(Ctl), hipHostMallocDefault));
   HIP_OK(hipMalloc(&P->d_inst, 2 * inst_slot_bytes()));
-  int64_t maxgrid = P->nblocks;
+  int64_t maxgrid = P->partial_rows;
   for (int a = 0; a <= D; ++a) maxgrid = std::max(maxgrid, P->tiles[a]);
   HIP_OK(hipMalloc((void**)&P->d_zero_map, (size_t)maxgrid * sizeof(uint16_t)));
   HIP_OK(hipMemset(P->d_zero_map, 0, (size_t)maxgrid * sizeof(uint16_t)));
@@ -1036,7 +1075,7 @@ int dot_step_residuals(dot_plan* P, const void* phi, const void* z, const void* 
 }
 
 int dot_profile_select(dot_plan* P, int32_t kernel_class) {
-  if (!P || kernel_class < -1 || kernel_class > DOT_K_FINAL) return fail(DOT_EINVAL, "bad kernel class");
+  if (!P || kernel_class < -1 || kernel_class > DOT_K_RHS) return fail(DOT_EINVAL, "bad kernel class");
   P->prof.cls = kernel_class;
   P->prof.used = 0;
   P->prof.ms = 0.0;
@@ -1128,11 +1167,14 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
     map_off[a] = maps.size();
     size_t smem = 0;
     int waves = 1;
+    int64_t all_tiles = 0;
+    for (int i = 0; i < count; ++i) all_tiles += B->plans[i]->tiles[a];
     for (int i = 0; i < count; ++i) {
       dot_plan* P = B->plans[i];
       maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)i);
       smem = std::max(smem, (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes);
-      waves = std::max(waves, B->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a]) : pass_waves<float>(P->g.N[a]));
+      waves = std::max(waves, B->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], all_tiles)
+                                                       : pass_waves<float>(P->g.N[a], all_tiles));
     }
     E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);
     E.smem_axis[a] = smem;
@@ -1198,7 +1240,7 @@ int dot_batch_set_graphs(dot_batch* B, int32_t enable) {
 }
 
 int dot_batch_profile_select(dot_batch* B, int32_t kernel_class) {
-  if (!B || kernel_class < -1 || kernel_class > DOT_K_FINAL) return fail(DOT_EINVAL, "bad kernel class");
+  if (!B || kernel_class < -1 || kernel_class > DOT_K_RHS) return fail(DOT_EINVAL, "bad kernel class");
   B->prof.cls = kernel_class;
   B->prof.used = 0;
   B->prof.ms = 0.0;
@@ -1363,6 +1405,9 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
     map_off[a] = maps.size();
     size_t smem = 0;
     int waves = 1, k = 0;
+    int64_t all_tiles = 0;
+    for (int sl = 0; sl < C->max_slots; ++sl)
+      if (C->slots[sl]) all_tiles += C->slots[sl]->plan->tiles[a];
     for (int sl = 0; sl < C->max_slots; ++sl) {
       Request* r = C->slots[sl];
       if (!r) continue;
@@ -1370,7 +1415,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
       maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)k);
       ++k;
       smem = std::max(smem, (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes);
-      waves = std::max(waves, std::is_same<T, double>::value ? pass_waves<double>(P->g.N[a]) : pass_waves<float>(P->g.N[a]));
+      waves = std::max(waves, pass_waves<T>(P->g.N[a], all_tiles));
     }
     E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);
     E.smem_axis[a] = smem;
@@ -1493,7 +1538,8 @@ size_t dot_footprint_bytes(const dot_problem* p) {
   if (p->precision == DOT_MIXED) s += align256(pb);          // transform scratch
   s += (size_t)(3 * (D + 1) + 4 * D + 2 + 4 * D) * pb;       // q, q_new, alpha, beta, W
   s = align256(s) + align256(sizeof(Ctl));
-  s += align256((nb + kBlock - 1) / kBlock * kNumSums * sizeof(double));
+  s += align256((nb / ((size_t)p->n[0] + 1) + kBlock - 1) / kBlock * ((size_t)p->n[0] + 1) * kNumSums *
+                sizeof(double));
   return s;
 }
 

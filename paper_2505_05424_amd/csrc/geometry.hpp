@@ -13,6 +13,16 @@ namespace dot {
 
 constexpr int kMaxAxes = 4;   // time + up to 3 spatial axes
 constexpr int kNumSums = 20;  // residual partial sums (see kernels_update.hpp)
+constexpr int kBlock = 256;   // lanes per workgroup of the node sweeps
+
+// Pointers into device memory qualified as global, so that loads and stores
+// through them compile to global (not flat) memory instructions.
+template <typename T>
+using gp = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gp<T> glob(T* p) {
+  return (gp<T>)p;
+}
 
 struct Geo {
   int D;                     // spatial dimensions
@@ -23,7 +33,21 @@ struct Geo {
   int64_t nb;                // elements per plane
   int64_t nx;                // spatial nodes per time slice
   double inv_h[kMaxAxes];    // n_d
+  // node sweeps: a workgroup takes kBlock consecutive spatial nodes and tc
+  // consecutive time slices (its lanes march through time); workgroup b of an
+  // instance covers spatial block b % nxb and time chunk b / nxb
+  uint32_t nxb;              // spatial blocks, ceil(nx / kBlock)
+  int32_t tc;                // time slices per workgroup
+  uint32_t nsweep;           // workgroups per sweep, nxb * ceil(N0 / tc)
 };
+
+// Workgroup b of a launch of G workgroups runs on XCD b % 8; remap so that
+// each XCD receives one contiguous range of the logical index (neighbouring
+// tiles then share that XCD's L2).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+  const uint32_t q = G >> 3, r = G & 7, x = b & 7, p = b >> 3;
+  return x * q + (x < r ? x : r) + p;
+}
 
 // Device-resident control block: penalty, counters, stop flag and the last
 // residuals. Kernels read sigma and stop at entry; the finalize kernel writes.

@@ -19,6 +19,7 @@ namespace dot {
 constexpr int kCW = 64;        // lines per tile
 constexpr int kMaxWaves = 16;  // waves per workgroup (upper bound)
 constexpr int kU = 8;          // k-steps per prefetch chunk
+constexpr int kLoadBatch = 8;  // rows a wave loads before writing them to the tile
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -67,13 +68,9 @@ struct AxisTab {
 };
 
 enum PassKind { kFwd = 0, kInv = 1, kFwdScaleInv = 2 };
-// What the first (time-axis forward) pass loads:
-//   kSrcPlane       the work plane itself (in place)
-//   kSrcDivergence  b = A^*(q - alpha/sigma) - c/sigma, computed while loading
-//   kSrcDefect      b - A^*A phi for the FP64 plane phi (mixed precision: the
-//                   FP32 transforms then solve only for the correction)
-//   kSrcPlaneF64    an FP64 right-hand side plane (mixed precision step call)
-enum PassSrc { kSrcPlane = 0, kSrcDivergence = 1, kSrcDefect = 2, kSrcPlaneF64 = 3 };
+// What the first (time-axis forward) pass loads: the work plane itself (in
+// place), or an FP64 right-hand side plane (mixed-precision step call).
+enum PassSrc { kSrcPlane = 0, kSrcPlaneF64 = 3 };
 // Where the last (time-axis inverse) pass stores: the work plane, phi += result
 // (FP64), or phi = result (FP64).
 enum PassDst { kDstPlane = 0, kDstPhiAdd = 1, kDstPhiSet = 2 };
@@ -118,8 +115,9 @@ __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv
     const int ks = odd ? a.ks_o : a.ks_e;
     const int nin = odd ? a.no : a.ne;
     typedef typename MfmaOps<T>::chunk_t chunk_t;
-    const chunk_t* tp = reinterpret_cast<const chunk_t*>(inv ? (odd ? a.io : a.ie) : (odd ? a.fo : a.fe)) +
-                        (size_t)m * (ks / kU + 1) * 64 + lane;
+    gp<const chunk_t> tp = (gp<const chunk_t>)reinterpret_cast<const chunk_t*>(inv ? (odd ? a.io : a.ie)
+                                                                                  : (odd ? a.fo : a.fe)) +
+                           (size_t)m * (ks / kU + 1) * 64 + lane;
     const int col = g * 32 + (lane & 15);
     // coefficient fragments are prefetched one chunk of kU k-steps ahead
     chunk_t cur = tp[0];
@@ -205,12 +203,14 @@ __device__ __forceinline__ void tile_inverse(T* tile, const AxisTab<T>& a) {
 // with spatial coordinates x[1..D]), the right-hand side of the phi-step of
 // Algorithm 2 (zero extension outside each staggered set).
 template <typename T, int D>
-__device__ __forceinline__ double divergence_at(const Geo& g, const T* __restrict__ q, const T* __restrict__ al,
+__device__ __forceinline__ double divergence_at(const Geo& g, const T* q_, const T* al_,
                                            const double* __restrict__ c_lo, const double* __restrict__ c_hi,
                                            double inv_sigma, int t, uint32_t xs, const int (&x)[kMaxAxes]) {
   const uint32_t nb = (uint32_t)g.nb;
   const uint32_t s0 = (uint32_t)g.stride[0];
   const uint32_t i = (uint32_t)t * s0 + xs;
+  gp<const T> q = glob(q_);
+  gp<const T> al = glob(al_);
   double b = 0.0;
   // time axis: cells t-1 and t
   if (t >= 1) b += ((double)q[i - s0] - (double)al[i - s0] * inv_sigma) * g.inv_h[0];
@@ -218,36 +218,14 @@ __device__ __forceinline__ double divergence_at(const Geo& g, const T* __restric
 #pragma unroll
   for (int d = 1; d <= D; ++d) {
     const uint32_t sd = (uint32_t)g.stride[d];
-    const T* qd = q + d * nb;
-    const T* ad = al + d * nb;
+    gp<const T> qd = q + (size_t)d * nb;
+    gp<const T> ad = al + (size_t)d * nb;
     if (x[d] >= 1) b += ((double)qd[i - sd] - (double)ad[i - sd] * inv_sigma) * g.inv_h[d];
     if (x[d] < g.n[d]) b -= ((double)qd[i] - (double)ad[i] * inv_sigma) * g.inv_h[d];
   }
-  if (t == 0) b -= c_lo[xs] * inv_sigma;
-  if (t == g.n[0]) b -= c_hi[xs] * inv_sigma;
+  if (t == 0) b -= glob(c_lo)[xs] * inv_sigma;
+  if (t == g.n[0]) b -= glob(c_hi)[xs] * inv_sigma;
   return b;
-}
-
-// (A^*A phi) at node (t, xs): sum over axes of the path-graph Laplacian
-// stencil / h_d^2 (Neumann ends), in FP64.
-template <int D>
-__device__ __forceinline__ double laplacian_at(const Geo& g, const double* __restrict__ phi, int t, uint32_t xs,
-                                               const int (&x)[kMaxAxes]) {
-  const uint32_t s0 = (uint32_t)g.stride[0];
-  const uint32_t i = (uint32_t)t * s0 + xs;
-  const double c = phi[i];
-  const double w0 = g.inv_h[0] * g.inv_h[0];
-  double r = 0.0;
-  if (t >= 1) r += (c - phi[i - s0]) * w0;
-  if (t < g.n[0]) r -= (phi[i + s0] - c) * w0;
-#pragma unroll
-  for (int d = 1; d <= D; ++d) {
-    const uint32_t sd = (uint32_t)g.stride[d];
-    const double wd = g.inv_h[d] * g.inv_h[d];
-    if (x[d] >= 1) r += (c - phi[i - sd]) * wd;
-    if (x[d] < g.n[d]) r -= (phi[i + sd] - c) * wd;
-  }
-  return r;
 }
 
 // Spatial coordinates x[1..D] of spatial flat index xs.
@@ -283,20 +261,32 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
   const int64_t c0 = blk * kCW;
   const int64_t inner = pa.inner;
   const int64_t ncols = pa.ncols;
-  double inv_sigma = 0.0;
-  if (SRC == kSrcDivergence || SRC == kSrcDefect) inv_sigma = 1.0 / (ctl ? ctl->sigma : sigma_arg);
 
-  // load (32-bit index math: planes hold fewer than 2^31 elements)
+  // load (32-bit index math: planes hold fewer than 2^31 elements). Each wave
+  // issues kLoadBatch independent loads before writing them to the tile, so
+  // the global-memory latency is paid once per batch, not once per row.
+  gp<T> pl = glob(plane);
   const int nw = blockDim.x >> 6;
   const int lane = threadIdx.x & 63;
   if (inner == 1) {
     const uint32_t base = (uint32_t)c0 * (uint32_t)L;
     const uint32_t lim = (uint32_t)ncols * (uint32_t)L;
-    for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
-      const int cl = e / L, j = e - cl * L;
-      T v = T(0);
-      if (base + e < lim) v = plane[base + e];
-      tile[j * (kCW + 1) + cl] = v;
+    const int tot = L * kCW;
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kLoadBatch * blockDim.x) {
+      T v[kLoadBatch];
+#pragma unroll
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int e = e0 + r * blockDim.x;
+        v[r] = (e < tot && base + e < lim) ? pl[base + e] : T(0);
+      }
+#pragma unroll
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int e = e0 + r * blockDim.x;
+        if (e < tot) {
+          const int cl = e / L, j = e - cl * L;
+          tile[j * (kCW + 1) + cl] = v[r];
+        }
+      }
     }
   } else {
     // one column per lane, rows spread over the waves
@@ -305,24 +295,25 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
     const uint32_t cu = (uint32_t)c;
     const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
     const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
-    int x[kMaxAxes] = {0, 0, 0, 0};
-    if (SRC == kSrcDivergence || SRC == kSrcDefect) spatial_coords<D>(g, cu, x);
-    for (int j = threadIdx.x >> 6; j < L; j += nw) {
-      T v = T(0);
-      if (ok) {
-        const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
-        if (SRC == kSrcDivergence) {
-          v = (T)divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, j, cu, x);
-        } else if (SRC == kSrcDefect) {
-          const double b = divergence_at<T, D>(g, q, al, c_lo, c_hi, inv_sigma, j, cu, x);
-          v = (T)(b - laplacian_at<D>(g, phi, j, cu, x));
-        } else if (SRC == kSrcPlaneF64) {
-          v = (T)phi[e];
-        } else {
-          v = plane[e];
+    for (int j0 = threadIdx.x >> 6; j0 < L; j0 += kLoadBatch * nw) {
+      T v[kLoadBatch];
+#pragma unroll
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int j = j0 + r * nw;
+        v[r] = T(0);
+        if (ok && j < L) {
+          const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
+          if (SRC == kSrcPlaneF64)
+            v[r] = (T)glob(phi)[e];
+          else
+            v[r] = pl[e];
         }
       }
-      tile[j * (kCW + 1) + lane] = v;
+#pragma unroll
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int j = j0 + r * nw;
+        if (j < L) tile[j * (kCW + 1) + lane] = v[r];
+      }
     }
   }
   __syncthreads();
@@ -334,7 +325,7 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
       const int64_t c = c0 + cl;
       T s = T(0);
       if (c < ncols) {
-        const T lam = lam_other[c] + lam_last[k];
+        const T lam = glob(lam_other)[c] + glob(lam_last)[k];
         s = lam > T(0) ? T(1) / lam : T(0);  // mode (0,...,0): phi in rge A^*
       }
       tile[k * (kCW + 1) + cl] *= s;
@@ -349,7 +340,7 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
     const uint32_t lim = (uint32_t)ncols * (uint32_t)L;
     for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
       const int cl = e / L, j = e - cl * L;
-      if (base + e < lim) plane[base + e] = tile[j * (kCW + 1) + cl];
+      if (base + e < lim) pl[base + e] = tile[j * (kCW + 1) + cl];
     }
   } else {
     const int64_t c = c0 + lane;
@@ -361,11 +352,11 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
         const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
         const T v = tile[j * (kCW + 1) + lane];
         if (DST == kDstPhiAdd)
-          phi[e] += (double)v;
+          glob(phi)[e] += (double)v;
         else if (DST == kDstPhiSet)
-          phi[e] = (double)v;
+          glob(phi)[e] = (double)v;
         else
-          plane[e] = v;
+          pl[e] = v;
       }
     }
   }

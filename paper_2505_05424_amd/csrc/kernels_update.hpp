@@ -79,76 +79,303 @@ __device__ __forceinline__ void soc_project(double (&y)[K]) {
   for (int k = 1; k < K; ++k) y[k] *= s;
 }
 
-// ---------------------------------------------------------------------------
-// a1 + a2 + q0 part of a5: per cell, z = Pi(u); w = z - d + beta/sigma;
-// q0_new = (A_0 phi + alpha0/sigma + w_{K-1} - w_0) / 3 and alpha0 update;
-// the weighted components sqrt(omega/2) w_{d,v} go to W for the q_d update.
-// ---------------------------------------------------------------------------
-template <typename T, int D>
-__device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restrict__ phi, const T* __restrict__ q,
-                                             T* __restrict__ alpha, const T* __restrict__ beta,
-                                             const double* __restrict__ sw_sp, T* __restrict__ qn, T* __restrict__ W,
-                                             const Ctl* __restrict__ ctl, int64_t blk) {
-  constexpr int K = 4 * D + 2;
-  const int64_t i = blk * blockDim.x + threadIdx.x;
-  const int64_t ncell = (int64_t)g.n[0] * g.stride[0];
-  if (i >= ncell) return;
-  const double sigma = ctl->sigma, tau = ctl->tau, inv_sigma = 1.0 / sigma;
-  int x[kMaxAxes];
-  node_coords<D>(g, i, x);
-  const int64_t xs = i % g.nx;
-  const double sw = sw_sp[xs];
-  double u[K];
-  cone_input<T, D>(g, q, beta, i, x, sw, inv_sigma, u);
-  soc_project<K>(u);
-  const int64_t nb = g.nb;
-  // w = z - d + beta/sigma
-  const double w0 = u[0] - 1.0 + (double)beta[i] * inv_sigma;
-  const double wl = u[K - 1] - 1.0 + (double)beta[(K - 1) * nb + i] * inv_sigma;
-  const double g0 = ((double)phi[i + g.stride[0]] - (double)phi[i]) * g.inv_h[0];
-  const double a0 = (double)alpha[i];
-  const double q0n = (g0 + a0 * inv_sigma + wl - w0) * (1.0 / 3.0);
-  qn[i] = (T)q0n;
-  alpha[i] = (T)(a0 + tau * sigma * (g0 - q0n));
+// ---- node sweeps ------------------------------------------------------------
+// A workgroup owns kBlock consecutive spatial nodes and the time slices
+// [t0, t1) of one chunk; each lane walks its spatial node through those slices,
+// so the values at slice t+1 that the cell at t needs (q_d, phi) are loaded
+// once and carried to the next slice in registers.
+struct Column {
+  uint32_t xs;          // spatial index of the lane
+  bool live;            // xs < nx
+  int x[kMaxAxes];      // spatial coordinates x[1..D]
+  int t0, t1;           // time slices of the workgroup
+};
+
+template <int D>
+__device__ __forceinline__ Column column_of(const Geo& g, uint32_t blk) {
+  Column c;
+  const uint32_t tci = blk / g.nxb;
+  const uint32_t xb = blk - tci * g.nxb;
+  c.xs = xb * kBlock + threadIdx.x;
+  c.live = c.xs < (uint32_t)g.nx;
+  uint32_t r = c.live ? c.xs : 0u;
 #pragma unroll
-  for (int k = 1; k < K - 1; ++k) {
-    const double wk = u[k] + (double)beta[k * nb + i] * inv_sigma;
-    W[(k - 1) * nb + i] = (T)(sw * wk);
+  for (int d = D; d >= 1; --d) {
+    const uint32_t Nd = (uint32_t)g.N[d];
+    const uint32_t qd = r / Nd;
+    c.x[d] = (int)(r - qd * Nd);
+    r = qd;
+  }
+  c.t0 = (int)tci * g.tc;
+  c.t1 = min(c.t0 + g.tc, g.N[0]);
+  return c;
+}
+
+// Values of F^d_v q at one cell that come from one time slice: for each d,
+// [0] = q_d[t, x - e_d] (x_d >= 1, else 0) and [1] = q_d[t, x] (x_d < n_d),
+// kept in the storage type (they are widened to double where used).
+template <typename T, int D>
+__device__ __forceinline__ void load_fq(const Geo& g, gp<const T> q, uint32_t i, const Column& c,
+                                        T (&f)[kMaxAxes][2]) {
+  const uint32_t nb = (uint32_t)g.nb;
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    gp<const T> qd = q + (size_t)d * nb;
+    const uint32_t sd = (uint32_t)g.stride[d];
+    f[d][0] = c.x[d] >= 1 ? qd[i - sd] : T(0);
+    f[d][1] = c.x[d] < g.n[d] ? qd[i] : T(0);
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void shift_fq(T (&a)[kMaxAxes][2], const T (&b)[kMaxAxes][2]) {
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    a[d][0] = b[d][0];
+    a[d][1] = b[d][1];
+  }
+}
+
+// u = B_omega F q + d - beta/sigma at a cell from its beta values bt, q0 and
+// the F q values of slices t (fa) and t+1 (fb), in double.
+template <typename T, int D>
+__device__ __forceinline__ void cone_arg(const T (&bt)[4 * D + 2], double q0, const T (&fa)[kMaxAxes][2],
+                                         const T (&fb)[kMaxAxes][2], double sw, double inv_sigma,
+                                         double (&u)[4 * D + 2]) {
+  constexpr int K = 4 * D + 2;
+  u[0] = 1.0 - q0 - (double)bt[0] * inv_sigma;
+  u[K - 1] = 1.0 + q0 - (double)bt[K - 1] * inv_sigma;
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    const int k = 1 + 4 * (d - 1);
+    u[k + 0] = sw * (double)fa[d][0] - (double)bt[k + 0] * inv_sigma;
+    u[k + 1] = sw * (double)fa[d][1] - (double)bt[k + 1] * inv_sigma;
+    u[k + 2] = sw * (double)fb[d][0] - (double)bt[k + 2] * inv_sigma;
+    u[k + 3] = sw * (double)fb[d][1] - (double)bt[k + 3] * inv_sigma;
+  }
+}
+
+// a1 + a2 + q0 part of a5 per cell: z = Pi(u); w = z - d + beta/sigma;
+// q0_new = (A_0 phi + alpha0/sigma + w_{K-1} - w_0) / 3 and the alpha0
+// update; the weighted components sqrt(omega/2) w_{d,v} go to W for the q_d
+// update.
+template <typename T, int D>
+__device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restrict__ phi_, const T* __restrict__ q_,
+                                             T* __restrict__ alpha_, const T* __restrict__ beta_,
+                                             const double* __restrict__ sw_sp, T* __restrict__ qn_, T* __restrict__ W_,
+                                             const Ctl* __restrict__ ctl, uint32_t blk) {
+  constexpr int K = 4 * D + 2;
+  const Column c = column_of<D>(g, blk);
+  const int tend = min(c.t1, g.n[0]);
+  if (!c.live || c.t0 >= tend) return;
+  gp<const double> phi = glob(phi_);
+  gp<const T> q = glob(q_);
+  gp<T> alpha = glob(alpha_);
+  gp<const T> beta = glob(beta_);
+  gp<T> qn = glob(qn_);
+  gp<T> W = glob(W_);
+  const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+  const double sigma = glob(ctl)->sigma, tau = glob(ctl)->tau, inv_sigma = 1.0 / sigma;
+  const double sw = glob(sw_sp)[c.xs];
+  uint32_t i = (uint32_t)c.t0 * nx + c.xs;
+  T fa[kMaxAxes][2], fb[kMaxAxes][2];
+  load_fq<T, D>(g, q, i, c, fa);
+  double ph = phi[i];
+  for (int t = c.t0; t < tend; ++t, i += nx) {
+    load_fq<T, D>(g, q, i + nx, c, fb);
+    const double ph1 = phi[i + nx];
+    T bt[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) bt[k] = beta[(size_t)k * nb + i];
+    const double q0 = (double)q[i];
+    const double a0 = (double)alpha[i];
+    double u[K];
+    cone_arg<T, D>(bt, q0, fa, fb, sw, inv_sigma, u);
+    soc_project<K>(u);
+    const double w0 = u[0] - 1.0 + (double)bt[0] * inv_sigma;
+    const double wl = u[K - 1] - 1.0 + (double)bt[K - 1] * inv_sigma;
+    const double g0 = (ph1 - ph) * g.inv_h[0];
+    const double q0n = (g0 + a0 * inv_sigma + wl - w0) * (1.0 / 3.0);
+    qn[i] = (T)q0n;
+    alpha[i] = (T)(a0 + tau * sigma * (g0 - q0n));
+#pragma unroll
+    for (int k = 1; k < K - 1; ++k) W[(size_t)(k - 1) * nb + i] = (T)(sw * (u[k] + (double)bt[k] * inv_sigma));
+    shift_fq<T, D>(fa, fb);
+    ph = ph1;
   }
 }
 
 // q_d update (d >= 1) of a5 per node: rhs = A_d phi + alpha_d/sigma + the four
 // adjacent cells' weighted w components; diagonal 1 + 1/2 sum of omega over
-// the adjacent cells (Prop. 3.2 with weights); alpha_d update.
+// the adjacent cells (Prop. 3.2 with weights); alpha_d update. The loads of
+// slice t+1 are issued before slice t is computed (two slices in flight).
 template <typename T, int D>
-__device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__ phi, T* __restrict__ alpha,
-                                        const double* __restrict__ om_sp, T* __restrict__ qn, const T* __restrict__ W,
-                                        const Ctl* __restrict__ ctl, int64_t blk) {
-  const int64_t i = blk * blockDim.x + threadIdx.x;
-  if (i >= g.nb) return;
-  const double sigma = ctl->sigma, tau = ctl->tau, inv_sigma = 1.0 / sigma;
-  int x[kMaxAxes];
-  node_coords<D>(g, i, x);
-  const int64_t nb = g.nb, s0 = g.stride[0];
-  const int64_t xs = i % g.nx;
-  const int t = x[0];
-  const bool has_now = t < g.n[0];
-  const bool has_prev = t >= 1;
-  const double ct = (double)has_now + (double)has_prev;
+struct QdSlice {
+  double ph;
+  double phd[kMaxAxes];  // phi[i + e_d]
+  T w[kMaxAxes][4];      // W_{d,v} of the adjacent cells (0 where absent)
+  T ad[kMaxAxes];        // alpha_d
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void qd_load(const Geo& g, const Column& c, int t, uint32_t i, gp<const double> phi,
+                                        gp<const T> alpha, gp<const T> W, QdSlice<T, D>& s) {
+  const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+  const bool has_now = t < g.n[0], has_prev = t >= 1;
+  s.ph = phi[i];
 #pragma unroll
   for (int d = 1; d <= D; ++d) {
-    if (x[d] >= g.n[d]) continue;
-    const int64_t sd = g.stride[d];
-    const T* Wd = W + (int64_t)(4 * (d - 1)) * nb;
-    double acc = 0.0;
-    if (has_now) acc += (double)Wd[0 * nb + i + sd] + (double)Wd[1 * nb + i];
-    if (has_prev) acc += (double)Wd[2 * nb + i - s0 + sd] + (double)Wd[3 * nb + i - s0];
-    const double diag = 1.0 + 0.5 * ct * (om_sp[xs] + om_sp[xs + sd]);
-    const double gd = ((double)phi[i + sd] - (double)phi[i]) * g.inv_h[d];
-    const double ad = (double)alpha[d * nb + i];
-    const double qdn = (gd + ad * inv_sigma + acc) / diag;
-    qn[d * nb + i] = (T)qdn;
-    alpha[d * nb + i] = (T)(ad + tau * sigma * (gd - qdn));
+    const bool in = c.x[d] < g.n[d];
+    const uint32_t sd = (uint32_t)g.stride[d];
+    gp<const T> Wd = W + (size_t)(4 * (d - 1)) * nb;
+    s.phd[d] = in ? phi[i + sd] : 0.0;
+    s.ad[d] = in ? alpha[(size_t)d * nb + i] : T(0);
+    s.w[d][0] = in && has_now ? Wd[(size_t)0 * nb + i + sd] : T(0);
+    s.w[d][1] = in && has_now ? Wd[(size_t)1 * nb + i] : T(0);
+    s.w[d][2] = in && has_prev ? Wd[(size_t)2 * nb + i - nx + sd] : T(0);
+    s.w[d][3] = in && has_prev ? Wd[(size_t)3 * nb + i - nx] : T(0);
+  }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__ phi_, T* __restrict__ alpha_,
+                                        const double* __restrict__ om_sp, T* __restrict__ qn_,
+                                        const T* __restrict__ W_, const Ctl* __restrict__ ctl, uint32_t blk) {
+  const Column c = column_of<D>(g, blk);
+  if (!c.live) return;
+  gp<const double> phi = glob(phi_);
+  gp<T> alpha = glob(alpha_);
+  gp<T> qn = glob(qn_);
+  gp<const T> W = glob(W_);
+  gp<const double> om = glob(om_sp);
+  const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+  const double sigma = glob(ctl)->sigma, tau = glob(ctl)->tau, inv_sigma = 1.0 / sigma;
+  double om_a = om[c.xs], om_b[kMaxAxes];
+#pragma unroll
+  for (int d = 1; d <= D; ++d) om_b[d] = c.x[d] < g.n[d] ? om[c.xs + (uint32_t)g.stride[d]] : 0.0;
+  uint32_t i = (uint32_t)c.t0 * nx + c.xs;
+  QdSlice<T, D> cur, nxt;
+  qd_load<T, D>(g, c, c.t0, i, phi, alpha, W, cur);
+  for (int t = c.t0; t < c.t1; ++t, i += nx) {
+    if (t + 1 < c.t1) qd_load<T, D>(g, c, t + 1, i + nx, phi, alpha, W, nxt);
+    const bool has_now = t < g.n[0];
+    const bool has_prev = t >= 1;
+    const double ct = (double)has_now + (double)has_prev;
+#pragma unroll
+    for (int d = 1; d <= D; ++d) {
+      if (c.x[d] >= g.n[d]) continue;
+      double acc = 0.0;
+      if (has_now) acc += (double)cur.w[d][0] + (double)cur.w[d][1];
+      if (has_prev) acc += (double)cur.w[d][2] + (double)cur.w[d][3];
+      const double diag = 1.0 + 0.5 * ct * (om_a + om_b[d]);
+      const double gd = (cur.phd[d] - cur.ph) * g.inv_h[d];
+      const double ad = (double)cur.ad[d];
+      const double qdn = (gd + ad * inv_sigma + acc) / diag;
+      qn[(size_t)d * nb + i] = (T)qdn;
+      alpha[(size_t)d * nb + i] = (T)(ad + tau * sigma * (gd - qdn));
+    }
+    cur = nxt;
+  }
+}
+
+// Right-hand side of the phi-step of Algorithm 2 per node, written to the
+// transform work plane: b = A^*(q - alpha/sigma) - c/sigma (zero extension
+// outside each staggered set) or, with DEFECT, the defect b - A^*A phi of the
+// FP64 phi (path-graph Laplacian / h_d^2 per axis, Neumann ends). The time
+// neighbours (q0 - alpha0/sigma at t-1, phi at t-1 and t) are carried, and
+// the loads of slice t+1 are issued before slice t is computed.
+template <typename T, int D>
+struct RhsSlice {
+  T q0, a0;                 // cell values at t (t < n0)
+  T qd[kMaxAxes][2];        // q_d at x - e_d and x
+  T ad[kMaxAxes][2];        // alpha_d at x - e_d and x
+  double phn;               // phi at t+1 (DEFECT)
+  double phs[kMaxAxes][2];  // phi at x - e_d and x + e_d (DEFECT)
+  double cb;                // c~ on the boundary slices
+};
+
+template <typename T, int D, bool DEFECT>
+__device__ __forceinline__ void rhs_load(const Geo& g, const Column& c, int t, uint32_t i, gp<const T> q,
+                                         gp<const T> al, gp<const double> phi, const double* c_lo,
+                                         const double* c_hi, RhsSlice<T, D>& s) {
+  const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+  const int n0 = g.n[0];
+  s.q0 = t < n0 ? q[i] : T(0);
+  s.a0 = t < n0 ? al[i] : T(0);
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    const uint32_t sd = (uint32_t)g.stride[d];
+    gp<const T> qd = q + (size_t)d * nb;
+    gp<const T> ad = al + (size_t)d * nb;
+    const bool lo = c.x[d] >= 1, hi = c.x[d] < g.n[d];
+    s.qd[d][0] = lo ? qd[i - sd] : T(0);
+    s.ad[d][0] = lo ? ad[i - sd] : T(0);
+    s.qd[d][1] = hi ? qd[i] : T(0);
+    s.ad[d][1] = hi ? ad[i] : T(0);
+    if (DEFECT) {
+      s.phs[d][0] = lo ? phi[i - sd] : 0.0;
+      s.phs[d][1] = hi ? phi[i + sd] : 0.0;
+    }
+  }
+  if (DEFECT) s.phn = t < n0 ? phi[i + nx] : 0.0;
+  s.cb = t == 0 ? glob(c_lo)[c.xs] : (t == n0 ? glob(c_hi)[c.xs] : 0.0);
+}
+
+template <typename T, int D, bool DEFECT>
+__device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ al_,
+                                         const double* __restrict__ phi_, const double* __restrict__ c_lo_,
+                                         const double* __restrict__ c_hi_, T* __restrict__ out_, double inv_sigma,
+                                         uint32_t blk) {
+  const Column c = column_of<D>(g, blk);
+  if (!c.live) return;
+  gp<const T> q = glob(q_);
+  gp<const T> al = glob(al_);
+  gp<const double> phi = glob(phi_);
+  gp<T> out = glob(out_);
+  const uint32_t nx = (uint32_t)g.nx, xs = c.xs;
+  const int n0 = g.n[0];
+  const double w0 = g.inv_h[0] * g.inv_h[0];
+  uint32_t i = (uint32_t)c.t0 * nx + xs;
+  double y0m = 0.0, phm = 0.0, ph = 0.0;
+  if (c.t0 >= 1) {
+    y0m = (double)q[i - nx] - (double)al[i - nx] * inv_sigma;
+    if (DEFECT) phm = phi[i - nx];
+  }
+  if (DEFECT) ph = phi[i];
+  RhsSlice<T, D> cur, nxt;
+  rhs_load<T, D, DEFECT>(g, c, c.t0, i, q, al, phi, c_lo_, c_hi_, cur);
+  for (int t = c.t0; t < c.t1; ++t, i += nx) {
+    if (t + 1 < c.t1) rhs_load<T, D, DEFECT>(g, c, t + 1, i + nx, q, al, phi, c_lo_, c_hi_, nxt);
+    double b = 0.0;
+    if (t >= 1) b += y0m * g.inv_h[0];
+    double y0 = 0.0;
+    if (t < n0) {
+      y0 = (double)cur.q0 - (double)cur.a0 * inv_sigma;
+      b -= y0 * g.inv_h[0];
+    }
+#pragma unroll
+    for (int d = 1; d <= D; ++d) {
+      if (c.x[d] >= 1) b += ((double)cur.qd[d][0] - (double)cur.ad[d][0] * inv_sigma) * g.inv_h[d];
+      if (c.x[d] < g.n[d]) b -= ((double)cur.qd[d][1] - (double)cur.ad[d][1] * inv_sigma) * g.inv_h[d];
+    }
+    if (t == 0 || t == n0) b -= cur.cb * inv_sigma;
+    if (DEFECT) {
+      double r = 0.0;
+      if (t >= 1) r += (ph - phm) * w0;
+      if (t < n0) r -= (cur.phn - ph) * w0;
+#pragma unroll
+      for (int d = 1; d <= D; ++d) {
+        const double wd = g.inv_h[d] * g.inv_h[d];
+        if (c.x[d] >= 1) r += (ph - cur.phs[d][0]) * wd;
+        if (c.x[d] < g.n[d]) r -= (cur.phs[d][1] - ph) * wd;
+      }
+      b -= r;
+      phm = ph;
+      ph = cur.phn;
+    }
+    out[i] = (T)b;
+    y0m = y0;
+    cur = nxt;
   }
 }
 
@@ -174,175 +401,197 @@ __device__ __forceinline__ void block_partials(double (&s)[NS], double* __restri
   }
 }
 
+// Block sum of one double into partials slot 11.
+__device__ __forceinline__ void block_slot11(double v, double* __restrict__ partials, uint32_t blk) {
+  __shared__ double red1[16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  if (lane == 0) red1[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int j = 0; j < nw; ++j) tot += red1[j];
+    glob(partials)[(size_t)blk * kNumSums + 11] = tot;
+  }
+}
+
 // beta update of a5 per cell: z recomputed from the old (q, beta),
 // beta += tau sigma (z - B F q_new - d); at residual checks the block sums of
 // |z - B F q_new - d|^2 go to partials slot 11. Block 0 counts the iteration.
 template <typename T, int D>
-__device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q, const T* __restrict__ qn,
-                                          T* __restrict__ beta, const double* __restrict__ sw_sp,
-                                          Ctl* __restrict__ ctl, double* __restrict__ partials, int check,
-                                          int64_t blk) {
+__device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ qn_,
+                                          T* __restrict__ beta_, const double* __restrict__ sw_sp, Ctl* __restrict__ ctl,
+                                          double* __restrict__ partials, int check, uint32_t blk) {
   constexpr int K = 4 * D + 2;
-  const int64_t i = blk * blockDim.x + threadIdx.x;
-  const int64_t ncell = (int64_t)g.n[0] * g.stride[0];
-  const double sigma = ctl->sigma, tau = ctl->tau, inv_sigma = 1.0 / sigma;
+  const Column c = column_of<D>(g, blk);
+  const int tend = min(c.t1, g.n[0]);
+  const double sigma = glob(ctl)->sigma, tau = glob(ctl)->tau, inv_sigma = 1.0 / sigma;
   double ssq = 0.0;
-  if (i < ncell) {
-    int x[kMaxAxes];
-    node_coords<D>(g, i, x);
-    const double sw = sw_sp[i % g.nx];
-    double u[K];
-    cone_input<T, D>(g, q, beta, i, x, sw, inv_sigma, u);
-    soc_project<K>(u);
-    // B F q_new + d
-    double bq[K];
-    const int64_t nb = g.nb;
-    const double q0 = (double)qn[i];
-    bq[0] = 1.0 - q0;
-    bq[K - 1] = 1.0 + q0;
+  if (c.live && c.t0 < tend) {
+    gp<const T> q = glob(q_);
+    gp<const T> qn = glob(qn_);
+    gp<T> beta = glob(beta_);
+    const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+    const double sw = glob(sw_sp)[c.xs];
+    uint32_t i = (uint32_t)c.t0 * nx + c.xs;
+    T fa[kMaxAxes][2], fb[kMaxAxes][2], ga[kMaxAxes][2], gb[kMaxAxes][2];
+    load_fq<T, D>(g, q, i, c, fa);
+    load_fq<T, D>(g, qn, i, c, ga);
+    for (int t = c.t0; t < tend; ++t, i += nx) {
+      load_fq<T, D>(g, q, i + nx, c, fb);
+      load_fq<T, D>(g, qn, i + nx, c, gb);
+      T bt[K];
 #pragma unroll
-    for (int d = 1; d <= D; ++d) {
-      const T* qd = qn + d * nb;
-      const bool lo = x[d] >= 1, hi = x[d] < g.n[d];
-      const int64_t sd = g.stride[d], s0 = g.stride[0];
-      const int k = 1 + 4 * (d - 1);
-      bq[k + 0] = lo ? sw * (double)qd[i - sd] : 0.0;
-      bq[k + 1] = hi ? sw * (double)qd[i] : 0.0;
-      bq[k + 2] = lo ? sw * (double)qd[i + s0 - sd] : 0.0;
-      bq[k + 3] = hi ? sw * (double)qd[i + s0] : 0.0;
-    }
+      for (int k = 0; k < K; ++k) bt[k] = beta[(size_t)k * nb + i];
+      double u[K];
+      cone_arg<T, D>(bt, (double)q[i], fa, fb, sw, inv_sigma, u);
+      soc_project<K>(u);
+      // r = z - (B F q_new + d), component by component
+      const double q0 = (double)qn[i];
+      auto upd = [&](int k, double bq) {
+        const double r = u[k] - bq;
+        ssq = fma(r, r, ssq);
+        beta[(size_t)k * nb + i] = (T)((double)bt[k] + tau * sigma * r);
+      };
+      upd(0, 1.0 - q0);
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const double r = u[k] - bq[k];
-      ssq = fma(r, r, ssq);
-      beta[k * nb + i] = (T)((double)beta[k * nb + i] + tau * sigma * r);
-    }
-  }
-  if (check) {
-    double s[1] = {ssq};
-    __shared__ double red1[16];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    double v = s[0];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red1[w] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double tot = 0.0;
-      for (int j = 0; j < nw; ++j) tot += red1[j];
-      partials[blk * kNumSums + 11] = tot;
+      for (int d = 1; d <= D; ++d) {
+        const int k = 1 + 4 * (d - 1);
+        upd(k + 0, sw * (double)ga[d][0]);
+        upd(k + 1, sw * (double)ga[d][1]);
+        upd(k + 2, sw * (double)gb[d][0]);
+        upd(k + 3, sw * (double)gb[d][1]);
+      }
+      upd(K - 1, 1.0 + q0);
+      shift_fq<T, D>(fa, fb);
+      shift_fq<T, D>(ga, gb);
     }
   }
-  if (blk == 0 && threadIdx.x == 0) ctl->iter += 1;
+  if (check) block_slot11(ssq, partials, blk);
+  if (blk == 0 && threadIdx.x == 0) glob(ctl)->iter += 1;
 }
 
 // Partial sums for the residuals of Sec. 5.3 at (phi, q, alpha, beta), one
-// lane per node. Slots: 0 |A phi - q|^2, 1 |A phi|^2, 2 |q|^2,
-// 3 |A^* alpha + c|^2, 5 |alpha0 - max(0, f + alpha0)|^2, 6 |alpha0|^2,
-// 7 |f|^2, 8 |alpha_bar - g|^2, 9 |alpha_bar|^2, 10 |g|^2,
-// 13 |F^*B^*beta + alpha|^2, 14 |F^*B^*beta|^2, 15 |alpha|^2, 16 <c, phi>,
-// 17 sum m^2 / r over r > 0. (4, 11, 12 are filled elsewhere.)
+// lane per spatial node over the workgroup's time slices. Slots:
+// 0 |A phi - q|^2, 1 |A phi|^2, 2 |q|^2, 3 |A^* alpha + c|^2,
+// 5 |alpha0 - max(0, f + alpha0)|^2, 6 |alpha0|^2, 7 |f|^2,
+// 8 |alpha_bar - g|^2, 9 |alpha_bar|^2, 10 |g|^2, 13 |F^*B^*beta + alpha|^2,
+// 14 |F^*B^*beta|^2, 15 |alpha|^2, 16 <c, phi>, 17 sum m^2 / r over r > 0.
+// (4, 11, 12 are filled elsewhere.)
 template <typename T, int D>
-__device__ __forceinline__ void resid_body(const Geo& g, const double* __restrict__ phi, const T* __restrict__ q,
-                                           const T* __restrict__ alpha, const T* __restrict__ beta,
-                                           const double* __restrict__ om_sp, const double* __restrict__ sw_sp,
-                                           const double* __restrict__ c_lo, const double* __restrict__ c_hi,
-                                           double* __restrict__ partials, int64_t blk) {
+__device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, const T* q_, const T* alpha_,
+                                           const T* beta_, const double* om_sp, const double* sw_sp,
+                                           const double* c_lo_, const double* c_hi_, double* __restrict__ partials,
+                                           uint32_t blk) {
   constexpr int K = 4 * D + 2;
   double s[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) s[k] = 0.0;
-  const int64_t i = blk * blockDim.x + threadIdx.x;
-  if (i < g.nb) {
-    int x[kMaxAxes];
-    node_coords<D>(g, i, x);
-    const int64_t nb = g.nb, s0 = g.stride[0];
-    const int64_t xs = i % g.nx;
-    const int t = x[0];
+  const Column c = column_of<D>(g, blk);
+  if (c.live) {
+    gp<const double> phi = glob(phi_);
+    gp<const T> q = glob(q_);
+    gp<const T> alpha = glob(alpha_);
+    gp<const T> beta = glob(beta_);
+    gp<const double> om = glob(om_sp);
+    gp<const double> swp = glob(sw_sp);
+    const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx, xs = c.xs;
     const int n0 = g.n[0];
-    // divergence residual at the node
-    double div = 0.0;
-    if (t >= 1) div += (double)alpha[i - s0] * g.inv_h[0];
-    if (t < n0) div -= (double)alpha[i] * g.inv_h[0];
+    const double oma = om[xs], swa = swp[xs];
+    double omb[kMaxAxes], swb[kMaxAxes];
 #pragma unroll
     for (int d = 1; d <= D; ++d) {
-      const T* ad = alpha + d * nb;
-      if (x[d] >= 1) div += (double)ad[i - g.stride[d]] * g.inv_h[d];
-      if (x[d] < g.n[d]) div -= (double)ad[i] * g.inv_h[d];
+      const bool in = c.x[d] < g.n[d];
+      omb[d] = in ? om[xs + (uint32_t)g.stride[d]] : 0.0;
+      swb[d] = in ? swp[xs + (uint32_t)g.stride[d]] : 0.0;
     }
-    double cc = 0.0;
-    if (t == 0) cc = c_lo[xs];
-    if (t == n0) cc = c_hi[xs];
-    div += cc;
-    s[3] += div * div;
-    s[16] += cc * (double)phi[i];
-    if (t < n0) {
-      // q0, alpha0 at the cell
-      const double g0 = ((double)phi[i + s0] - (double)phi[i]) * g.inv_h[0];
-      const double q0 = (double)q[i], a0 = (double)alpha[i];
-      s[0] += (g0 - q0) * (g0 - q0);
-      s[1] += g0 * g0;
-      s[2] += q0 * q0;
-      const double fb = (double)beta[(K - 1) * nb + i] - (double)beta[i];
-      s[13] += (fb + a0) * (fb + a0);
-      s[14] += fb * fb;
-      s[15] += a0 * a0;
-      // f(q) = q0 + omega/8 sum_{d,v} (F^d_v q_d)^2
-      double sq = 0.0;
+    uint32_t i = (uint32_t)c.t0 * nx + xs;
+    for (int t = c.t0; t < c.t1; ++t, i += nx) {
+      // divergence residual at the node
+      double div = 0.0;
+      if (t >= 1) div += (double)alpha[i - nx] * g.inv_h[0];
+      if (t < n0) div -= (double)alpha[i] * g.inv_h[0];
 #pragma unroll
       for (int d = 1; d <= D; ++d) {
-        const T* qd = q + d * nb;
-        const int64_t sd = g.stride[d];
-        if (x[d] >= 1) {
-          const double f1 = (double)qd[i - sd], f3 = (double)qd[i + s0 - sd];
-          sq += f1 * f1 + f3 * f3;
-        }
-        if (x[d] < g.n[d]) {
-          const double f2 = (double)qd[i], f4 = (double)qd[i + s0];
-          sq += f2 * f2 + f4 * f4;
-        }
+        gp<const T> ad = alpha + (size_t)d * nb;
+        if (c.x[d] >= 1) div += (double)ad[i - (uint32_t)g.stride[d]] * g.inv_h[d];
+        if (c.x[d] < g.n[d]) div -= (double)ad[i] * g.inv_h[d];
       }
-      const double f = q0 + 0.125 * om_sp[xs] * sq;
-      const double cr = a0 - fmax(0.0, f + a0);
-      s[5] += cr * cr;
-      s[6] += a0 * a0;
-      s[7] += f * f;
-    }
-#pragma unroll
-    for (int d = 1; d <= D; ++d) {
-      if (x[d] >= g.n[d]) continue;
-      const int64_t sd = g.stride[d];
-      const double gd = ((double)phi[i + sd] - (double)phi[i]) * g.inv_h[d];
-      const double qd = (double)q[d * nb + i];
-      const double ad = (double)alpha[d * nb + i];
-      s[0] += (gd - qd) * (gd - qd);
-      s[1] += gd * gd;
-      s[2] += qd * qd;
-      s[15] += ad * ad;
-      // F^*B^* beta at this point, and r_d = L_X^d L_T^*(omega alpha0)
-      const int k = 1 + 4 * (d - 1);
-      const double swa = sw_sp[xs], swb = sw_sp[xs + sd];
-      const double oma = om_sp[xs], omb = om_sp[xs + sd];
-      double fb = 0.0, r = 0.0;
+      double cc = 0.0;
+      if (t == 0) cc = glob(c_lo_)[xs];
+      if (t == n0) cc = glob(c_hi_)[xs];
+      div += cc;
+      const double ph = phi[i];
+      s[3] += div * div;
+      s[16] += cc * ph;
       if (t < n0) {
-        fb += swb * (double)beta[(k + 0) * nb + i + sd] + swa * (double)beta[(k + 1) * nb + i];
-        r += omb * (double)alpha[i + sd] + oma * (double)alpha[i];
+        // q0, alpha0 at the cell
+        const double g0 = (phi[i + nx] - ph) * g.inv_h[0];
+        const double q0 = (double)q[i], a0 = (double)alpha[i];
+        s[0] += (g0 - q0) * (g0 - q0);
+        s[1] += g0 * g0;
+        s[2] += q0 * q0;
+        const double fb = (double)beta[(size_t)(K - 1) * nb + i] - (double)beta[i];
+        s[13] += (fb + a0) * (fb + a0);
+        s[14] += fb * fb;
+        s[15] += a0 * a0;
+        // f(q) = q0 + omega/8 sum_{d,v} (F^d_v q_d)^2
+        double sq = 0.0;
+#pragma unroll
+        for (int d = 1; d <= D; ++d) {
+          gp<const T> qd = q + (size_t)d * nb;
+          const uint32_t sd = (uint32_t)g.stride[d];
+          if (c.x[d] >= 1) {
+            const double f1 = (double)qd[i - sd], f3 = (double)qd[i + nx - sd];
+            sq += f1 * f1 + f3 * f3;
+          }
+          if (c.x[d] < g.n[d]) {
+            const double f2 = (double)qd[i], f4 = (double)qd[i + nx];
+            sq += f2 * f2 + f4 * f4;
+          }
+        }
+        const double f = q0 + 0.125 * oma * sq;
+        const double cr = a0 - fmax(0.0, f + a0);
+        s[5] += cr * cr;
+        s[6] += a0 * a0;
+        s[7] += f * f;
       }
-      if (t >= 1) {
-        fb += swb * (double)beta[(k + 2) * nb + i - s0 + sd] + swa * (double)beta[(k + 3) * nb + i - s0];
-        r += omb * (double)alpha[i - s0 + sd] + oma * (double)alpha[i - s0];
+#pragma unroll
+      for (int d = 1; d <= D; ++d) {
+        if (c.x[d] >= g.n[d]) continue;
+        const uint32_t sd = (uint32_t)g.stride[d];
+        const double gd = (phi[i + sd] - ph) * g.inv_h[d];
+        const double qd = (double)q[(size_t)d * nb + i];
+        const double ad = (double)alpha[(size_t)d * nb + i];
+        s[0] += (gd - qd) * (gd - qd);
+        s[1] += gd * gd;
+        s[2] += qd * qd;
+        s[15] += ad * ad;
+        // F^*B^* beta at this point, and r_d = L_X^d L_T^*(omega alpha0)
+        const int k = 1 + 4 * (d - 1);
+        double fb = 0.0, r = 0.0;
+        if (t < n0) {
+          fb += swb[d] * (double)beta[(size_t)(k + 0) * nb + i + sd] + swa * (double)beta[(size_t)(k + 1) * nb + i];
+          r += omb[d] * (double)alpha[i + sd] + oma * (double)alpha[i];
+        }
+        if (t >= 1) {
+          fb += swb[d] * (double)beta[(size_t)(k + 2) * nb + i - nx + sd] +
+                swa * (double)beta[(size_t)(k + 3) * nb + i - nx];
+          r += omb[d] * (double)alpha[i - nx + sd] + oma * (double)alpha[i - nx];
+        }
+        r *= 0.25;
+        s[13] += (fb + ad) * (fb + ad);
+        s[14] += fb * fb;
+        const double gg = r * qd;
+        s[8] += (ad - gg) * (ad - gg);
+        s[9] += ad * ad;
+        s[10] += gg * gg;
+        if (r > 0.0) s[17] += ad * ad / r;
       }
-      r *= 0.25;
-      s[13] += (fb + ad) * (fb + ad);
-      s[14] += fb * fb;
-      const double gg = r * qd;
-      s[8] += (ad - gg) * (ad - gg);
-      s[9] += ad * ad;
-      s[10] += gg * gg;
-      if (r > 0.0) s[17] += ad * ad / r;
     }
   }
-  block_partials<kNumSums>(s, partials + blk * kNumSums, 11);
+  block_partials<kNumSums>(s, partials + (size_t)blk * kNumSums, 11);
 }
 
 // Scalars the finalize step needs besides the partials.
@@ -452,51 +701,42 @@ __device__ __forceinline__ void cone_out_body(const Geo& g, const T* __restrict_
   for (int k = 0; k < K; ++k) z[k * nb + i] = (T)u[k];
 }
 
-// |z - B F q - d|^2 block sums into partials slot 11 (z given).
+// |z - B F q - d|^2 block sums into partials slot 11 (z given), over the
+// same workgroups as the residual sweep.
 template <typename T, int D>
-__device__ __forceinline__ void zres_body(const Geo& g, const T* __restrict__ z, const T* __restrict__ q,
-                                          const double* __restrict__ sw_sp, double* __restrict__ partials,
-                                          int64_t blk) {
+__device__ __forceinline__ void zres_body(const Geo& g, const T* z_, const T* q_, const double* sw_sp,
+                                          double* __restrict__ partials, uint32_t blk) {
   constexpr int K = 4 * D + 2;
-  const int64_t i = blk * blockDim.x + threadIdx.x;
+  const Column c = column_of<D>(g, blk);
+  const int tend = min(c.t1, g.n[0]);
   double ssq = 0.0;
-  if (i < (int64_t)g.n[0] * g.stride[0]) {
-    int x[kMaxAxes];
-    node_coords<D>(g, i, x);
-    const int64_t nb = g.nb;
-    const double sw = sw_sp[i % g.nx];
-    const double q0 = (double)q[i];
-    double r0 = (double)z[i] - (1.0 - q0);
-    double rl = (double)z[(K - 1) * nb + i] - (1.0 + q0);
-    ssq = r0 * r0 + rl * rl;
+  if (c.live) {
+    gp<const T> z = glob(z_);
+    gp<const T> q = glob(q_);
+    const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+    const double sw = glob(sw_sp)[c.xs];
+    uint32_t i = (uint32_t)c.t0 * nx + c.xs;
+    for (int t = c.t0; t < tend; ++t, i += nx) {
+      T fa[kMaxAxes][2], fb[kMaxAxes][2];
+      load_fq<T, D>(g, q, i, c, fa);
+      load_fq<T, D>(g, q, i + nx, c, fb);
+      const double q0 = (double)q[i];
+      const double r0 = (double)z[i] - (1.0 - q0);
+      const double rl = (double)z[(size_t)(K - 1) * nb + i] - (1.0 + q0);
+      ssq += r0 * r0 + rl * rl;
 #pragma unroll
-    for (int d = 1; d <= D; ++d) {
-      const T* qd = q + d * nb;
-      const bool lo = x[d] >= 1, hi = x[d] < g.n[d];
-      const int64_t sd = g.stride[d], s0 = g.stride[0];
-      const int k = 1 + 4 * (d - 1);
-      const double f[4] = {lo ? (double)qd[i - sd] : 0.0, hi ? (double)qd[i] : 0.0,
-                           lo ? (double)qd[i + s0 - sd] : 0.0, hi ? (double)qd[i + s0] : 0.0};
+      for (int d = 1; d <= D; ++d) {
+        const int k = 1 + 4 * (d - 1);
+        const double f[4] = {(double)fa[d][0], (double)fa[d][1], (double)fb[d][0], (double)fb[d][1]};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const double r = (double)z[(k + v) * nb + i] - sw * f[v];
-        ssq += r * r;
+        for (int v = 0; v < 4; ++v) {
+          const double r = (double)z[(size_t)(k + v) * nb + i] - sw * f[v];
+          ssq += r * r;
+        }
       }
     }
   }
-  double s[1] = {ssq};
-  __shared__ double red1[16];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double v = s[0];
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  if (lane == 0) red1[w] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (int j = 0; j < nw; ++j) tot += red1[j];
-    partials[blk * kNumSums + 11] = tot;
-  }
+  block_slot11(ssq, partials, blk);
 }
 
 }  // namespace dot

@@ -20,23 +20,28 @@ def sizes(D: int, n: Sequence[int]) -> Dict[str, int]:
 
 
 def kernel_bytes(D: int, n: Sequence[int], w: int) -> Dict[str, float]:
-    """Compulsory bytes per launch of each kernel class."""
+    """Compulsory bytes per launch of each kernel class; w is the bulk scalar
+    size (8 FP64, 4 mixed); phi is always FP64 (8 bytes per node)."""
     z = sizes(D, n)
     Nc, S, Q, Qb, K = z["Nc"], z["S"], z["Q"], z["Qbar"], z["K"]
+    mixed = w != 8
+    last_inv = (w + 16) * Nc if mixed else 2 * w * Nc  # time-axis inverse adds into phi (mixed)
     return {
-        # divergence of (q, alpha) fused into the time-axis forward pass
-        "dct_first": w * (2 * Q + Nc),
-        "dct_mid": w * 2 * Nc,
-        "dct_last": w * 2 * Nc,
-        "dct_inv": w * 2 * Nc,
+        # b (FP64) or b - A^*A phi (mixed): read q, alpha (and phi); write the work plane
+        "rhs": w * (2 * Q + Nc) + (8 * Nc if mixed else 0),
+        "dct_first": 2 * w * Nc,
+        "dct_mid": 2 * w * Nc,
+        "dct_last": 2 * w * Nc,
+        # D launches: D-1 plain inverse passes and the time-axis one
+        "dct_inv": ((D - 1) * 2 * w * Nc + last_inv) / D,
         # cone: read q, beta, phi, alpha0; write q0_new, alpha0, 4D weighted w planes
-        "cone": w * (Q + K * S + Nc + S + 2 * S + 4 * D * S),
+        "cone": w * (Q + K * S + S + 2 * S + 4 * D * S) + 8 * Nc,
         # q_d: read phi, alpha_d, w planes; write q_d, alpha_d
-        "qd": w * (Nc + Qb + 4 * D * S + 2 * Qb),
+        "qd": w * (Qb + 4 * D * S + 2 * Qb) + 8 * Nc,
         # beta: read q_old, q_new, beta; write beta
         "beta": w * (2 * Q + 2 * K * S),
         # residual partials: read phi, q, alpha, beta
-        "resid": w * (Nc + 2 * Q + K * S),
+        "resid": w * (2 * Q + K * S) + 8 * Nc,
         "final": 0.0,
     }
 
@@ -50,5 +55,5 @@ def iteration_min_bytes(D: int, n: Sequence[int], w: int) -> float:
 
 
 def launches_per_iteration(D: int) -> Dict[str, int]:
-    return {"dct_first": 1, "dct_mid": max(D - 1, 0), "dct_last": 1, "dct_inv": D,
+    return {"rhs": 1, "dct_first": 1, "dct_mid": max(D - 1, 0), "dct_last": 1, "dct_inv": D,
             "cone": 1, "qd": 1, "beta": 1}

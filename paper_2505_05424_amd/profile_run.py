@@ -4,8 +4,10 @@ counter collection:
   rocprofv3 --kernel-trace --stats --output-format csv -d OUT -- \
       python3 -m paper_2505_05424_amd.profile_run --workload 2d-32x64x64 --iters 500
 
-Workloads: 1d-16x32, 2d-32x64x64, 2d-64x256x256 (add --mixed for the
-mixed-precision mode)."""
+Workloads: 1d-16x32, 2d-32x64x64, 2d-64x256x256, 3d-32x64x64x64 (add
+--mixed for the mixed-precision mode). --copy-mib M first runs one plain
+device-to-device copy of M MiB (torch), the calibration of the HBM byte
+counters."""
 import argparse
 import os
 import sys
@@ -21,17 +23,27 @@ WORKLOADS = {
     "1d-16x32": dotgen.config1_instance,
     "2d-32x64x64": dotgen.config2_instance,
     "2d-64x256x256": dotgen.config3_instance,
+    "3d-32x64x64x64": dotgen.serving_3d_instance,
 }
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", action="append", required=True)
+    ap.add_argument("--workload", action="append", default=[])
+    ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--iters", type=int, action="append")
     ap.add_argument("--mixed", action="store_true")
     a = ap.parse_args()
     import torch
     st = torch.cuda.current_stream().cuda_stream
+    if a.copy_mib:
+        nbytes = a.copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy {nbytes} bytes", flush=True)
+        del src, dst
     iters = a.iters or [100] * len(a.workload)
     for name, its in zip(a.workload, iters):
         inst = WORKLOADS[name]()
