@@ -246,6 +246,11 @@ bool axis_fits(int L) {
   return items <= MfmaOps<T>::kItems * kMaxWaves;
 }
 
+// Dynamic LDS of a transform pass over an axis of L points: the tile of
+// kCW columns (row stride kCW + 1) and, behind it, the eigenvalue tables of the
+// scale pass (L rows, kCW columns).
+size_t pass_smem(int L, int scalar_bytes) { return ((size_t)L * (kCW + 1) + L + kCW) * scalar_bytes; }
+
 double axis_eig(int N, int nseg, int k) {
   const double s = std::sin(M_PI * k / (2.0 * N));
   return 4.0 * (double)nseg * (double)nseg * s * s;
@@ -626,7 +631,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = P->d_zero_map;
     E.grid_axis[a] = (unsigned)P->tiles[a];
-    E.smem_axis[a] = (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes;
+    E.smem_axis[a] = pass_smem(P->g.N[a], P->scalar_bytes);
     E.waves_axis[a] = P->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], P->tiles[a])
                                                : pass_waves<float>(P->g.N[a], P->tiles[a]);
   }
@@ -927,7 +932,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   int max_smem = 0;
   HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
   for (int a = 0; a <= D; ++a) {
-    const size_t need = (size_t)g.N[a] * (kCW + 1) * P->scalar_bytes;
+    const size_t need = pass_smem(g.N[a], P->scalar_bytes);
     const bool fits = P->precision == DOT_FP64 ? axis_fits<double>(g.N[a]) : axis_fits<float>(g.N[a]);
     if ((int64_t)need > max_smem || !fits)
       return fail(DOT_EINVAL, "axis of " + std::to_string(g.N[a]) + " nodes exceeds the transform tile capacity");
@@ -1172,7 +1177,7 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
     for (int i = 0; i < count; ++i) {
       dot_plan* P = B->plans[i];
       maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)i);
-      smem = std::max(smem, (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes);
+      smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes));
       waves = std::max(waves, B->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], all_tiles)
                                                        : pass_waves<float>(P->g.N[a], all_tiles));
     }
@@ -1414,7 +1419,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
       dot_plan* P = r->plan;
       maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)k);
       ++k;
-      smem = std::max(smem, (size_t)P->g.N[a] * (kCW + 1) * P->scalar_bytes);
+      smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes));
       waves = std::max(waves, pass_waves<T>(P->g.N[a], all_tiles));
     }
     E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);

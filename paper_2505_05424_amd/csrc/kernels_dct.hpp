@@ -262,6 +262,18 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
   const int64_t inner = pa.inner;
   const int64_t ncols = pa.ncols;
 
+  if (KIND == kFwdScaleInv) {
+    // stage the eigenvalue tables of this tile behind it in LDS (read after
+    // the forward transform, so their latency hides behind the tile load)
+    T* lam_r = tile + L * (kCW + 1);
+    T* lam_c = lam_r + L;
+    for (int e = threadIdx.x; e < L + kCW; e += blockDim.x) {
+      if (e < L)
+        lam_r[e] = glob(lam_last)[e];
+      else
+        lam_c[e - L] = c0 + (e - L) < ncols ? glob(lam_other)[c0 + (e - L)] : T(0);
+    }
+  }
   // load (32-bit index math: planes hold fewer than 2^31 elements). Each wave
   // issues kLoadBatch independent loads before writing them to the tile, so
   // the global-memory latency is paid once per batch, not once per row.
@@ -320,12 +332,16 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
 
   if (KIND == kFwd || KIND == kFwdScaleInv) tile_forward(tile, a);
   if (KIND == kFwdScaleInv) {
+    // eigenvalue sums Lambda = lam_other[column] + lam_last[row] from the
+    // copies staged in LDS at entry
+    const T* lam_r = tile + L * (kCW + 1);
+    const T* lam_c = lam_r + L;
     for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
       const int k = e / kCW, cl = e % kCW;
       const int64_t c = c0 + cl;
       T s = T(0);
       if (c < ncols) {
-        const T lam = glob(lam_other)[c] + glob(lam_last)[k];
+        const T lam = lam_c[cl] + lam_r[k];
         s = lam > T(0) ? T(1) / lam : T(0);  // mode (0,...,0): phi in rge A^*
       }
       tile[k * (kCW + 1) + cl] *= s;
@@ -348,15 +364,30 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
       const uint32_t cu = (uint32_t)c;
       const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
       const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
-      for (int j = threadIdx.x >> 6; j < L; j += nw) {
-        const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
-        const T v = tile[j * (kCW + 1) + lane];
-        if (DST == kDstPhiAdd)
-          glob(phi)[e] += (double)v;
-        else if (DST == kDstPhiSet)
-          glob(phi)[e] = (double)v;
-        else
-          pl[e] = v;
+      if (DST == kDstPhiAdd) {
+        // read-modify-write of phi in batches (loads first, then the stores)
+        for (int j0 = threadIdx.x >> 6; j0 < L; j0 += kLoadBatch * nw) {
+          double old[kLoadBatch];
+#pragma unroll
+          for (int r = 0; r < kLoadBatch; ++r) {
+            const int j = j0 + r * nw;
+            old[r] = j < L ? glob(phi)[base + (uint32_t)j * (uint32_t)inner] : 0.0;
+          }
+#pragma unroll
+          for (int r = 0; r < kLoadBatch; ++r) {
+            const int j = j0 + r * nw;
+            if (j < L) glob(phi)[base + (uint32_t)j * (uint32_t)inner] = old[r] + (double)tile[j * (kCW + 1) + lane];
+          }
+        }
+      } else {
+        for (int j = threadIdx.x >> 6; j < L; j += nw) {
+          const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
+          const T v = tile[j * (kCW + 1) + lane];
+          if (DST == kDstPhiSet)
+            glob(phi)[e] = (double)v;
+          else
+            pl[e] = v;
+        }
       }
     }
   }
