@@ -99,19 +99,17 @@ kb_finalize(const Inst<T>* __restrict__ I, int update_ctl) {
   finalize_body(s.fa, s.partials, s.ctl, update_ctl);
 }
 
-template <typename T, int D, int KIND, int SRC, int DST>
+template <typename T, int D, int KIND, int SRC, int DST, int CW>
 __global__ void __launch_bounds__(kMaxWaves * 64)
-kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int axis, int par,
-             double sigma_arg) {
+kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int axis) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
   if (stopped(s)) return;
   PassArgs pa;
   pa.inner = s.g.stride[axis];
   pa.ncols = s.g.nb / s.g.N[axis];
-  axis_pass_body<T, D, KIND, SRC, DST>(s.g, pa, s.tab[axis], s.work, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi,
-                                       s.lam_other, s.lam_last, s.ctl, sigma_arg,
-                                       (int64_t)(L - s.tile0[axis]));
+  axis_pass_body<T, D, KIND, SRC, DST, CW>(s.g, pa, s.tab[axis], s.work, s.phi, s.lam_other, s.lam_last,
+                                           (int64_t)(L - s.tile0[axis]));
 }
 
 // ---- step-level kernels (single instance, caller pointers) ----------------

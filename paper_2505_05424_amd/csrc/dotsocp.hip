@@ -126,7 +126,8 @@ struct dot_plan {
   double vol = 1.0, c_norm2 = 0.0, d_norm2 = 0.0;
   int64_t nblocks = 0;       // workgroups of one node sweep (g.nsweep)
   int64_t partial_rows = 0;  // capacity of the partial-sum rows (nsweep at one slice per workgroup)
-  int64_t tiles[kMaxAxes] = {0, 0, 0, 0};
+  int64_t tiles[kMaxAxes] = {0, 0, 0, 0};  // transform tiles per axis at this plan's own tile width
+  int64_t lines[kMaxAxes] = {0, 0, 0, 0};  // lines per axis (nb / N[a])
   // device constant tables
   double* sw_sp = nullptr;  // sqrt(omega/2) on spatial nodes
   double* om_sp = nullptr;  // omega on spatial nodes
@@ -230,9 +231,10 @@ int build_axis(dot_plan* P, int a, void** buf, AxisTab<T>* tab) {
 // workgroups share a CU.
 constexpr int64_t kManyTiles = 1024;
 template <typename T>
-int pass_waves(int L, int64_t tiles) {
+int pass_waves(int L, int64_t tiles, int cw) {
   const int M = L / 2, ne = L - M, no = M;
-  const int items = 2 * ((ne + 15) / 16 + (no + 15) / 16);
+  const int groups = cw >= 32 ? cw / 32 : 1;  // work items per row block (see tile_mfma)
+  const int items = groups * ((ne + 15) / 16 + (no + 15) / 16);
   const int rounds = (items + MfmaOps<T>::kItems - 1) / MfmaOps<T>::kItems;
   // many tiles: small workgroups, several per CU; few tiles: spread the items
   const int w = (tiles >= kManyTiles || items > kMaxWaves) ? rounds : items;
@@ -249,7 +251,12 @@ bool axis_fits(int L) {
 // Dynamic LDS of a transform pass over an axis of L points: the tile of
 // kCW columns (row stride kCW + 1) and, behind it, the eigenvalue tables of the
 // scale pass (L rows, kCW columns).
-size_t pass_smem(int L, int scalar_bytes) { return ((size_t)L * (kCW + 1) + L + kCW) * scalar_bytes; }
+size_t pass_smem(int L, int scalar_bytes, int cw) { return ((size_t)L * (cw + 1) + L + cw) * scalar_bytes; }
+
+// Tile width of a transform launch over `lines` lines in all: the wide tile
+// when that still gives many workgroups, else the narrow one.
+int choose_cw(int64_t lines) { return (lines + kCW - 1) / kCW >= kManyTiles ? kCW : kCWNarrow; }
+int64_t tiles_for(int64_t lines, int cw) { return (lines + cw - 1) / cw; }
 
 double axis_eig(int N, int nseg, int k) {
   const double s = std::sin(M_PI * k / (2.0 * N));
@@ -383,6 +390,7 @@ struct Exec {
   unsigned grid_axis[kMaxAxes] = {0, 0, 0, 0};
   size_t smem_axis[kMaxAxes] = {0, 0, 0, 0};
   int waves_axis[kMaxAxes] = {0, 0, 0, 0};
+  int cw_axis[kMaxAxes] = {kCW, kCW, kCW, kCW};  // transform tile width per axis
   Prof* prof = nullptr;
   int device = 0;
   struct GraphCache* graphs = nullptr;  // captured 10-iteration blocks (nullptr: plain launches)
@@ -396,9 +404,9 @@ int set_max_lds(const void* fn, int device) {
   return DOT_OK;
 }
 
-template <typename T, int D, int KIND, int SRC, int DST>
-int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
-  auto fn = kb_axis_pass<T, D, KIND, SRC, DST>;
+template <typename T, int D, int KIND, int SRC, int DST, int CW>
+int launch_pass_cw(const Exec& E, int a, hipStream_t st) {
+  auto fn = kb_axis_pass<T, D, KIND, SRC, DST, CW>;
   // the LDS opt-in is per kernel and process: set once (thread-safe static)
   static const int smem_rc = set_max_lds((const void*)fn, E.device);
   if (smem_rc) return smem_rc;
@@ -407,9 +415,17 @@ int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
                                          : (a == 0 ? DOT_K_DCT_FIRST : DOT_K_DCT_MID);
   ProfScope ps(E.prof, cls, st);
   hipLaunchKernelGGL(fn, dim3(E.grid_axis[a]), dim3(E.waves_axis[a] * 64), E.smem_axis[a], st,
-                     (const Inst<T>*)E.d_inst, E.map_axis[a], a, par, sigma);
+                     (const Inst<T>*)E.d_inst, E.map_axis[a], a);
   HIP_OK(hipGetLastError());
   return DOT_OK;
+}
+
+template <typename T, int D, int KIND, int SRC, int DST>
+int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
+  (void)par;
+  (void)sigma;
+  return E.cw_axis[a] == kCW ? launch_pass_cw<T, D, KIND, SRC, DST, kCW>(E, a, st)
+                             : launch_pass_cw<T, D, KIND, SRC, DST, kCWNarrow>(E, a, st);
 }
 
 // The 2D+1 transform passes of one Poisson solve (a3 + a4): first pass on the
@@ -630,10 +646,12 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.grid_nodes = (unsigned)P->nblocks;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = P->d_zero_map;
-    E.grid_axis[a] = (unsigned)P->tiles[a];
-    E.smem_axis[a] = pass_smem(P->g.N[a], P->scalar_bytes);
-    E.waves_axis[a] = P->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], P->tiles[a])
-                                               : pass_waves<float>(P->g.N[a], P->tiles[a]);
+    const int cw = choose_cw(P->lines[a]);
+    E.cw_axis[a] = cw;
+    E.grid_axis[a] = (unsigned)tiles_for(P->lines[a], cw);
+    E.smem_axis[a] = pass_smem(P->g.N[a], P->scalar_bytes, cw);
+    E.waves_axis[a] = P->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], E.grid_axis[a], cw)
+                                               : pass_waves<float>(P->g.N[a], E.grid_axis[a], cw);
   }
   E.prof = &P->prof;
   E.device = P->device;
@@ -848,7 +866,7 @@ int batch_descriptors(dot_batch* B, void* ws, hipStream_t st) {
     blk += (uint32_t)P->nblocks;
     for (int a = 0; a <= B->D; ++a) {
       host[i].tile0[a] = tile[a];
-      tile[a] += (uint32_t)P->tiles[a];
+      tile[a] += (uint32_t)tiles_for(P->lines[a], B->E.cw_axis[a]);
     }
   }
   HIP_OK(hipMemcpyAsync(B->d_inst, host.data(), sizeof(Inst<T>) * count, hipMemcpyHostToDevice, st));
@@ -932,11 +950,12 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   int max_smem = 0;
   HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
   for (int a = 0; a <= D; ++a) {
-    const size_t need = pass_smem(g.N[a], P->scalar_bytes);
+    const size_t need = pass_smem(g.N[a], P->scalar_bytes, kCW);
     const bool fits = P->precision == DOT_FP64 ? axis_fits<double>(g.N[a]) : axis_fits<float>(g.N[a]);
     if ((int64_t)need > max_smem || !fits)
       return fail(DOT_EINVAL, "axis of " + std::to_string(g.N[a]) + " nodes exceeds the transform tile capacity");
-    P->tiles[a] = (g.nb / g.N[a] + kCW - 1) / kCW;
+    P->lines[a] = g.nb / g.N[a];
+    P->tiles[a] = tiles_for(P->lines[a], choose_cw(P->lines[a]));
   }
   // problem data
   const int64_t nx = g.nx;
@@ -988,7 +1007,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   HIP_OK(hipHostMalloc((void**)&P->host_ctl, sizeof(Ctl), hipHostMallocDefault));
   HIP_OK(hipMalloc(&P->d_inst, 2 * inst_slot_bytes()));
   int64_t maxgrid = P->partial_rows;
-  for (int a = 0; a <= D; ++a) maxgrid = std::max(maxgrid, P->tiles[a]);
+  for (int a = 0; a <= D; ++a) maxgrid = std::max(maxgrid, tiles_for(P->lines[a], kCWNarrow));
   HIP_OK(hipMalloc((void**)&P->d_zero_map, (size_t)maxgrid * sizeof(uint16_t)));
   HIP_OK(hipMemset(P->d_zero_map, 0, (size_t)maxgrid * sizeof(uint16_t)));
   *out = P.release();
@@ -1172,14 +1191,18 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
     map_off[a] = maps.size();
     size_t smem = 0;
     int waves = 1;
+    int64_t all_lines = 0;
+    for (int i = 0; i < count; ++i) all_lines += B->plans[i]->lines[a];
+    const int cw = choose_cw(all_lines);
+    E.cw_axis[a] = cw;
     int64_t all_tiles = 0;
-    for (int i = 0; i < count; ++i) all_tiles += B->plans[i]->tiles[a];
+    for (int i = 0; i < count; ++i) all_tiles += tiles_for(B->plans[i]->lines[a], cw);
     for (int i = 0; i < count; ++i) {
       dot_plan* P = B->plans[i];
-      maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)i);
-      smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes));
-      waves = std::max(waves, B->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], all_tiles)
-                                                       : pass_waves<float>(P->g.N[a], all_tiles));
+      maps.insert(maps.end(), (size_t)tiles_for(P->lines[a], cw), (uint16_t)i);
+      smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes, cw));
+      waves = std::max(waves, B->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], all_tiles, cw)
+                                                       : pass_waves<float>(P->g.N[a], all_tiles, cw));
     }
     E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);
     E.smem_axis[a] = smem;
@@ -1383,6 +1406,12 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
     C->dirty = false;
     return DOT_OK;
   }
+  // transform tile width per axis, from the lines of all active instances
+  for (int a = 0; a <= C->D; ++a) {
+    int64_t all_lines = 0;
+    for (dot_plan* P : act) all_lines += P->lines[a];
+    E.cw_axis[a] = choose_cw(all_lines);
+  }
   // descriptors of the active instances, in slot order
   uint32_t blk = 0;
   uint32_t tile[kMaxAxes] = {0, 0, 0, 0};
@@ -1397,7 +1426,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
     blk += (uint32_t)P->nblocks;
     for (int a = 0; a <= C->D; ++a) {
       s.tile0[a] = tile[a];
-      tile[a] += (uint32_t)P->tiles[a];
+      tile[a] += (uint32_t)tiles_for(P->lines[a], E.cw_axis[a]);
     }
     host.push_back(s);
     maps.insert(maps.end(), (size_t)P->nblocks, (uint16_t)idx);
@@ -1410,17 +1439,17 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
     map_off[a] = maps.size();
     size_t smem = 0;
     int waves = 1, k = 0;
+    const int cw = E.cw_axis[a];
     int64_t all_tiles = 0;
-    for (int sl = 0; sl < C->max_slots; ++sl)
-      if (C->slots[sl]) all_tiles += C->slots[sl]->plan->tiles[a];
+    for (dot_plan* P : act) all_tiles += tiles_for(P->lines[a], cw);
     for (int sl = 0; sl < C->max_slots; ++sl) {
       Request* r = C->slots[sl];
       if (!r) continue;
       dot_plan* P = r->plan;
-      maps.insert(maps.end(), (size_t)P->tiles[a], (uint16_t)k);
+      maps.insert(maps.end(), (size_t)tiles_for(P->lines[a], cw), (uint16_t)k);
       ++k;
-      smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes));
-      waves = std::max(waves, pass_waves<T>(P->g.N[a], all_tiles));
+      smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes, cw));
+      waves = std::max(waves, pass_waves<T>(P->g.N[a], all_tiles, cw));
     }
     E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);
     E.smem_axis[a] = smem;

@@ -16,7 +16,8 @@
 
 namespace dot {
 
-constexpr int kCW = 64;        // lines per tile
+constexpr int kCW = 64;        // lines per tile (launches with many tiles)
+constexpr int kCWNarrow = 16;  // lines per tile (launches with few tiles: 4x the workgroups)
 constexpr int kMaxWaves = 16;  // waves per workgroup (upper bound)
 constexpr int kU = 8;          // k-steps per prefetch chunk
 constexpr int kLoadBatch = 8;  // rows a wave loads before writing them to the tile
@@ -90,26 +91,30 @@ __device__ __forceinline__ int out_slot(bool inv, bool odd, int L, int r) {
   return inv ? (odd ? L - 1 - r : r) : (odd ? 2 * r + 1 : 2 * r);
 }
 
-// Both half-size products of one direction on the tile; results are written
-// back into the tile (natural order after a forward pass; E/O slots after an
-// inverse pass, combined by the caller).
-template <typename T>
+// Both half-size products of one direction on a tile of CW columns; results
+// are written back into the tile (natural order after a forward pass; E/O
+// slots after an inverse pass, combined by the caller). A work item is one
+// 16-row block of a half matrix times 16 * NACC columns (NACC accumulators
+// sharing the coefficient fragments).
+template <typename T, int CW>
 __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv) {
   typedef typename MfmaOps<T>::acc_t acc_t;
   constexpr int KI = MfmaOps<T>::kItems;
+  constexpr int NACC = CW >= 32 ? 2 : 1;
+  constexpr int NG = CW / (16 * NACC);  // column groups per row block
   const int lane = threadIdx.x & 63;
   const int w = wave_id();
   const int nwaves = blockDim.x >> 6;
-  const int nitems = 2 * (a.rb_e + a.rb_o);  // (row block, 32-column group)
+  const int nitems = NG * (a.rb_e + a.rb_o);
   const int L = a.L;
-  acc_t acc[KI][2];
+  acc_t acc[KI][NACC];
 #pragma unroll
   for (int b = 0; b < KI; ++b) {
-    acc[b][0] = acc_t{0, 0, 0, 0};
-    acc[b][1] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int h = 0; h < NACC; ++h) acc[b][h] = acc_t{0, 0, 0, 0};
     const int it = w + b * nwaves;
     if (it >= nitems) continue;
-    const int rbi = it >> 1, g = it & 1;
+    const int rbi = it / NG, g = it % NG;
     const bool odd = rbi >= a.rb_e;
     const int m = odd ? rbi - a.rb_e : rbi;
     const int ks = odd ? a.ks_o : a.ks_e;
@@ -118,27 +123,27 @@ __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv
     gp<const chunk_t> tp = (gp<const chunk_t>)reinterpret_cast<const chunk_t*>(inv ? (odd ? a.io : a.ie)
                                                                                   : (odd ? a.fo : a.fe)) +
                            (size_t)m * (ks / kU + 1) * 64 + lane;
-    const int col = g * 32 + (lane & 15);
+    const int col = g * 16 * NACC + (lane & 15);
     // coefficient fragments are prefetched one chunk of kU k-steps ahead
     chunk_t cur = tp[0];
     for (int st = 0; st < ks; st += kU) {
       const chunk_t nxt = tp[(st / kU + 1) * 64];
       // keep the prefetch ahead of this chunk's LDS reads and MFMAs
       __builtin_amdgcn_sched_barrier(0);
-      T b0[kU], b1[kU];
+      T bv[NACC][kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         int k = (st + u) * 4 + (lane >> 4);
         k = k < nin ? k : nin - 1;  // padded inputs: zero coefficient, any finite value
-        const int sl = in_slot(inv, odd, L, k) * (kCW + 1) + col;
-        b0[u] = tile[sl];
-        b1[u] = tile[sl + 16];
+        const int sl = in_slot(inv, odd, L, k) * (CW + 1) + col;
+#pragma unroll
+        for (int h = 0; h < NACC; ++h) bv[h][u] = tile[sl + 16 * h];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        acc[b][0] = MfmaOps<T>::mma(cur[u], b0[u], acc[b][0]);
-        acc[b][1] = MfmaOps<T>::mma(cur[u], b1[u], acc[b][1]);
+#pragma unroll
+        for (int h = 0; h < NACC; ++h) acc[b][h] = MfmaOps<T>::mma(cur[u], bv[h][u], acc[b][h]);
       }
       cur = nxt;
     }
@@ -148,18 +153,18 @@ __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv
   for (int b = 0; b < KI; ++b) {
     const int it = w + b * nwaves;
     if (it >= nitems) continue;
-    const int rbi = it >> 1, g = it & 1;
+    const int rbi = it / NG, g = it % NG;
     const bool odd = rbi >= a.rb_e;
     const int m = odd ? rbi - a.rb_e : rbi;
     const int nout = odd ? a.no : a.ne;
-    const int col = g * 32 + (lane & 15);
+    const int col = g * 16 * NACC + (lane & 15);
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int r = m * 16 + MfmaOps<T>::out_row(lane, v);
       if (r < nout) {
-        const int sl = out_slot(inv, odd, L, r) * (kCW + 1) + col;
-        tile[sl] = acc[b][0][v];
-        tile[sl + 16] = acc[b][1][v];
+        const int sl = out_slot(inv, odd, L, r) * (CW + 1) + col;
+#pragma unroll
+        for (int h = 0; h < NACC; ++h) tile[sl + 16 * h] = acc[b][h][v];
       }
     }
   }
@@ -168,33 +173,33 @@ __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv
 
 // Forward transform of the tile (input x in natural order, output X in
 // natural order).
-template <typename T>
+template <typename T, int CW>
 __device__ __forceinline__ void tile_forward(T* tile, const AxisTab<T>& a) {
   const int L = a.L, M = a.M;
-  for (int p = threadIdx.x; p < M * kCW; p += blockDim.x) {
-    const int j = p / kCW, c = p % kCW;
-    const T x0 = tile[j * (kCW + 1) + c];
-    const T x1 = tile[(L - 1 - j) * (kCW + 1) + c];
-    tile[j * (kCW + 1) + c] = x0 + x1;            // u_j
-    tile[(L - 1 - j) * (kCW + 1) + c] = x0 - x1;  // v_j
+  for (int p = threadIdx.x; p < M * CW; p += blockDim.x) {
+    const int j = p / CW, c = p % CW;
+    const T x0 = tile[j * (CW + 1) + c];
+    const T x1 = tile[(L - 1 - j) * (CW + 1) + c];
+    tile[j * (CW + 1) + c] = x0 + x1;            // u_j
+    tile[(L - 1 - j) * (CW + 1) + c] = x0 - x1;  // v_j
   }
   __syncthreads();
-  tile_mfma(tile, a, false);
+  tile_mfma<T, CW>(tile, a, false);
 }
 
 // Inverse transform (DCT-III, the transpose) of the tile, natural order in
 // and out: E_j = sum_k' C[2k'][j] X_{2k'}, O_j = sum_k' C[2k'+1][j] X_{2k'+1},
 // x_j = E_j + O_j, x_{L-1-j} = E_j - O_j.
-template <typename T>
+template <typename T, int CW>
 __device__ __forceinline__ void tile_inverse(T* tile, const AxisTab<T>& a) {
   const int L = a.L, M = a.M;
-  tile_mfma(tile, a, true);
-  for (int p = threadIdx.x; p < M * kCW; p += blockDim.x) {
-    const int j = p / kCW, c = p % kCW;
-    const T e = tile[j * (kCW + 1) + c];
-    const T o = tile[(L - 1 - j) * (kCW + 1) + c];
-    tile[j * (kCW + 1) + c] = e + o;
-    tile[(L - 1 - j) * (kCW + 1) + c] = e - o;
+  tile_mfma<T, CW>(tile, a, true);
+  for (int p = threadIdx.x; p < M * CW; p += blockDim.x) {
+    const int j = p / CW, c = p % CW;
+    const T e = tile[j * (CW + 1) + c];
+    const T o = tile[(L - 1 - j) * (CW + 1) + c];
+    tile[j * (CW + 1) + c] = e + o;
+    tile[(L - 1 - j) * (CW + 1) + c] = e - o;
   }
   __syncthreads();
 }
@@ -245,149 +250,149 @@ struct PassArgs {
   int64_t ncols;   // number of lines = outer * inner
 };
 
-// One axis pass over a plane, in place. SRC != kSrcPlane and DST != kDstPlane
-// occur on the time axis only (first forward / last inverse pass). KIND =
-// kFwdScaleInv (last axis only) applies forward, 1/Lambda, inverse.
-template <typename T, int D, int KIND, int SRC, int DST>
+// One axis pass over a plane, in place, on tiles of CW lines. SRC and DST
+// other than kSrcPlane / kDstPlane occur on the time axis only (first forward
+// / last inverse pass). KIND = kFwdScaleInv (last axis only) applies forward,
+// 1/Lambda, inverse.
+template <typename T, int D, int KIND, int SRC, int DST, int CW>
 __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa, const AxisTab<T>& a,
-                                               T* __restrict__ plane, const T* __restrict__ q,
-                                               const T* __restrict__ al, double* __restrict__ phi,
-                                               const double* __restrict__ c_lo, const double* __restrict__ c_hi,
+                                               T* __restrict__ plane, double* __restrict__ phi,
                                                const T* __restrict__ lam_other, const T* __restrict__ lam_last,
-                                               const Ctl* __restrict__ ctl, double sigma_arg, int64_t blk) {
+                                               int64_t blk) {
   extern __shared__ unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
   const int L = a.L;
-  const int64_t c0 = blk * kCW;
-  const int64_t inner = pa.inner;
+  const int64_t c0 = blk * CW;
+  const uint32_t inner = (uint32_t)pa.inner;
   const int64_t ncols = pa.ncols;
-
+  gp<T> pl = glob(plane);
+  gp<double> ph = glob(phi);
+  const int tot = L * CW;
   if (KIND == kFwdScaleInv) {
     // stage the eigenvalue tables of this tile behind it in LDS (read after
     // the forward transform, so their latency hides behind the tile load)
-    T* lam_r = tile + L * (kCW + 1);
+    T* lam_r = tile + L * (CW + 1);
     T* lam_c = lam_r + L;
-    for (int e = threadIdx.x; e < L + kCW; e += blockDim.x) {
+    for (int e = threadIdx.x; e < L + CW; e += blockDim.x) {
       if (e < L)
         lam_r[e] = glob(lam_last)[e];
       else
         lam_c[e - L] = c0 + (e - L) < ncols ? glob(lam_other)[c0 + (e - L)] : T(0);
     }
   }
-  // load (32-bit index math: planes hold fewer than 2^31 elements). Each wave
-  // issues kLoadBatch independent loads before writing them to the tile, so
-  // the global-memory latency is paid once per batch, not once per row.
-  gp<T> pl = glob(plane);
-  const int nw = blockDim.x >> 6;
-  const int lane = threadIdx.x & 63;
+  // Loads and stores use 32-bit index math (planes hold at most 2^28
+  // elements). Lines along the last axis (inner == 1) are contiguous and are
+  // walked line by line; strided lines (column c = o * inner + ii) give each
+  // thread one fixed tile column (blockDim is a multiple of CW) and a row
+  // stride, so CW consecutive columns of a row are consecutive in memory.
+  const int nthr = blockDim.x;
+  const int my_cl = threadIdx.x % CW, row0 = threadIdx.x / CW, rstep = nthr / CW;
+  uint32_t cbase = 0;
+  bool cok = false;
+  if (inner != 1) {
+    const int64_t c = c0 + my_cl;
+    cok = c < ncols;
+    const uint32_t cu = (uint32_t)c;
+    const uint32_t o = cu / inner, ii = cu - o * inner;
+    cbase = o * (uint32_t)L * inner + ii;
+  }
+  const uint32_t lbase = (uint32_t)c0 * (uint32_t)L;
+  const uint32_t llim = (uint32_t)ncols * (uint32_t)L;
+  // load: each thread issues kLoadBatch independent loads before writing
+  // them to the tile, so the memory latency is paid once per batch
   if (inner == 1) {
-    const uint32_t base = (uint32_t)c0 * (uint32_t)L;
-    const uint32_t lim = (uint32_t)ncols * (uint32_t)L;
-    const int tot = L * kCW;
-    for (int e0 = threadIdx.x; e0 < tot; e0 += kLoadBatch * blockDim.x) {
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kLoadBatch * nthr) {
       T v[kLoadBatch];
 #pragma unroll
       for (int r = 0; r < kLoadBatch; ++r) {
-        const int e = e0 + r * blockDim.x;
-        v[r] = (e < tot && base + e < lim) ? pl[base + e] : T(0);
+        const int e = e0 + r * nthr;
+        v[r] = (e < tot && lbase + e < llim) ? (SRC == kSrcPlaneF64 ? (T)ph[lbase + e] : pl[lbase + e]) : T(0);
       }
 #pragma unroll
       for (int r = 0; r < kLoadBatch; ++r) {
-        const int e = e0 + r * blockDim.x;
+        const int e = e0 + r * nthr;
         if (e < tot) {
           const int cl = e / L, j = e - cl * L;
-          tile[j * (kCW + 1) + cl] = v[r];
+          tile[j * (CW + 1) + cl] = v[r];
         }
       }
     }
   } else {
-    // one column per lane, rows spread over the waves
-    const int64_t c = c0 + lane;
-    const bool ok = c < ncols;
-    const uint32_t cu = (uint32_t)c;
-    const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
-    const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
-    for (int j0 = threadIdx.x >> 6; j0 < L; j0 += kLoadBatch * nw) {
+    for (int j0 = row0; j0 < L; j0 += kLoadBatch * rstep) {
       T v[kLoadBatch];
 #pragma unroll
       for (int r = 0; r < kLoadBatch; ++r) {
-        const int j = j0 + r * nw;
-        v[r] = T(0);
-        if (ok && j < L) {
-          const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
-          if (SRC == kSrcPlaneF64)
-            v[r] = (T)glob(phi)[e];
-          else
-            v[r] = pl[e];
-        }
+        const int j = j0 + r * rstep;
+        const uint32_t o = cbase + (uint32_t)j * inner;
+        v[r] = (cok && j < L) ? (SRC == kSrcPlaneF64 ? (T)ph[o] : pl[o]) : T(0);
       }
 #pragma unroll
       for (int r = 0; r < kLoadBatch; ++r) {
-        const int j = j0 + r * nw;
-        if (j < L) tile[j * (kCW + 1) + lane] = v[r];
+        const int j = j0 + r * rstep;
+        if (j < L) tile[j * (CW + 1) + my_cl] = v[r];
       }
     }
   }
   __syncthreads();
 
-  if (KIND == kFwd || KIND == kFwdScaleInv) tile_forward(tile, a);
+  if (KIND == kFwd || KIND == kFwdScaleInv) tile_forward<T, CW>(tile, a);
   if (KIND == kFwdScaleInv) {
     // eigenvalue sums Lambda = lam_other[column] + lam_last[row] from the
     // copies staged in LDS at entry
-    const T* lam_r = tile + L * (kCW + 1);
+    const T* lam_r = tile + L * (CW + 1);
     const T* lam_c = lam_r + L;
-    for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
-      const int k = e / kCW, cl = e % kCW;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) {
+      const int k = e / CW, cl = e % CW;
       const int64_t c = c0 + cl;
       T s = T(0);
       if (c < ncols) {
         const T lam = lam_c[cl] + lam_r[k];
         s = lam > T(0) ? T(1) / lam : T(0);  // mode (0,...,0): phi in rge A^*
       }
-      tile[k * (kCW + 1) + cl] *= s;
+      tile[k * (CW + 1) + cl] *= s;
     }
     __syncthreads();
   }
-  if (KIND == kInv || KIND == kFwdScaleInv) tile_inverse(tile, a);
+  if (KIND == kInv || KIND == kFwdScaleInv) tile_inverse<T, CW>(tile, a);
 
-  // store
+  // store (phi += result in batches: loads first, then the stores)
+  auto put = [&](uint32_t o, T v, double old) {
+    if (DST == kDstPhiAdd)
+      ph[o] = old + (double)v;
+    else if (DST == kDstPhiSet)
+      ph[o] = (double)v;
+    else
+      pl[o] = v;
+  };
   if (inner == 1) {
-    const uint32_t base = (uint32_t)c0 * (uint32_t)L;
-    const uint32_t lim = (uint32_t)ncols * (uint32_t)L;
-    for (int e = threadIdx.x; e < L * kCW; e += blockDim.x) {
-      const int cl = e / L, j = e - cl * L;
-      if (base + e < lim) pl[base + e] = tile[j * (kCW + 1) + cl];
+    for (int e0 = threadIdx.x; e0 < tot; e0 += kLoadBatch * nthr) {
+      double old[kLoadBatch];
+#pragma unroll
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int e = e0 + r * nthr;
+        old[r] = (DST == kDstPhiAdd && e < tot && lbase + e < llim) ? ph[lbase + e] : 0.0;
+      }
+#pragma unroll
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int e = e0 + r * nthr;
+        if (e < tot && lbase + e < llim) {
+          const int cl = e / L, j = e - cl * L;
+          put(lbase + e, tile[j * (CW + 1) + cl], old[r]);
+        }
+      }
     }
-  } else {
-    const int64_t c = c0 + lane;
-    if (c < ncols) {
-      const uint32_t cu = (uint32_t)c;
-      const uint32_t o = cu / (uint32_t)inner, ii = cu - o * (uint32_t)inner;
-      const uint32_t base = o * (uint32_t)L * (uint32_t)inner + ii;
-      if (DST == kDstPhiAdd) {
-        // read-modify-write of phi in batches (loads first, then the stores)
-        for (int j0 = threadIdx.x >> 6; j0 < L; j0 += kLoadBatch * nw) {
-          double old[kLoadBatch];
+  } else if (cok) {
+    for (int j0 = row0; j0 < L; j0 += kLoadBatch * rstep) {
+      double old[kLoadBatch];
 #pragma unroll
-          for (int r = 0; r < kLoadBatch; ++r) {
-            const int j = j0 + r * nw;
-            old[r] = j < L ? glob(phi)[base + (uint32_t)j * (uint32_t)inner] : 0.0;
-          }
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int j = j0 + r * rstep;
+        old[r] = (DST == kDstPhiAdd && j < L) ? ph[cbase + (uint32_t)j * inner] : 0.0;
+      }
 #pragma unroll
-          for (int r = 0; r < kLoadBatch; ++r) {
-            const int j = j0 + r * nw;
-            if (j < L) glob(phi)[base + (uint32_t)j * (uint32_t)inner] = old[r] + (double)tile[j * (kCW + 1) + lane];
-          }
-        }
-      } else {
-        for (int j = threadIdx.x >> 6; j < L; j += nw) {
-          const uint32_t e = base + (uint32_t)j * (uint32_t)inner;
-          const T v = tile[j * (kCW + 1) + lane];
-          if (DST == kDstPhiSet)
-            glob(phi)[e] = (double)v;
-          else
-            pl[e] = v;
-        }
+      for (int r = 0; r < kLoadBatch; ++r) {
+        const int j = j0 + r * rstep;
+        if (j < L) put(cbase + (uint32_t)j * inner, tile[j * (CW + 1) + my_cl], old[r]);
       }
     }
   }
