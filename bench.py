@@ -13,6 +13,7 @@ device) until eta_dot <= 1e-6. Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -105,6 +106,66 @@ def kernel_breakdown(plan, ptr, st):
             out[name] = {"ms_total": ms, "launches": cnt, "us_per_launch": 1e3 * ms / cnt}
     B.dot_profile_select(plan, -1)
     return out
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2505_05424_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(workload, kernel_class):
+    """HBM bytes per launch of one kernel class from the committed counter
+    summary (FETCH_SIZE / WRITE_SIZE runs scaled by a copy calibration), or
+    None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"kernels_{workload}.md")
+    try:
+        text = open(path).read()
+        blk = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blk.get("source_sha256") != kernel_sources_hash():
+        return None
+    b = blk["per_launch_bytes"].get(kernel_class)
+    if not b:
+        return None
+    return {"bytes": b["fetch"] + b["write"], "fetch": b["fetch"], "write": b["write"],
+            "copy_factor_fetch": blk["copy_factor_fetch"], "copy_factor_write": blk["copy_factor_write"],
+            "source": f"profiles/kernels_{workload}.md"}
+
+
+def large_roofline(torch, st, iters=60):
+    """Per-class HIP-event timing on the bandwidth-bound size: 2D 64x256x256,
+    mixed precision, `iters` iterations per class after a warm-up."""
+    inst = dotgen.config3_instance()
+    plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=-1.0, max_iter=10 ** 6,
+                             precision=B.DOT_MIXED)
+    buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+    B.dot_state_reset(plan, buf.data_ptr(), st)
+    B.dot_run(plan, buf.data_ptr(), 20, st)
+    kb = PM.kernel_bytes(inst.D, inst.n, 4)
+    classes = {}
+    for name, cls in B.KERNEL_CLASSES.items():
+        if name in ("resid", "final"):
+            continue
+        B.dot_profile_select(plan, cls)
+        B.dot_run(plan, buf.data_ptr(), iters, st)
+        ms, cnt = B.dot_profile_read(plan)
+        if cnt:
+            us = 1e3 * ms / cnt
+            classes[name] = {"avg_launch_us": us, "algorithmic_bytes": kb[name],
+                             "achieved_GBs": kb[name] / (us * 1e-6) / 1e9,
+                             "frac": kb[name] / (us * 1e-6) / 1e9 / PM.HBM_PEAK_GBS}
+    B.dot_profile_select(plan, -1)
+    plan.close()
+    lp = PM.launches_per_iteration(inst.D)
+    dom = max(classes, key=lambda k: classes[k]["avg_launch_us"] * lp.get(k, 1))
+    return {"workload": "2d-64x256x256-gaussmix5-mixed", "dominant": dom, "peak_GBs": PM.HBM_PEAK_GBS,
+            "classes": classes}
+
 
 
 def batched_section(torch, st, count, sample, seed=4000):
@@ -283,10 +344,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched section (0: skip)")
     ap.add_argument("--plain-sample", type=int, default=4)
-    ap.add_argument("--serve-seconds", type=float, default=45.0, help="serving arrival window (0: skip)")
-    ap.add_argument("--serve-drain", type=float, default=60.0)
-    ap.add_argument("--serve-rate", type=float, default=0.0,
-                    help="arrivals/s (0: 80%% of the batched section's solves/s)")
+    ap.add_argument("--serve-seconds", type=float, default=50.0, help="serving arrival window (0: skip)")
+    ap.add_argument("--serve-drain", type=float, default=90.0)
+    # about 80% of the serving mix's capacity on one MI355X: a 3D request
+    # (32 x 64^3, ~1.3 ms per iteration) costs ~15 GPU-seconds and an average
+    # 2D request ~1.5, so the 90/10 mix needs ~3 GPU-seconds per request
+    ap.add_argument("--serve-rate", type=float, default=0.25, help="Poisson arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -328,6 +391,9 @@ def main():
     avg_us = 1e3 * dom_ms / max(dom_cnt, 1)
     achieved = kb[dominant] / (avg_us * 1e-6) / 1e9
     it_min = PM.iteration_min_bytes(D, n, w)
+    traffic = profiled_traffic("2d_32x64x64_fp64", dominant)
+    log("roofline at 2D 64x256x256 (mixed)")
+    large = large_roofline(torch, st)
 
     out = {
         "metric": "solves/s at KKT residual 1e-6 (plain FP64, one instance)",
@@ -356,7 +422,8 @@ def main():
             "peak": PM.HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / PM.HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic["bytes"] if traffic else None,
+            "traffic_detail": traffic,
             "algorithmic_bytes_per_launch": kb[dominant],
             "avg_launch_us": avg_us,
             "launches": dom_cnt,
@@ -369,14 +436,12 @@ def main():
             "min_bytes_frac_of_hbm_peak": it_min / (el / sum(iters)) / 1e9 / PM.HBM_PEAK_GBS,
         },
         "kernel_breakdown_one_solve": breakdown,
+        "roofline_bandwidth_bound_size": large,
     }
     if args.batch > 0:
         out["batched"] = batched_section(torch, st, args.batch, args.plain_sample)
     if args.serve_seconds > 0:
-        rate = args.serve_rate
-        if rate <= 0:
-            rate = 0.8 * out["batched"]["solves_per_s"] if "batched" in out else 0.5
-        out["serving"] = serving_section(torch, rate, args.serve_seconds, args.serve_drain)
+        out["serving"] = serving_section(torch, args.serve_rate, args.serve_seconds, args.serve_drain)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(inst, iters[0], args.cpu_budget)

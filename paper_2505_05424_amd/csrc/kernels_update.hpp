@@ -383,26 +383,39 @@ __device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_,
 // across waves); the first NS threads write the block's partials, except
 // slot `skip`, which another kernel owns.
 template <int NS>
-__device__ __forceinline__ void block_partials(double (&s)[NS], double* __restrict__ out_block, int skip) {
+__device__ __forceinline__ void wave_sums(double (&s)[NS]) {
+  // butterfly over the 64 lanes; the NS sums advance together, so their
+  // cross-lane exchanges overlap instead of forming NS serial chains
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) s[k] += __shfl_xor(s[k], off, 64);
+  }
+}
+
+// The partials of an instance are slot-major: slot k of workgroup b at
+// partials[k * nsweep + b], so the finalize reads each slot coalesced.
+template <int NS>
+__device__ __forceinline__ void block_partials(double (&s)[NS], double* __restrict__ partials, uint32_t blk,
+                                               uint32_t nsweep, int skip) {
   __shared__ double red[16][NS];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  wave_sums<NS>(s);
+  if (lane == 0) {
 #pragma unroll
-  for (int k = 0; k < NS; ++k) {
-    double v = s[k];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[w][k] = v;
+    for (int k = 0; k < NS; ++k) red[w][k] = s[k];
   }
   __syncthreads();
   if (threadIdx.x < NS && (int)threadIdx.x != skip) {
     double v = 0.0;
     for (int j = 0; j < nw; ++j) v += red[j][threadIdx.x];
-    out_block[threadIdx.x] = v;
+    glob(partials)[(size_t)threadIdx.x * nsweep + blk] = v;
   }
 }
 
 // Block sum of one double into partials slot 11.
-__device__ __forceinline__ void block_slot11(double v, double* __restrict__ partials, uint32_t blk) {
+__device__ __forceinline__ void block_slot11(double v, double* __restrict__ partials, uint32_t blk,
+                                             uint32_t nsweep) {
   __shared__ double red1[16];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
@@ -412,7 +425,7 @@ __device__ __forceinline__ void block_slot11(double v, double* __restrict__ part
   if (threadIdx.x == 0) {
     double tot = 0.0;
     for (int j = 0; j < nw; ++j) tot += red1[j];
-    glob(partials)[(size_t)blk * kNumSums + 11] = tot;
+    glob(partials)[(size_t)11 * nsweep + blk] = tot;
   }
 }
 
@@ -468,7 +481,7 @@ __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_
       shift_fq<T, D>(ga, gb);
     }
   }
-  if (check) block_slot11(ssq, partials, blk);
+  if (check) block_slot11(ssq, partials, blk, g.nsweep);
   if (blk == 0 && threadIdx.x == 0) glob(ctl)->iter += 1;
 }
 
@@ -591,7 +604,7 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
       }
     }
   }
-  block_partials<kNumSums>(s, partials + (size_t)blk * kNumSums, 11);
+  block_partials<kNumSums>(s, partials, blk, g.nsweep, 11);
 }
 
 // Scalars the finalize step needs besides the partials.
@@ -614,12 +627,21 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
   __shared__ double acc[1024 / 64][kNumSums];
   __shared__ double tot[kNumSums];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int k = 0; k < kNumSums; ++k) {
-    double v = 0.0;
-    for (int64_t j = threadIdx.x; j < fa.nblocks; j += blockDim.x) v += partials[j * kNumSums + k];
+  // one pass over the workgroup partials: each thread sums every slot of its
+  // workgroups (slot-major rows, read coalesced), then the slots are reduced
+  // across the block
+  gp<const double> pr = glob(partials);
+  double v[kNumSums];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) acc[w][k] = v;
+  for (int k = 0; k < kNumSums; ++k) v[k] = 0.0;
+  for (int64_t j = threadIdx.x; j < fa.nblocks; j += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) v[k] += pr[k * fa.nblocks + j];
+  }
+  wave_sums<kNumSums>(v);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) acc[w][k] = v[k];
   }
   __syncthreads();
   if (threadIdx.x < kNumSums) {
@@ -639,42 +661,44 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
   const double p2 = sqrt(vol * tot[11]) / (1.0 + sqrt(vol * fa.d_norm2));
   const double d2 = eta_ratio(tot[13], tot[14], tot[15], vol);
   const double eps = fmax(eta_p, p2), eds = fmax(eta_d, d2);
-  ctl->eta[0] = eta_dot;
-  ctl->eta[1] = eta_p;
-  ctl->eta[2] = eta_d;
-  ctl->eta[3] = eta_c;
-  ctl->eta[4] = eps;
-  ctl->eta[5] = eds;
-  ctl->eta[6] = c1;
-  ctl->eta[7] = c2;
-  ctl->objective = -vol * tot[16];
-  ctl->dual_objective = 0.5 * vol * tot[17];
-  if (!update_ctl) return;
-  ctl->checks += 1;
-  if (!(eta_dot == eta_dot) || isinf(eta_dot)) {
-    ctl->stop = 3;
-    return;
-  }
-  if (eta_dot <= ctl->tol) {
-    ctl->stop = 1;
-    return;
-  }
-  if (ctl->adapt && ctl->iter >= ctl->next_update) {
-    const double ratio = eds > 0.0 ? eps / eds : INFINITY;
-    if (ratio > 2.0) {
-      ctl->sigma *= 1.25;
-      ctl->sigma_changes += 1;
-    } else if (ratio < 0.5) {
-      ctl->sigma /= 1.25;
-      ctl->sigma_changes += 1;
+  // work on a register copy of the control block: one load, one store
+  Ctl c = *ctl;
+  c.eta[0] = eta_dot;
+  c.eta[1] = eta_p;
+  c.eta[2] = eta_d;
+  c.eta[3] = eta_c;
+  c.eta[4] = eps;
+  c.eta[5] = eds;
+  c.eta[6] = c1;
+  c.eta[7] = c2;
+  c.objective = -vol * tot[16];
+  c.dual_objective = 0.5 * vol * tot[17];
+  if (update_ctl) {
+    c.checks += 1;
+    if (!(eta_dot == eta_dot) || isinf(eta_dot)) {
+      c.stop = 3;
+    } else if (eta_dot <= c.tol) {
+      c.stop = 1;
+    } else {
+      if (c.adapt && c.iter >= c.next_update) {
+        const double ratio = eds > 0.0 ? eps / eds : INFINITY;
+        if (ratio > 2.0) {
+          c.sigma *= 1.25;
+          c.sigma_changes += 1;
+        } else if (ratio < 0.5) {
+          c.sigma /= 1.25;
+          c.sigma_changes += 1;
+        }
+        while (c.next_update <= c.iter) {
+          const int nxt = (int)floor(c.growth * (double)c.gap) + c.cadence;
+          c.gap = nxt - nxt % c.cadence;
+          c.next_update += c.gap;
+        }
+      }
+      if (c.iter >= c.iter_limit) c.stop = 2;
     }
-    while (ctl->next_update <= ctl->iter) {
-      const int nxt = (int)floor(ctl->growth * (double)ctl->gap) + ctl->cadence;
-      ctl->gap = nxt - nxt % ctl->cadence;
-      ctl->next_update += ctl->gap;
-    }
   }
-  if (ctl->iter >= ctl->iter_limit) ctl->stop = 2;
+  *ctl = c;
 }
 
 // ---- standalone step kernels (step-level entry points) --------------------
@@ -736,7 +760,7 @@ __device__ __forceinline__ void zres_body(const Geo& g, const T* z_, const T* q_
       }
     }
   }
-  block_slot11(ssq, partials, blk);
+  block_slot11(ssq, partials, blk, g.nsweep);
 }
 
 }  // namespace dot
