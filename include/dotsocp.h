@@ -32,8 +32,9 @@
  *     beta, z  : K = 4D+2 consecutive planes, component order
  *                [1 - q0 side, (d=1,v=1..4), ..., (d=D,v=1..4), 1 + q0 side]
  *                as in eq. bdd / eq. operBF.
- *   phi and the right-hand side b are always double planes. The bulk state
- *   (q, alpha, beta, z and the cone workspace) is double in DOT_FP64 mode and
+ *   phi, the right-hand side b and the multipliers alpha (which accumulate
+ *   small updates every iteration) are always double planes. The bulk state
+ *   (q, beta, z and the cone workspace) is double in DOT_FP64 mode and
  *   float in DOT_MIXED mode (dot_plan_info.scalar_bytes); in DOT_MIXED the
  *   cosine transforms run in float on the correction of phi (defect
  *   correction: A^*A dphi = b - A^*A phi, phi += dphi, in double), while the
@@ -107,10 +108,10 @@ typedef struct {
   int32_t n[4];
   int64_t nb;             /* scalars per plane */
   int32_t scalar_bytes;   /* 8 (FP64) or 4 (MIXED bulk) */
-  int32_t n_planes;       /* bulk-type planes in the state buffer */
+  int32_t n_planes;       /* bulk-type planes in the state buffer (q, q_new, beta, W) */
   size_t state_bytes;     /* bytes the caller must provide for a state buffer */
   /* byte offsets inside a state buffer: phi (FP64 plane), transform scratch
-   * (mixed precision only), q, q_new, alpha, beta, W (bulk scalar type) */
+   * (mixed precision only), q, q_new (bulk type), alpha (double), beta, W (bulk type) */
   uint64_t off_phi, off_scratch, off_q, off_qn, off_alpha, off_beta, off_w;
 } dot_plan_info;
 
@@ -150,8 +151,8 @@ int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double
  * DCT-II on every axis, divide by the eigenvalues, zero mode set to 0 (phi in
  * rge A^*), inverse transform. */
 int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
-/* a3 + a4 as the iteration runs them (divergence fused into the first
- * transform pass): phi from (q, alpha, sigma). */
+/* a3 + a4 as the iteration runs them (right-hand side sweep, then the
+ * transform passes): phi from (q, alpha, sigma). */
 int dot_step_rhs_poisson(dot_plan* plan, const void* q, const void* alpha, double sigma,
                          void* phi, void* stream);
 /* a1 + a2: z = Pi_Q(B_omega F q + d - beta/sigma) (z-step of Algorithm 2; eq. app-proj

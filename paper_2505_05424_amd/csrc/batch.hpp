@@ -19,7 +19,7 @@ struct Inst {
   double* phi;      // FP64 potential
   T* work;          // transform work plane: phi itself (FP64) or the FP32 scratch
   T* q[2];          // q and q_new, swapped every iteration (parity argument)
-  T* alpha;
+  double* alpha;    // multipliers alpha (FP64 in both modes: they accumulate updates)
   T* beta;
   T* W;
   Ctl* ctl;         // nullptr for step-level calls (sigma from the argument)

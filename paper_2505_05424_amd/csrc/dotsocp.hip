@@ -329,10 +329,10 @@ FinArgs fin_args(const dot_plan* P) {
   return fa;
 }
 
-// Descriptor of one instance with caller planes: phi / b (FP64), q, q_new,
-// alpha, beta, W (bulk type), transform work plane, control block, partials.
+// Descriptor of one instance with caller planes: phi / b and alpha (FP64), q,
+// q_new, beta, W (bulk type), transform work plane, control block, partials.
 template <typename T>
-Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, T* alpha, T* beta, T* W, Ctl* ctl,
+Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, double* alpha, T* beta, T* W, Ctl* ctl,
                 double* partials) {
   Inst<T> s{};
   s.g = P->g;
@@ -361,7 +361,7 @@ Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, T* alpha, T
 template <typename T>
 Inst<T> state_inst(const dot_plan* P, void* state, Ctl* ctl) {
   return inst_of<T>(P, at<double>(state, P->off_phi), at<T>(state, P->off_scr), at<T>(state, P->off_q),
-                    at<T>(state, P->off_qn), at<T>(state, P->off_alpha), at<T>(state, P->off_beta),
+                    at<T>(state, P->off_qn), at<double>(state, P->off_alpha), at<T>(state, P->off_beta),
                     at<T>(state, P->off_w), ctl, at<double>(state, P->partials_offset));
 }
 
@@ -688,7 +688,7 @@ struct RunF {
 template <typename T>
 Inst<T> step_inst(dot_plan* P, const void* phi, const void* q, const void* alpha, const void* beta, void* q_out,
                   void* W, Ctl* ctl) {
-  return inst_of<T>(P, (double*)phi, (T*)P->step_scratch, (T*)q, (T*)q_out, (T*)alpha, (T*)beta, (T*)W, ctl,
+  return inst_of<T>(P, (double*)phi, (T*)P->step_scratch, (T*)q, (T*)q_out, (double*)alpha, (T*)beta, (T*)W, ctl,
                     P->step_partials);
 }
 
@@ -801,29 +801,26 @@ int validate(const dot_problem* p) {
 }
 
 int extract_impl(dot_plan* P, const void* state, double* rho_out, double* m_out, hipStream_t st) {
+  // rho = alpha0 on the cells, m_d = alpha_d on G^s_d (alpha planes are FP64)
   const Geo& g = P->g;
-  const size_t sb = P->scalar_bytes;
-  std::vector<unsigned char> buf(g.nb * sb);
-  auto get = [&](size_t i) -> double {
-    return sb == 8 ? reinterpret_cast<const double*>(buf.data())[i] : reinterpret_cast<const float*>(buf.data())[i];
-  };
-  const char* base = static_cast<const char*>(state);
+  std::vector<double> buf(g.nb);
+  const char* base = static_cast<const char*>(state) + P->off_alpha;
   if (rho_out) {
-    HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha, g.nb * sb, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(buf.data(), base, g.nb * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     const int64_t ncell = (int64_t)g.n[0] * g.nx;
-    for (int64_t i = 0; i < ncell; ++i) rho_out[i] = get(i);
+    for (int64_t i = 0; i < ncell; ++i) rho_out[i] = buf[i];
   }
   if (m_out) {
     size_t o = 0;
     for (int d = 1; d <= P->D; ++d) {
-      HIP_OK(hipMemcpyAsync(buf.data(), base + P->off_alpha + (size_t)d * g.nb * sb, g.nb * sb,
+      HIP_OK(hipMemcpyAsync(buf.data(), base + (size_t)d * g.nb * sizeof(double), g.nb * sizeof(double),
                             hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
       for (int64_t i = 0; i < g.nb; ++i) {
         const int64_t r = i / g.stride[d];
         const int xd = (int)(r % g.N[d]);
-        if (xd < g.n[d]) m_out[o++] = get(i);
+        if (xd < g.n[d]) m_out[o++] = buf[i];
       }
     }
   }
@@ -983,17 +980,17 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   }
   rc = P->precision == DOT_FP64 ? build_eigs<double>(P.get()) : build_eigs<float>(P.get());
   if (rc) return rc;
-  // state layout: phi (FP64) | scratch (mixed) | q (D+1) | q_new (D+1) | alpha (D+1) | beta (K) | W (4D) |
-  // control block | partials
+  // state layout: phi (FP64) | scratch (mixed) | q (D+1) | q_new (D+1) | alpha (D+1, FP64) | beta (K) |
+  // W (4D) | control block | partials (the same arithmetic as dot_footprint_bytes)
   const size_t pb = (size_t)g.nb * P->scalar_bytes;
   P->off_phi = 0;
   P->off_scr = align256((size_t)g.nb * sizeof(double));
   P->off_q = P->off_scr + (P->precision == DOT_MIXED ? align256(pb) : 0);
   P->off_qn = P->off_q + (size_t)(D + 1) * pb;
-  P->off_alpha = P->off_qn + (size_t)(D + 1) * pb;
-  P->off_beta = P->off_alpha + (size_t)(D + 1) * pb;
+  P->off_alpha = align256(P->off_qn + (size_t)(D + 1) * pb);
+  P->off_beta = P->off_alpha + (size_t)(D + 1) * g.nb * sizeof(double);
   P->off_w = P->off_beta + (size_t)P->K * pb;
-  P->n_planes = 3 * (D + 1) + P->K + 4 * D;
+  P->n_planes = 2 * (D + 1) + P->K + 4 * D;
   set_sweep(g, default_tc(g.nx, g.N[0]));
   P->nblocks = g.nsweep;
   P->partial_rows = (int64_t)g.nxb * g.N[0];
@@ -1570,7 +1567,9 @@ size_t dot_footprint_bytes(const dot_problem* p) {
   const size_t pb = nb * w;
   size_t s = align256(nb * 8);                               // phi
   if (p->precision == DOT_MIXED) s += align256(pb);          // transform scratch
-  s += (size_t)(3 * (D + 1) + 4 * D + 2 + 4 * D) * pb;       // q, q_new, alpha, beta, W
+  s = align256(s + (size_t)(2 * (D + 1)) * pb);              // q, q_new
+  s += (size_t)(D + 1) * nb * 8;                             // alpha (FP64)
+  s += (size_t)(4 * D + 2 + 4 * D) * pb;                     // beta, W
   s = align256(s) + align256(sizeof(Ctl));
   s += align256((nb / ((size_t)p->n[0] + 1) + kBlock - 1) / kBlock * ((size_t)p->n[0] + 1) * kNumSums *
                 sizeof(double));

@@ -208,14 +208,14 @@ __device__ __forceinline__ void tile_inverse(T* tile, const AxisTab<T>& a) {
 // with spatial coordinates x[1..D]), the right-hand side of the phi-step of
 // Algorithm 2 (zero extension outside each staggered set).
 template <typename T, int D>
-__device__ __forceinline__ double divergence_at(const Geo& g, const T* q_, const T* al_,
+__device__ __forceinline__ double divergence_at(const Geo& g, const T* q_, const double* al_,
                                            const double* __restrict__ c_lo, const double* __restrict__ c_hi,
                                            double inv_sigma, int t, uint32_t xs, const int (&x)[kMaxAxes]) {
   const uint32_t nb = (uint32_t)g.nb;
   const uint32_t s0 = (uint32_t)g.stride[0];
   const uint32_t i = (uint32_t)t * s0 + xs;
   gp<const T> q = glob(q_);
-  gp<const T> al = glob(al_);
+  gp<const double> al = glob(al_);
   double b = 0.0;
   // time axis: cells t-1 and t
   if (t >= 1) b += ((double)q[i - s0] - (double)al[i - s0] * inv_sigma) * g.inv_h[0];
@@ -224,7 +224,7 @@ __device__ __forceinline__ double divergence_at(const Geo& g, const T* q_, const
   for (int d = 1; d <= D; ++d) {
     const uint32_t sd = (uint32_t)g.stride[d];
     gp<const T> qd = q + (size_t)d * nb;
-    gp<const T> ad = al + (size_t)d * nb;
+    gp<const double> ad = al + (size_t)d * nb;
     if (x[d] >= 1) b += ((double)qd[i - sd] - (double)ad[i - sd] * inv_sigma) * g.inv_h[d];
     if (x[d] < g.n[d]) b -= ((double)qd[i] - (double)ad[i] * inv_sigma) * g.inv_h[d];
   }

@@ -161,7 +161,7 @@ __device__ __forceinline__ void cone_arg(const T (&bt)[4 * D + 2], double q0, co
 // update.
 template <typename T, int D>
 __device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restrict__ phi_, const T* __restrict__ q_,
-                                             T* __restrict__ alpha_, const T* __restrict__ beta_,
+                                             double* __restrict__ alpha_, const T* __restrict__ beta_,
                                              const double* __restrict__ sw_sp, T* __restrict__ qn_, T* __restrict__ W_,
                                              const Ctl* __restrict__ ctl, uint32_t blk) {
   constexpr int K = 4 * D + 2;
@@ -170,7 +170,7 @@ __device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restr
   if (!c.live || c.t0 >= tend) return;
   gp<const double> phi = glob(phi_);
   gp<const T> q = glob(q_);
-  gp<T> alpha = glob(alpha_);
+  gp<double> alpha = glob(alpha_);
   gp<const T> beta = glob(beta_);
   gp<T> qn = glob(qn_);
   gp<T> W = glob(W_);
@@ -188,7 +188,7 @@ __device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restr
 #pragma unroll
     for (int k = 0; k < K; ++k) bt[k] = beta[(size_t)k * nb + i];
     const double q0 = (double)q[i];
-    const double a0 = (double)alpha[i];
+    const double a0 = alpha[i];
     double u[K];
     cone_arg<T, D>(bt, q0, fa, fb, sw, inv_sigma, u);
     soc_project<K>(u);
@@ -197,7 +197,7 @@ __device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restr
     const double g0 = (ph1 - ph) * g.inv_h[0];
     const double q0n = (g0 + a0 * inv_sigma + wl - w0) * (1.0 / 3.0);
     qn[i] = (T)q0n;
-    alpha[i] = (T)(a0 + tau * sigma * (g0 - q0n));
+    alpha[i] = a0 + tau * sigma * (g0 - q0n);
 #pragma unroll
     for (int k = 1; k < K - 1; ++k) W[(size_t)(k - 1) * nb + i] = (T)(sw * (u[k] + (double)bt[k] * inv_sigma));
     shift_fq<T, D>(fa, fb);
@@ -214,12 +214,12 @@ struct QdSlice {
   double ph;
   double phd[kMaxAxes];  // phi[i + e_d]
   T w[kMaxAxes][4];      // W_{d,v} of the adjacent cells (0 where absent)
-  T ad[kMaxAxes];        // alpha_d
+  double ad[kMaxAxes];   // alpha_d
 };
 
 template <typename T, int D>
 __device__ __forceinline__ void qd_load(const Geo& g, const Column& c, int t, uint32_t i, gp<const double> phi,
-                                        gp<const T> alpha, gp<const T> W, QdSlice<T, D>& s) {
+                                        gp<const double> alpha, gp<const T> W, QdSlice<T, D>& s) {
   const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
   const bool has_now = t < g.n[0], has_prev = t >= 1;
   s.ph = phi[i];
@@ -229,7 +229,7 @@ __device__ __forceinline__ void qd_load(const Geo& g, const Column& c, int t, ui
     const uint32_t sd = (uint32_t)g.stride[d];
     gp<const T> Wd = W + (size_t)(4 * (d - 1)) * nb;
     s.phd[d] = in ? phi[i + sd] : 0.0;
-    s.ad[d] = in ? alpha[(size_t)d * nb + i] : T(0);
+    s.ad[d] = in ? alpha[(size_t)d * nb + i] : 0.0;
     s.w[d][0] = in && has_now ? Wd[(size_t)0 * nb + i + sd] : T(0);
     s.w[d][1] = in && has_now ? Wd[(size_t)1 * nb + i] : T(0);
     s.w[d][2] = in && has_prev ? Wd[(size_t)2 * nb + i - nx + sd] : T(0);
@@ -238,13 +238,13 @@ __device__ __forceinline__ void qd_load(const Geo& g, const Column& c, int t, ui
 }
 
 template <typename T, int D>
-__device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__ phi_, T* __restrict__ alpha_,
+__device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__ phi_, double* __restrict__ alpha_,
                                         const double* __restrict__ om_sp, T* __restrict__ qn_,
                                         const T* __restrict__ W_, const Ctl* __restrict__ ctl, uint32_t blk) {
   const Column c = column_of<D>(g, blk);
   if (!c.live) return;
   gp<const double> phi = glob(phi_);
-  gp<T> alpha = glob(alpha_);
+  gp<double> alpha = glob(alpha_);
   gp<T> qn = glob(qn_);
   gp<const T> W = glob(W_);
   gp<const double> om = glob(om_sp);
@@ -269,10 +269,10 @@ __device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__
       if (has_prev) acc += (double)cur.w[d][2] + (double)cur.w[d][3];
       const double diag = 1.0 + 0.5 * ct * (om_a + om_b[d]);
       const double gd = (cur.phd[d] - cur.ph) * g.inv_h[d];
-      const double ad = (double)cur.ad[d];
+      const double ad = cur.ad[d];
       const double qdn = (gd + ad * inv_sigma + acc) / diag;
       qn[(size_t)d * nb + i] = (T)qdn;
-      alpha[(size_t)d * nb + i] = (T)(ad + tau * sigma * (gd - qdn));
+      alpha[(size_t)d * nb + i] = ad + tau * sigma * (gd - qdn);
     }
     cur = nxt;
   }
@@ -286,9 +286,10 @@ __device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__
 // the loads of slice t+1 are issued before slice t is computed.
 template <typename T, int D>
 struct RhsSlice {
-  T q0, a0;                 // cell values at t (t < n0)
+  T q0;                     // q0 at the cell t (t < n0)
+  double a0;                // alpha0 at the cell t (t < n0)
   T qd[kMaxAxes][2];        // q_d at x - e_d and x
-  T ad[kMaxAxes][2];        // alpha_d at x - e_d and x
+  double ad[kMaxAxes][2];   // alpha_d at x - e_d and x
   double phn;               // phi at t+1 (DEFECT)
   double phs[kMaxAxes][2];  // phi at x - e_d and x + e_d (DEFECT)
   double cb;                // c~ on the boundary slices
@@ -296,22 +297,22 @@ struct RhsSlice {
 
 template <typename T, int D, bool DEFECT>
 __device__ __forceinline__ void rhs_load(const Geo& g, const Column& c, int t, uint32_t i, gp<const T> q,
-                                         gp<const T> al, gp<const double> phi, const double* c_lo,
+                                         gp<const double> al, gp<const double> phi, const double* c_lo,
                                          const double* c_hi, RhsSlice<T, D>& s) {
   const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
   const int n0 = g.n[0];
   s.q0 = t < n0 ? q[i] : T(0);
-  s.a0 = t < n0 ? al[i] : T(0);
+  s.a0 = t < n0 ? al[i] : 0.0;
 #pragma unroll
   for (int d = 1; d <= D; ++d) {
     const uint32_t sd = (uint32_t)g.stride[d];
     gp<const T> qd = q + (size_t)d * nb;
-    gp<const T> ad = al + (size_t)d * nb;
+    gp<const double> ad = al + (size_t)d * nb;
     const bool lo = c.x[d] >= 1, hi = c.x[d] < g.n[d];
     s.qd[d][0] = lo ? qd[i - sd] : T(0);
-    s.ad[d][0] = lo ? ad[i - sd] : T(0);
+    s.ad[d][0] = lo ? ad[i - sd] : 0.0;
     s.qd[d][1] = hi ? qd[i] : T(0);
-    s.ad[d][1] = hi ? ad[i] : T(0);
+    s.ad[d][1] = hi ? ad[i] : 0.0;
     if (DEFECT) {
       s.phs[d][0] = lo ? phi[i - sd] : 0.0;
       s.phs[d][1] = hi ? phi[i + sd] : 0.0;
@@ -322,14 +323,14 @@ __device__ __forceinline__ void rhs_load(const Geo& g, const Column& c, int t, u
 }
 
 template <typename T, int D, bool DEFECT>
-__device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ al_,
+__device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_, const double* __restrict__ al_,
                                          const double* __restrict__ phi_, const double* __restrict__ c_lo_,
                                          const double* __restrict__ c_hi_, T* __restrict__ out_, double inv_sigma,
                                          uint32_t blk) {
   const Column c = column_of<D>(g, blk);
   if (!c.live) return;
   gp<const T> q = glob(q_);
-  gp<const T> al = glob(al_);
+  gp<const double> al = glob(al_);
   gp<const double> phi = glob(phi_);
   gp<T> out = glob(out_);
   const uint32_t nx = (uint32_t)g.nx, xs = c.xs;
@@ -338,7 +339,7 @@ __device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_,
   uint32_t i = (uint32_t)c.t0 * nx + xs;
   double y0m = 0.0, phm = 0.0, ph = 0.0;
   if (c.t0 >= 1) {
-    y0m = (double)q[i - nx] - (double)al[i - nx] * inv_sigma;
+    y0m = (double)q[i - nx] - al[i - nx] * inv_sigma;
     if (DEFECT) phm = phi[i - nx];
   }
   if (DEFECT) ph = phi[i];
@@ -350,13 +351,13 @@ __device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_,
     if (t >= 1) b += y0m * g.inv_h[0];
     double y0 = 0.0;
     if (t < n0) {
-      y0 = (double)cur.q0 - (double)cur.a0 * inv_sigma;
+      y0 = (double)cur.q0 - cur.a0 * inv_sigma;
       b -= y0 * g.inv_h[0];
     }
 #pragma unroll
     for (int d = 1; d <= D; ++d) {
-      if (c.x[d] >= 1) b += ((double)cur.qd[d][0] - (double)cur.ad[d][0] * inv_sigma) * g.inv_h[d];
-      if (c.x[d] < g.n[d]) b -= ((double)cur.qd[d][1] - (double)cur.ad[d][1] * inv_sigma) * g.inv_h[d];
+      if (c.x[d] >= 1) b += ((double)cur.qd[d][0] - cur.ad[d][0] * inv_sigma) * g.inv_h[d];
+      if (c.x[d] < g.n[d]) b -= ((double)cur.qd[d][1] - cur.ad[d][1] * inv_sigma) * g.inv_h[d];
     }
     if (t == 0 || t == n0) b -= cur.cb * inv_sigma;
     if (DEFECT) {
@@ -493,7 +494,7 @@ __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_
 // 14 |F^*B^*beta|^2, 15 |alpha|^2, 16 <c, phi>, 17 sum m^2 / r over r > 0.
 // (4, 11, 12 are filled elsewhere.)
 template <typename T, int D>
-__device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, const T* q_, const T* alpha_,
+__device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, const T* q_, const double* alpha_,
                                            const T* beta_, const double* om_sp, const double* sw_sp,
                                            const double* c_lo_, const double* c_hi_, double* __restrict__ partials,
                                            uint32_t blk) {
@@ -505,7 +506,7 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
   if (c.live) {
     gp<const double> phi = glob(phi_);
     gp<const T> q = glob(q_);
-    gp<const T> alpha = glob(alpha_);
+    gp<const double> alpha = glob(alpha_);
     gp<const T> beta = glob(beta_);
     gp<const double> om = glob(om_sp);
     gp<const double> swp = glob(sw_sp);
@@ -527,7 +528,7 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
       if (t < n0) div -= (double)alpha[i] * g.inv_h[0];
 #pragma unroll
       for (int d = 1; d <= D; ++d) {
-        gp<const T> ad = alpha + (size_t)d * nb;
+        gp<const double> ad = alpha + (size_t)d * nb;
         if (c.x[d] >= 1) div += (double)ad[i - (uint32_t)g.stride[d]] * g.inv_h[d];
         if (c.x[d] < g.n[d]) div -= (double)ad[i] * g.inv_h[d];
       }

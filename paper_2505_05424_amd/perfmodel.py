@@ -21,27 +21,28 @@ def sizes(D: int, n: Sequence[int]) -> Dict[str, int]:
 
 def kernel_bytes(D: int, n: Sequence[int], w: int) -> Dict[str, float]:
     """Compulsory bytes per launch of each kernel class; w is the bulk scalar
-    size (8 FP64, 4 mixed); phi is always FP64 (8 bytes per node)."""
+    size (8 FP64, 4 mixed); phi and alpha are always FP64 (8 bytes)."""
     z = sizes(D, n)
     Nc, S, Q, Qb, K = z["Nc"], z["S"], z["Q"], z["Qbar"], z["K"]
     mixed = w != 8
+    a = 8  # alpha
     last_inv = (w + 16) * Nc if mixed else 2 * w * Nc  # time-axis inverse adds into phi (mixed)
     return {
         # b (FP64) or b - A^*A phi (mixed): read q, alpha (and phi); write the work plane
-        "rhs": w * (2 * Q + Nc) + (8 * Nc if mixed else 0),
+        "rhs": w * Q + a * Q + w * Nc + (8 * Nc if mixed else 0),
         "dct_first": 2 * w * Nc,
         "dct_mid": 2 * w * Nc,
         "dct_last": 2 * w * Nc,
         # D launches: D-1 plain inverse passes and the time-axis one
         "dct_inv": ((D - 1) * 2 * w * Nc + last_inv) / D,
         # cone: read q, beta, phi, alpha0; write q0_new, alpha0, 4D weighted w planes
-        "cone": w * (Q + K * S + S + 2 * S + 4 * D * S) + 8 * Nc,
+        "cone": w * (Q + K * S + S + 4 * D * S) + 2 * a * S + 8 * Nc,
         # q_d: read phi, alpha_d, w planes; write q_d, alpha_d
-        "qd": w * (Qb + 4 * D * S + 2 * Qb) + 8 * Nc,
+        "qd": w * (Qb + 4 * D * S) + 2 * a * Qb + 8 * Nc,
         # beta: read q_old, q_new, beta; write beta
         "beta": w * (2 * Q + 2 * K * S),
         # residual partials: read phi, q, alpha, beta
-        "resid": w * (2 * Q + K * S) + 8 * Nc,
+        "resid": w * (Q + K * S) + a * Q + 8 * Nc,
         "final": 0.0,
     }
 
@@ -49,9 +50,9 @@ def kernel_bytes(D: int, n: Sequence[int], w: int) -> Dict[str, float]:
 def iteration_min_bytes(D: int, n: Sequence[int], w: int) -> float:
     """Fused lower bound per PALM iteration: read phi, q, alpha, beta and write
     q, alpha, beta, b once, plus one read of b and one write of phi in the
-    Poisson solve."""
+    Poisson solve (phi, b and alpha in FP64)."""
     z = sizes(D, n)
-    return w * (4 * z["Nc"] + 4 * z["Q"] + 2 * z["K"] * z["S"])
+    return 8 * 4 * z["Nc"] + (2 * w + 16) * z["Q"] + w * 2 * z["K"] * z["S"]
 
 
 def launches_per_iteration(D: int) -> Dict[str, int]:

@@ -55,7 +55,7 @@ def test_mixed_steps(name):
     st = G.stream_handle()
     f32 = np.float32
     qd = G.dev(G.planes_of(q, g.n, f32))
-    ad = G.dev(G.planes_of(al, g.n, f32))
+    ad = G.dev(G.planes_of(al, g.n))  # alpha is FP64 in both modes
     bed = G.dev(G.planes_of(list(be), g.n, f32))
     # a3: FP64 arithmetic on FP32 inputs
     bd = G.dev(np.zeros(g.node_shape))
@@ -104,7 +104,7 @@ def test_mixed_residuals_are_fp64_reductions():
     st = G.stream_handle()
     f32 = np.float32
     args = [G.dev(B.to_box(S.phi, g.n)), G.dev(G.planes_of(list(z), g.n, f32)), G.dev(G.planes_of(q, g.n, f32)),
-            G.dev(G.planes_of(al, g.n, f32)), G.dev(G.planes_of(list(be), g.n, f32))]
+            G.dev(G.planes_of(al, g.n)), G.dev(G.planes_of(list(be), g.n, f32))]
     r = B.dot_step_residuals(plan, *[a.data_ptr() for a in args], st)
     ref = O.residuals(P, S.phi, z, q, al, be)
     for k in ("eta_dot", "eta_p", "eta_d", "eta_c", "eta_p_soc", "eta_d_soc"):
