@@ -168,6 +168,21 @@ def large_roofline(torch, st, iters=60):
 
 
 
+def variants_section(torch, st, inst):
+    """Algorithm variants on the same kernels (Rem. 4.2): dual step length tau
+    in {1, 1.5, 1.9} on the single-instance workload, FP64, to eta_dot <= 1e-6."""
+    out = {}
+    for tau in (1.0, 1.5, 1.9):
+        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=TOL, max_iter=MAX_ITER,
+                                 tau=tau)
+        buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+        el, r = time_solves(plan, buf.data_ptr(), st, 1, torch)
+        out[f"tau={tau}"] = {"iters": r[0].iters, "term": B.TERM_NAMES[r[0].term], "seconds": el,
+                             "solves_per_s": 1.0 / el, "objective": r[0].objective}
+        plan.close()
+    return out
+
+
 def batched_section(torch, st, count, sample, seed=4000):
     """Config-4-like batch: `count` instances (grid sides from {32..128}, n0
     from {16, 32, 64}, half masked), mixed precision, one launch per kernel
@@ -438,6 +453,8 @@ def main():
         "kernel_breakdown_one_solve": breakdown,
         "roofline_bandwidth_bound_size": large,
     }
+    log("variants (tau)")
+    out["variants_tau"] = variants_section(torch, st, inst)
     if args.batch > 0:
         out["batched"] = batched_section(torch, st, args.batch, args.plain_sample)
     if args.serve_seconds > 0:

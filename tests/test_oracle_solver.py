@@ -160,3 +160,37 @@ def test_sigma_rule_constants():
     pts = O.sigma_update_points(400)
     assert pts[:6] == [10, 25, 45, 70, 105, 150]
     assert all(p % 5 == 0 for p in pts)
+
+
+@pytest.mark.parametrize("tau", [1.0, 1.5])
+def test_step_length_variants_reach_the_bruteforce_optimum(tau):
+    """Rem. 4.2: any dual step length tau in (0, 2) converges to the same
+    optimum; tau = 1 is the unrelaxed variant. The oracle with tau = 1 and
+    1.5 reaches the brute-force SOCP optimum on a tiny masked 2D grid."""
+    inst = dotgen.tiny_instance(2, (3, 4, 4), masked=True)
+    bf = BFS.solve(2, (3, 4, 4), inst.rho0, inst.rho1, inst.mask)
+    P = O.make_problem(2, (3, 4, 4), inst.rho0, inst.rho1, inst.mask)
+    r = O.solve(P, tol=1e-11, max_iter=40000, tau=tau)
+    assert r.converged
+    assert abs(r.objective - bf["objective"]) <= 1e-8 * abs(bf["objective"])
+    np.testing.assert_allclose(r.state.alpha[0], bf["rho"], atol=1e-5)
+
+
+def test_step_length_scales_only_the_multiplier_steps():
+    """tau enters the multiplier steps only: from the same state, one
+    iteration gives the same phi, z and q_new for any tau, and the alpha and
+    beta increments are proportional to tau."""
+    inst = dotgen.tiny_instance(2, (4, 5, 6), seed=3, floor=0.0, n_comp=3)
+    P = O.make_problem(2, inst.n, inst.rho0, inst.rho1)
+    S = O.zero_state(P)
+    for _ in range(7):
+        S = O.iterate(P, S)
+    a = O.iterate(P, S, tau=1.0)
+    b = O.iterate(P, S, tau=1.6)
+    np.testing.assert_array_equal(a.phi, b.phi)
+    np.testing.assert_array_equal(a.z, b.z)
+    for qa, qb in zip(a.q, b.q):
+        np.testing.assert_array_equal(qa, qb)
+    for x0, xa, xb in zip(S.alpha, a.alpha, b.alpha):
+        np.testing.assert_allclose(1.6 * (xa - x0), xb - x0, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(1.6 * (a.beta - S.beta), b.beta - S.beta, rtol=1e-12, atol=1e-14)
