@@ -183,6 +183,24 @@ def variants_section(torch, st, inst):
     return out
 
 
+def multilevel_section(torch, inst):
+    """Multilevel initialisation (coarse grids n / 2^v, each level started from
+    the interpolated coarser solution) on the single-instance workload, FP64,
+    one-shot calls (plans and states allocated inside, as dot_solve does)."""
+    out = {}
+    for levels in (0, 1, 2, 3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r, rho, m, lv = B.dot_solve_multilevel(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, levels=levels,
+                                               tol=TOL, max_iter=MAX_ITER)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"levels={levels}"] = {"seconds": el, "solves_per_s": 1.0 / el, "term": B.TERM_NAMES[r.term],
+                                   "iters_per_level_coarsest_first": [x.iters for x in lv],
+                                   "objective": r.objective, "eta_dot": r.eta_dot}
+    return out
+
+
 def batched_section(torch, st, count, sample, seed=4000):
     """Config-4-like batch: `count` instances (grid sides from {32..128}, n0
     from {16, 32, 64}, half masked), mixed precision, one launch per kernel
@@ -453,6 +471,8 @@ def main():
         "kernel_breakdown_one_solve": breakdown,
         "roofline_bandwidth_bound_size": large,
     }
+    log("multilevel")
+    out["multilevel"] = multilevel_section(torch, inst)
     log("variants (tau)")
     out["variants_tau"] = variants_section(torch, st, inst)
     if args.batch > 0:

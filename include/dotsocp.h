@@ -229,6 +229,36 @@ int dot_batch_set_graphs(dot_batch* batch, int32_t enable);
  * free. rho_out: n0*prod(n_d+1); m_out: sum_d |G^s_d| doubles. */
 int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* res);
 
+/* ---- multilevel initialisation ------------------------------------------ */
+/* The multilevel strategy of the paper (implementation details of Sec. 5.3,
+ * experiments of Sec. 5.4): solve on grids with n_d / 2^v segments,
+ * v = L..1, and start each finer level from the linear interpolation of the
+ * coarser solution; level v is solved to max{tol * 10^-v, 1e-6}. */
+
+/* Data of the next coarser grid (n_d / 2 segments on every axis; every n_d
+ * must be even and >= 2). Host arrays: node masses are restricted with the
+ * transpose of linear interpolation (fine node 2i gives all its mass to coarse
+ * node i, fine node 2i+1 half to each of i and i+1), which keeps the total
+ * mass; with a mask, coarse node i is an obstacle node when fine node 2i is,
+ * carries no mass, and each density is renormalised to its total. Outputs
+ * hold prod_d (n_d/2 + 1) entries (mask_out only if mask is given). */
+int dot_coarsen_data(int32_t D, const int32_t* n, const double* rho0, const double* rho1, const uint8_t* mask,
+                     double* rho0_out, double* rho1_out, uint8_t* mask_out);
+/* Initial point of the finer level: q, alpha and beta of fine_state become the
+ * tensor-product linear interpolation of those of coarse_state (positions of
+ * each staggered set in physical coordinates, constant beyond the outermost
+ * coarse positions), phi, z-weights and q_new are zeroed, sigma carries over
+ * and the iteration counter and sigma schedule restart. The plans need the
+ * same D and precision and fine n[d] = 2 * coarse n[d]. Blocks. */
+int dot_prolong(const dot_plan* coarse, const void* coarse_state, dot_plan* fine, void* fine_state, void* stream);
+/* One-shot multilevel solve with `levels` coarser grids (0 = plain solve):
+ * allocates, solves level by level on the default stream, copies rho / m of
+ * the target grid (as dot_solve) and frees. res: the target level;
+ * level_results (may be NULL): levels + 1 entries, coarsest first. max_iter
+ * caps every level. */
+int dot_solve_multilevel(const dot_problem* p, int32_t levels, double* rho_out, double* m_out, dot_result* res,
+                         dot_result* level_results);
+
 /* ---- serving: continuous batching under an HBM budget --------------------- */
 /* A serving context holds one device arena of hbm_budget_bytes and up to
  * max_slots running instances of one D and precision. Requests queue in

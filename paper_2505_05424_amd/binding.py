@@ -30,7 +30,7 @@ EXPORTED = [
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
     "dot_plan_set_graphs", "dot_batch_set_graphs",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_step", "dot_ctx_poll",
-    "dot_ctx_fetch", "dot_ctx_stats",
+    "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
 ]
 
 CTX_QUEUED, CTX_RUNNING, CTX_DONE = 0, 1, 2
@@ -164,6 +164,14 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result)]
     lib.dot_ctx_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int64),
                                   ctypes.POINTER(ctypes.c_int64)]
+    lib.dot_coarsen_data.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_uint8),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_uint8)]
+    lib.dot_prolong.argtypes = [vp, vp, vp, vp, vp]
+    lib.dot_solve_multilevel.argtypes = [ctypes.POINTER(dot_problem), i32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result),
+                                         ctypes.POINTER(dot_result)]
     for name in EXPORTED:
         if name not in ("dot_last_error", "dot_plan_destroy", "dot_batch_destroy", "dot_batch_workspace_bytes",
                         "dot_batch_size", "dot_footprint_bytes", "dot_ctx_destroy"):
@@ -463,6 +471,43 @@ def _split(m, shapes):
         out.append(m[o:o + k].reshape(s))
         o += k
     return out
+
+
+# ---- multilevel initialisation ---------------------------------------------
+def dot_coarsen_data(D, n, rho0, rho1, mask=None):
+    """(n / 2, rho0, rho1, mask) of the next coarser grid (host arithmetic)."""
+    n = [int(k) for k in n[:D + 1]]
+    nc = tuple(k // 2 for k in n)
+    shape = tuple(k + 1 for k in nc[1:])
+    r0 = np.ascontiguousarray(rho0, dtype=np.float64).ravel()
+    r1 = np.ascontiguousarray(rho1, dtype=np.float64).ravel()
+    o0 = np.zeros(shape)
+    o1 = np.zeros(shape)
+    mk = mo = None
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8).ravel()
+        mo = np.zeros(shape, dtype=np.uint8)
+    narr = (ctypes.c_int32 * 4)(*(n + [0] * (4 - len(n))))
+    u8 = ctypes.POINTER(ctypes.c_uint8)
+    _check(load().dot_coarsen_data(int(D), narr, _dptr(r0), _dptr(r1),
+                                   mk.ctypes.data_as(u8) if mk is not None else None, _dptr(o0), _dptr(o1),
+                                   mo.ctypes.data_as(u8) if mo is not None else None))
+    return nc, o0, o1, mo
+
+
+def dot_prolong(coarse: Plan, coarse_state_ptr: int, fine: Plan, fine_state_ptr: int, stream: int = 0):
+    _check(load().dot_prolong(coarse.handle, ctypes.c_void_p(coarse_state_ptr), fine.handle,
+                              ctypes.c_void_p(fine_state_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_solve_multilevel(D, n, rho0, rho1, mask=None, levels=2, **kw):
+    """Multilevel one-shot solve; returns (result, rho, [m_d], level_results coarsest first)."""
+    p, keep = make_problem(D, n, rho0, rho1, mask, **kw)
+    rho, m, shapes = _solution_buffers(D, n)
+    r = dot_result()
+    lv = (dot_result * (levels + 1))()
+    _check(load().dot_solve_multilevel(ctypes.byref(p), int(levels), _dptr(rho), _dptr(m), ctypes.byref(r), lv))
+    return r, rho, _split(m, shapes), list(lv)
 
 
 # ---- serving context ---------------------------------------------------------

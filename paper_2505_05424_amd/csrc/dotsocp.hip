@@ -22,6 +22,7 @@
 #include "batch.hpp"
 #include "geometry.hpp"
 #include "kernels_dct.hpp"
+#include "kernels_multilevel.hpp"
 #include "kernels_update.hpp"
 
 using namespace dot;
@@ -1280,6 +1281,203 @@ int dot_batch_profile_read(dot_batch* B, double* total_ms, int64_t* launches) {
   B->prof.ms = 0.0;
   B->prof.launches = 0;
   return DOT_OK;
+}
+
+// ---- multilevel initialisation ------------------------------------------
+
+int dot_coarsen_data(int32_t D, const int32_t* n, const double* rho0, const double* rho1, const uint8_t* mask,
+                     double* rho0_out, double* rho1_out, uint8_t* mask_out) {
+  if (D < 1 || D > 3 || !n || !rho0 || !rho1 || !rho0_out || !rho1_out || (mask && !mask_out))
+    return fail(DOT_EINVAL, "bad coarsening arguments");
+  for (int d = 0; d <= D; ++d)
+    if (n[d] < 2 || n[d] % 2) return fail(DOT_EINVAL, "segment counts must be even (>= 2) to coarsen");
+  // spatial node counts, fine and coarse; C order, last axis fastest
+  std::vector<int64_t> Nf(D), Nc(D);
+  for (int d = 0; d < D; ++d) {
+    Nf[d] = n[d + 1] + 1;
+    Nc[d] = n[d + 1] / 2 + 1;
+  }
+  int64_t cf = 1, cc = 1;
+  for (int d = 0; d < D; ++d) {
+    cf *= Nf[d];
+    cc *= Nc[d];
+  }
+  // restrict one axis at a time: coarse i <- fine 2i (weight 1), 2i-1 and 2i+1 (weight 1/2)
+  auto restrict_all = [&](const double* in, double* out) {
+    std::vector<double> cur(in, in + cf), nxt;
+    std::vector<int64_t> shape(Nf.begin(), Nf.end());
+    for (int ax = 0; ax < D; ++ax) {
+      int64_t outer = 1, inner = 1;
+      for (int d = 0; d < ax; ++d) outer *= shape[d];
+      for (int d = ax + 1; d < D; ++d) inner *= shape[d];
+      const int64_t lf = shape[ax], lc = Nc[ax];
+      nxt.assign((size_t)(outer * lc * inner), 0.0);
+      for (int64_t o = 0; o < outer; ++o)
+        for (int64_t j = 0; j < lf; ++j) {
+          const double* srow = cur.data() + (o * lf + j) * inner;
+          auto add = [&](int64_t ci, double wgt) {
+            double* drow = nxt.data() + (o * lc + ci) * inner;
+            for (int64_t k = 0; k < inner; ++k) drow[k] += wgt * srow[k];
+          };
+          if (j % 2 == 0) {
+            add(j / 2, 1.0);
+          } else {
+            add((j - 1) / 2, 0.5);
+            add((j + 1) / 2, 0.5);
+          }
+        }
+      cur.swap(nxt);
+      shape[ax] = lc;
+    }
+    std::copy(cur.begin(), cur.end(), out);
+  };
+  restrict_all(rho0, rho0_out);
+  restrict_all(rho1, rho1_out);
+  if (mask) {
+    // coarse node i is an obstacle node when fine node 2i is; no mass there
+    double s0 = 0.0, s1 = 0.0;
+    for (int64_t c = 0; c < cc; ++c) {
+      int64_t r = c, f = 0, mul = 1;
+      for (int d = D - 1; d >= 0; --d) {
+        const int64_t x = r % Nc[d];
+        r /= Nc[d];
+        f += 2 * x * mul;
+        mul *= Nf[d];
+      }
+      mask_out[c] = mask[f];
+      if (mask_out[c]) rho0_out[c] = rho1_out[c] = 0.0;
+      s0 += rho0_out[c];
+      s1 += rho1_out[c];
+    }
+    if (!(s0 > 0.0) || !(s1 > 0.0)) return fail(DOT_EINVAL, "coarse data has no mass outside the obstacles");
+    for (int64_t c = 0; c < cc; ++c) {
+      rho0_out[c] /= s0;
+      rho1_out[c] /= s1;
+    }
+  }
+  return DOT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+template <typename T, int D>
+struct ProlongF {
+  static int run(const dot_plan* C, const void* cs, dot_plan* F, void* fs, hipStream_t st) {
+    const char* c = static_cast<const char*>(cs);
+    char* f = static_cast<char*>(fs);
+    const dim3 blk(kBlock);
+    const unsigned gx = (unsigned)((F->g.nb + kBlock - 1) / kBlock);
+    // q0 / alpha0 / beta: cells (staggered in time); q_d / alpha_d: staggered on axis d
+    hipLaunchKernelGGL((kb_prolong<T, D>), dim3(gx, 1), blk, 0, st, C->g, F->g,
+                       (const T*)(c + C->off_q), (T*)(f + F->off_q), 1);
+    hipLaunchKernelGGL((kb_prolong<double, D>), dim3(gx, 1), blk, 0, st, C->g, F->g,
+                       (const double*)(c + C->off_alpha), (double*)(f + F->off_alpha), 1);
+    hipLaunchKernelGGL((kb_prolong<T, D>), dim3(gx, (unsigned)C->K), blk, 0, st, C->g, F->g,
+                       (const T*)(c + C->off_beta), (T*)(f + F->off_beta), 1);
+    for (int d = 1; d <= D; ++d) {
+      hipLaunchKernelGGL((kb_prolong<T, D>), dim3(gx, 1), blk, 0, st, C->g, F->g,
+                         (const T*)(c + C->off_q) + (size_t)d * C->g.nb, (T*)(f + F->off_q) + (size_t)d * F->g.nb,
+                         1 << d);
+      hipLaunchKernelGGL((kb_prolong<double, D>), dim3(gx, 1), blk, 0, st, C->g, F->g,
+                         (const double*)(c + C->off_alpha) + (size_t)d * C->g.nb,
+                         (double*)(f + F->off_alpha) + (size_t)d * F->g.nb, 1 << d);
+    }
+    HIP_OK(hipGetLastError());
+    return DOT_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int dot_prolong(const dot_plan* C, const void* coarse_state, dot_plan* F, void* fine_state, void* stream) {
+  if (!C || !F || !coarse_state || !fine_state) return fail(DOT_EINVAL, "null argument");
+  if (C->D != F->D || C->precision != F->precision) return fail(DOT_EINVAL, "plans differ in D or precision");
+  for (int d = 0; d <= C->D; ++d)
+    if (F->n[d] != 2 * C->n[d]) return fail(DOT_EINVAL, "the fine grid must have twice the segments per axis");
+  hipStream_t st = (hipStream_t)stream;
+  // sigma of the coarse iterate carries over; counters and schedule restart
+  Ctl cc{};
+  HIP_OK(hipMemcpyAsync(&cc, static_cast<const char*>(coarse_state) + C->ctl_offset, sizeof(Ctl),
+                        hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  HIP_OK(hipMemsetAsync(fine_state, 0, F->ctl_offset, st));
+  int rc = dispatch<ProlongF>(C->precision, C->D, C, coarse_state, F, fine_state, st);
+  if (rc) return rc;
+  Ctl h = initial_ctl(F);
+  h.sigma = cc.sigma;
+  *F->host_ctl = h;
+  HIP_OK(hipMemcpyAsync(static_cast<char*>(fine_state) + F->ctl_offset, F->host_ctl, sizeof(Ctl),
+                        hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return DOT_OK;
+}
+
+int dot_solve_multilevel(const dot_problem* p, int32_t levels, double* rho_out, double* m_out, dot_result* res,
+                         dot_result* level_results) {
+  if (!p || levels < 0 || levels > 8) return fail(DOT_EINVAL, "bad multilevel arguments");
+  int rc = validate(p);
+  if (rc) return rc;
+  const int D = p->D;
+  // data of every level, finest first
+  struct Level {
+    int32_t n[4];
+    std::vector<double> r0, r1;
+    std::vector<uint8_t> mask;
+  };
+  std::vector<Level> L(levels + 1);
+  size_t nx = 1;
+  for (int d = 1; d <= D; ++d) nx *= (size_t)p->n[d] + 1;
+  for (int d = 0; d < 4; ++d) L[0].n[d] = p->n[d];
+  L[0].r0.assign(p->rho0, p->rho0 + nx);
+  L[0].r1.assign(p->rho1, p->rho1 + nx);
+  if (p->mask) L[0].mask.assign(p->mask, p->mask + nx);
+  for (int v = 1; v <= levels; ++v) {
+    Level& a = L[v - 1];
+    Level& b = L[v];
+    size_t ncx = 1;
+    for (int d = 0; d < 4; ++d) b.n[d] = d <= D ? a.n[d] / 2 : 0;
+    for (int d = 1; d <= D; ++d) ncx *= (size_t)b.n[d] + 1;
+    b.r0.resize(ncx);
+    b.r1.resize(ncx);
+    if (!a.mask.empty()) b.mask.resize(ncx);
+    rc = dot_coarsen_data(D, a.n, a.r0.data(), a.r1.data(), a.mask.empty() ? nullptr : a.mask.data(), b.r0.data(),
+                          b.r1.data(), b.mask.empty() ? nullptr : b.mask.data());
+    if (rc) return rc;
+  }
+  std::vector<dot_plan*> plans(levels + 1, nullptr);
+  std::vector<void*> states(levels + 1, nullptr);
+  auto cleanup = [&]() {
+    for (auto* s : states) (void)hipFree(s);
+    for (auto* P : plans) dot_plan_destroy(P);
+  };
+  for (int v = levels; v >= 0; --v) {
+    dot_problem q = *p;
+    for (int d = 0; d < 4; ++d) q.n[d] = L[v].n[d];
+    q.rho0 = L[v].r0.data();
+    q.rho1 = L[v].r1.data();
+    q.mask = L[v].mask.empty() ? nullptr : L[v].mask.data();
+    // coarse level v: max{tol 10^-v, 1e-6}; the target level: tol
+    if (v > 0) q.tol = std::max(p->tol * std::pow(10.0, -v), 1e-6);
+    rc = dot_plan_create(&q, &plans[v]);
+    if (!rc && hipMalloc(&states[v], plans[v]->state_bytes) != hipSuccess) rc = fail(DOT_ENOMEM, "state allocation failed");
+    if (!rc) rc = v == levels ? dot_state_reset(plans[v], states[v], nullptr)
+                              : dot_prolong(plans[v + 1], states[v + 1], plans[v], states[v], nullptr);
+    dot_result r{};
+    if (!rc) rc = dot_run(plans[v], states[v], p->max_iter, nullptr, &r);
+    if (rc) {
+      cleanup();
+      return rc;
+    }
+    if (level_results) level_results[levels - v] = r;
+    if (v == 0 && res) *res = r;
+  }
+  rc = dot_extract(plans[0], states[0], rho_out, m_out, nullptr);
+  cleanup();
+  return rc;
 }
 
 // ---- serving: continuous batching with admission by HBM footprint ---------

@@ -48,3 +48,19 @@ def test_invalid_problems_are_rejected():
     assert "segment" in _bad(n=(0, 8))
     assert "tau" in _bad(tau=2.5)
     assert "positive total" in _bad(rho0=np.zeros(9), rho1=np.zeros(9))
+
+
+@pytest.mark.parametrize("D,n,masked", [(1, (4, 10), False), (2, (6, 8, 12), True), (3, (4, 6, 4, 8), False)])
+def test_coarsen_data_matches_the_oracle(D, n, masked):
+    """Host arithmetic of the library (no device): the restriction of the
+    data to the coarser grid equals the oracle's."""
+    import dotgen
+    from oracle import multilevel as ML
+    inst = dotgen.tiny_instance(D, n, seed=11, floor=0.0, masked=masked)
+    nc, r0, r1, mk = B.dot_coarsen_data(D, n, inst.rho0, inst.rho1, inst.mask)
+    nc2, q0, q1, mk2 = ML.coarse_data(n, inst.rho0, inst.rho1, inst.mask)
+    assert nc == nc2
+    np.testing.assert_allclose(r0, q0, rtol=1e-14, atol=1e-17)
+    np.testing.assert_allclose(r1, q1, rtol=1e-14, atol=1e-17)
+    if masked:
+        np.testing.assert_array_equal(mk, mk2)
