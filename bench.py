@@ -185,19 +185,24 @@ def variants_section(torch, st, inst):
 
 def multilevel_section(torch, inst):
     """Multilevel initialisation (coarse grids n / 2^v, each level started from
-    the interpolated coarser solution) on the single-instance workload, FP64,
-    one-shot calls (plans and states allocated inside, as dot_solve does)."""
-    out = {}
-    for levels in (0, 1, 2, 3):
+    the interpolated coarser solution), one-shot calls (plans and states
+    allocated inside, as dot_solve does): the single-instance workload in FP64
+    with 0..3 coarse levels, and 2D 64x256x256 (5-component mixtures) in mixed
+    precision without and with 3 coarse levels."""
+    def one(i, levels, prec):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r, rho, m, lv = B.dot_solve_multilevel(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, levels=levels,
-                                               tol=TOL, max_iter=MAX_ITER)
+        r, rho, m, lv = B.dot_solve_multilevel(i.D, i.n, i.rho0, i.rho1, i.mask, levels=levels, tol=TOL,
+                                               max_iter=MAX_ITER, precision=prec)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        out[f"levels={levels}"] = {"seconds": el, "solves_per_s": 1.0 / el, "term": B.TERM_NAMES[r.term],
-                                   "iters_per_level_coarsest_first": [x.iters for x in lv],
-                                   "objective": r.objective, "eta_dot": r.eta_dot}
+        return {"seconds": el, "solves_per_s": 1.0 / el, "term": B.TERM_NAMES[r.term],
+                "iters_per_level_coarsest_first": [x.iters for x in lv], "objective": r.objective,
+                "eta_dot": r.eta_dot}
+    out = {"2d-32x64x64-fp64": {f"levels={v}": one(inst, v, B.DOT_FP64) for v in (0, 1, 2, 3)}}
+    big = dotgen.config3_instance()
+    log("multilevel at 2D 64x256x256 (mixed)")
+    out["2d-64x256x256-mixed"] = {f"levels={v}": one(big, v, B.DOT_MIXED) for v in (0, 3)}
     return out
 
 
