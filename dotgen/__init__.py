@@ -32,6 +32,7 @@ __all__ = [
     "config3_instance",
     "config4_instances",
     "serving_3d_instance",
+    "image_like_instance",
     "serving_request",
     "tiny_instance",
 ]
@@ -182,6 +183,18 @@ def serving_3d_instance(seed: int = 5003) -> Instance:
     """The 3D request shape of the serving stream: 64^3 segments, 32 time
     steps, 3-component mixtures in [0,1]^3, no floor."""
     return _mixture_pair(3, (32, 64, 64, 64), seed, 3)
+
+
+def image_like_instance(n: Sequence[int] = (32, 1024, 1024), seed: int = 6000, n_comp: int = 16) -> Instance:
+    """Large 2D instance standing in for the paper's 1024^2 image pair (the
+    images are not available): mixtures of n_comp narrow isotropic Gaussians
+    (standard deviations U[0.015, 0.06], means U[0.1, 0.9]^2, Dirichlet(1)
+    weights), no floor."""
+    rng = np.random.default_rng(seed)
+    sp = list(n[1:])
+    r0 = normalise(mixture_nodes(sp, rng, n_comp, 0.1, 0.9, 0.015, 0.06))
+    r1 = normalise(mixture_nodes(sp, rng, n_comp, 0.1, 0.9, 0.015, 0.06))
+    return Instance(len(sp), tuple(n), r0, r1, None, seed, "image-like-" + "x".join(map(str, n)))
 
 
 def config4_instances(count: int = 64, seed: int = 4000,

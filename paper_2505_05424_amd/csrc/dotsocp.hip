@@ -129,6 +129,7 @@ struct dot_plan {
   int64_t partial_rows = 0;  // capacity of the partial-sum rows (nsweep at one slice per workgroup)
   int64_t tiles[kMaxAxes] = {0, 0, 0, 0};  // transform tiles per axis at this plan's own tile width
   int64_t lines[kMaxAxes] = {0, 0, 0, 0};  // lines per axis (nb / N[a])
+  bool wide_ok[kMaxAxes] = {true, true, true, true};  // the axis fits a tile of kCW lines
   // device constant tables
   double* sw_sp = nullptr;  // sqrt(omega/2) on spatial nodes
   double* om_sp = nullptr;  // omega on spatial nodes
@@ -228,35 +229,49 @@ int build_axis(dot_plan* P, int a, void** buf, AxisTab<T>* tab) {
 // Waves per workgroup of a transform pass over an axis of L points. A launch
 // with few tiles (fewer than kManyTiles workgroups) gives each work item its
 // own wave, so the coefficient streams of all items run concurrently; with
-// many tiles each wave takes up to MfmaOps<T>::kItems items and more
-// workgroups share a CU.
+// many tiles each wave takes up to items_per_wave items and more workgroups
+// share a CU.
 constexpr int64_t kManyTiles = 1024;
-template <typename T>
-int pass_waves(int L, int64_t tiles, int cw) {
+
+int pass_items(int L, int cw) {
   const int M = L / 2, ne = L - M, no = M;
   const int groups = cw >= 32 ? cw / 32 : 1;  // work items per row block (see tile_mfma)
-  const int items = groups * ((ne + 15) / 16 + (no + 15) / 16);
-  const int rounds = (items + MfmaOps<T>::kItems - 1) / MfmaOps<T>::kItems;
+  return groups * ((ne + 15) / 16 + (no + 15) / 16);
+}
+
+template <typename T>
+int wave_items(int cw) {
+  return cw >= 32 ? items_per_wave<T, kCW>() : items_per_wave<T, kCWNarrow>();
+}
+
+template <typename T>
+int pass_waves(int L, int64_t tiles, int cw) {
+  const int items = pass_items(L, cw);
+  const int rounds = (items + wave_items<T>(cw) - 1) / wave_items<T>(cw);
   // many tiles: small workgroups, several per CU; few tiles: spread the items
   const int w = (tiles >= kManyTiles || items > kMaxWaves) ? rounds : items;
   return std::max(4, std::min(kMaxWaves, w));
 }
 
-template <typename T>
-bool axis_fits(int L) {
-  const int M = L / 2, ne = L - M, no = M;
-  const int items = 2 * ((ne + 15) / 16 + (no + 15) / 16);
-  return items <= MfmaOps<T>::kItems * kMaxWaves;
-}
-
 // Dynamic LDS of a transform pass over an axis of L points: the tile of
-// kCW columns (row stride kCW + 1) and, behind it, the eigenvalue tables of the
-// scale pass (L rows, kCW columns).
+// cw columns (row stride cw + 1) and, behind it, the eigenvalue tables of the
+// scale pass (L rows, cw columns).
 size_t pass_smem(int L, int scalar_bytes, int cw) { return ((size_t)L * (cw + 1) + L + cw) * scalar_bytes; }
 
+// Whether an axis of L points fits a tile of cw lines: its work items within
+// one workgroup's waves and the tile within the LDS.
+template <typename T>
+bool axis_fits(int L, int cw, int max_smem) {
+  return pass_items(L, cw) <= wave_items<T>(cw) * kMaxWaves &&
+         (int64_t)pass_smem(L, sizeof(T), cw) <= (int64_t)max_smem;
+}
+
 // Tile width of a transform launch over `lines` lines in all: the wide tile
-// when that still gives many workgroups, else the narrow one.
-int choose_cw(int64_t lines) { return (lines + kCW - 1) / kCW >= kManyTiles ? kCW : kCWNarrow; }
+// when every axis of the launch fits it and it still gives many workgroups,
+// else the narrow one.
+int choose_cw(int64_t lines, bool wide_ok = true) {
+  return wide_ok && (lines + kCW - 1) / kCW >= kManyTiles ? kCW : kCWNarrow;
+}
 int64_t tiles_for(int64_t lines, int cw) { return (lines + cw - 1) / cw; }
 
 double axis_eig(int N, int nseg, int k) {
@@ -647,7 +662,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.grid_nodes = (unsigned)P->nblocks;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = P->d_zero_map;
-    const int cw = choose_cw(P->lines[a]);
+    const int cw = choose_cw(P->lines[a], P->wide_ok[a]);
     E.cw_axis[a] = cw;
     E.grid_axis[a] = (unsigned)tiles_for(P->lines[a], cw);
     E.smem_axis[a] = pass_smem(P->g.N[a], P->scalar_bytes, cw);
@@ -948,12 +963,15 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   int max_smem = 0;
   HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
   for (int a = 0; a <= D; ++a) {
-    const size_t need = pass_smem(g.N[a], P->scalar_bytes, kCW);
-    const bool fits = P->precision == DOT_FP64 ? axis_fits<double>(g.N[a]) : axis_fits<float>(g.N[a]);
-    if ((int64_t)need > max_smem || !fits)
+    auto fits = [&](int cw) {
+      return P->precision == DOT_FP64 ? axis_fits<double>(g.N[a], cw, max_smem)
+                                      : axis_fits<float>(g.N[a], cw, max_smem);
+    };
+    if (!fits(kCWNarrow))
       return fail(DOT_EINVAL, "axis of " + std::to_string(g.N[a]) + " nodes exceeds the transform tile capacity");
+    P->wide_ok[a] = fits(kCW);
     P->lines[a] = g.nb / g.N[a];
-    P->tiles[a] = tiles_for(P->lines[a], choose_cw(P->lines[a]));
+    P->tiles[a] = tiles_for(P->lines[a], choose_cw(P->lines[a], P->wide_ok[a]));
   }
   // problem data
   const int64_t nx = g.nx;
@@ -1190,8 +1208,12 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
     size_t smem = 0;
     int waves = 1;
     int64_t all_lines = 0;
-    for (int i = 0; i < count; ++i) all_lines += B->plans[i]->lines[a];
-    const int cw = choose_cw(all_lines);
+    bool wide_ok = true;
+    for (int i = 0; i < count; ++i) {
+      all_lines += B->plans[i]->lines[a];
+      wide_ok = wide_ok && B->plans[i]->wide_ok[a];
+    }
+    const int cw = choose_cw(all_lines, wide_ok);
     E.cw_axis[a] = cw;
     int64_t all_tiles = 0;
     for (int i = 0; i < count; ++i) all_tiles += tiles_for(B->plans[i]->lines[a], cw);
@@ -1604,8 +1626,12 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
   // transform tile width per axis, from the lines of all active instances
   for (int a = 0; a <= C->D; ++a) {
     int64_t all_lines = 0;
-    for (dot_plan* P : act) all_lines += P->lines[a];
-    E.cw_axis[a] = choose_cw(all_lines);
+    bool wide_ok = true;
+    for (dot_plan* P : act) {
+      all_lines += P->lines[a];
+      wide_ok = wide_ok && P->wide_ok[a];
+    }
+    E.cw_axis[a] = choose_cw(all_lines, wide_ok);
   }
   // descriptors of the active instances, in slot order
   uint32_t blk = 0;

@@ -68,6 +68,14 @@ struct AxisTab {
   int rb_e, rb_o, ks_e, ks_o;
 };
 
+// Work items a wave may take in one pass: a narrow tile has one accumulator
+// per item instead of two, so a wave holds twice as many items in the same
+// registers.
+template <typename T, int CW>
+constexpr int items_per_wave() {
+  return MfmaOps<T>::kItems * (CW >= 32 ? 1 : 2);
+}
+
 enum PassKind { kFwd = 0, kInv = 1, kFwdScaleInv = 2 };
 // What the first (time-axis forward) pass loads: the work plane itself (in
 // place), or an FP64 right-hand side plane (mixed-precision step call).
@@ -99,7 +107,7 @@ __device__ __forceinline__ int out_slot(bool inv, bool odd, int L, int r) {
 template <typename T, int CW>
 __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv) {
   typedef typename MfmaOps<T>::acc_t acc_t;
-  constexpr int KI = MfmaOps<T>::kItems;
+  constexpr int KI = items_per_wave<T, CW>();
   constexpr int NACC = CW >= 32 ? 2 : 1;
   constexpr int NG = CW / (16 * NACC);  // column groups per row block
   const int lane = threadIdx.x & 63;

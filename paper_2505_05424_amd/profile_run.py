@@ -4,7 +4,7 @@ counter collection:
   rocprofv3 --kernel-trace --stats --output-format csv -d OUT -- \
       python3 -m paper_2505_05424_amd.profile_run --workload 2d-32x64x64 --iters 500
 
-Workloads: 1d-16x32, 2d-32x64x64, 2d-64x256x256, 3d-32x64x64x64 (add
+Workloads: 1d-16x32, 2d-32x64x64, 2d-64x256x256, 3d-32x64x64x64, 2d-32x1024x1024 (add
 --mixed for the mixed-precision mode). --copy-mib M first runs one plain
 device-to-device copy of M MiB (torch), the calibration of the HBM byte
 counters."""
@@ -24,6 +24,7 @@ WORKLOADS = {
     "2d-32x64x64": dotgen.config2_instance,
     "2d-64x256x256": dotgen.config3_instance,
     "3d-32x64x64x64": dotgen.serving_3d_instance,
+    "2d-32x1024x1024": dotgen.image_like_instance,
 }
 
 
