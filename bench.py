@@ -206,6 +206,46 @@ def multilevel_section(torch, inst):
     return out
 
 
+def large_section(torch, st, iters=40, max_solve_s=60.0):
+    """The paper's large single-instance size, 2D 32x1024x1024 (image-like
+    mixtures of 16 narrow Gaussians stand in for its image pair): state size,
+    ms per iteration (after a warm-up, graphs on) in both modes, and a mixed
+    solve to eta_dot <= 1e-4 (the tolerance of the paper's 1024^2 runs),
+    stopped after `max_solve_s` seconds."""
+    inst = dotgen.image_like_instance()
+    out = {"workload": "2d-32x1024x1024-image-like", "nodes": int(np.prod([k + 1 for k in inst.n]))}
+    for prec, name in ((B.DOT_MIXED, "mixed"), (B.DOT_FP64, "fp64")):
+        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, None, tol=1e-4, max_iter=10 ** 6,
+                                 precision=prec)
+        buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+        B.dot_state_reset(plan, buf.data_ptr(), st)
+        B.dot_run(plan, buf.data_ptr(), 20, st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.dot_run(plan, buf.data_ptr(), iters, st)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / iters
+        rec = {"state_GB": plan.info.state_bytes / 1e9, "ms_per_iter": ms,
+               "min_bytes_frac_of_hbm_peak": PM.iteration_min_bytes(inst.D, inst.n, 8 if name == "fp64" else 4)
+               / (ms * 1e-3) / 1e9 / PM.HBM_PEAK_GBS}
+        if name == "mixed":
+            B.dot_state_reset(plan, buf.data_ptr(), st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while True:
+                r = B.dot_run(plan, buf.data_ptr(), 1000, st)
+                el = time.perf_counter() - t0
+                log(f"large: {r.iters} iterations, eta {r.eta_dot:.2e}, {el:.1f} s")
+                if B.TERM_NAMES[r.term] != "maxiter" or el > max_solve_s:
+                    break
+            rec["solve_tol_1e-4"] = {"iters": r.iters, "term": B.TERM_NAMES[r.term], "seconds": el,
+                                     "eta_dot": r.eta_dot, "objective": r.objective}
+        out[name] = rec
+        del buf
+        plan.close()
+    return out
+
+
 def batched_section(torch, st, count, sample, seed=4000):
     """Config-4-like batch: `count` instances (grid sides from {32..128}, n0
     from {16, 32, 64}, half masked), mixed precision, one launch per kernel
@@ -476,6 +516,8 @@ def main():
         "kernel_breakdown_one_solve": breakdown,
         "roofline_bandwidth_bound_size": large,
     }
+    log("large instance 32x1024x1024")
+    out["large_instance"] = large_section(torch, st)
     log("multilevel")
     out["multilevel"] = multilevel_section(torch, inst)
     log("variants (tau)")

@@ -289,6 +289,16 @@ void dot_ctx_destroy(dot_ctx* ctx);
  * exceeds the whole budget; DOT_EINVAL if D / precision differ from the
  * context's. The host arrays of p are copied before return. */
 int dot_ctx_submit(dot_ctx* ctx, const dot_problem* p, uint64_t* ticket);
+/* As dot_ctx_submit, for the multilevel solve of dot_solve_multilevel (the
+ * multilevel initialisation of Sec. 5.3): the coarse problems are built at
+ * submission (levels in 0..8; 0 is dot_ctx_submit), the request reserves the
+ * states of all levels in one arena block and iterates the coarsest level
+ * first; when a level stops (converged, diverged or at max_iter) its iterate
+ * is interpolated into the next finer level's state, sigma carried, and that
+ * level starts at the next step. Only the target level retires; its rho / m
+ * and result are what dot_ctx_fetch returns, bitwise those of
+ * dot_solve_multilevel with the same settings. */
+int dot_ctx_submit_ml(dot_ctx* ctx, const dot_problem* p, int32_t levels, uint64_t* ticket);
 /* Admit, run iters (a multiple of 10) iterations, retire; blocks until the
  * work is done. Optional outputs: running and queued counts after the step.
  * With nothing running, only admission happens. */

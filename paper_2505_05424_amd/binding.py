@@ -29,7 +29,7 @@ EXPORTED = [
     "dot_batch_create", "dot_batch_destroy", "dot_batch_workspace_bytes", "dot_batch_size", "dot_batch_reset",
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
     "dot_plan_set_graphs", "dot_batch_set_graphs",
-    "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_step", "dot_ctx_poll",
+    "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
 ]
 
@@ -158,6 +158,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_ctx_destroy.argtypes = [vp]
     lib.dot_ctx_destroy.restype = None
     lib.dot_ctx_submit.argtypes = [vp, ctypes.POINTER(dot_problem), ctypes.POINTER(ctypes.c_uint64)]
+    lib.dot_ctx_submit_ml.argtypes = [vp, ctypes.POINTER(dot_problem), i32, ctypes.POINTER(ctypes.c_uint64)]
     lib.dot_ctx_step.argtypes = [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.dot_ctx_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(i32)]
     lib.dot_ctx_fetch.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double),
@@ -557,6 +558,15 @@ def dot_ctx_submit(ctx: Ctx, inst, **kw) -> int:
     p, keep = make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=ctx.precision, **kw)
     t = ctypes.c_uint64()
     _check(load().dot_ctx_submit(ctx.handle, ctypes.byref(p), ctypes.byref(t)))
+    ctx.shapes[t.value] = (inst.D, tuple(int(k) for k in inst.n))
+    return t.value
+
+
+def dot_ctx_submit_ml(ctx: Ctx, inst, levels: int, **kw) -> int:
+    """Queue one multilevel solve (levels coarser grids first); returns its ticket."""
+    p, keep = make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=ctx.precision, **kw)
+    t = ctypes.c_uint64()
+    _check(load().dot_ctx_submit_ml(ctx.handle, ctypes.byref(p), int(levels), ctypes.byref(t)))
     ctx.shapes[t.value] = (inst.D, tuple(int(k) for k in inst.n))
     return t.value
 

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1411,6 +1412,13 @@ struct ProlongF {
   }
 };
 
+// Fine state from a coarse one: phi, z and the work planes cleared, q,
+// alpha and beta interpolated (the control block is left to the caller).
+int prolong_planes(const dot_plan* C, const void* coarse_state, dot_plan* F, void* fine_state, hipStream_t st) {
+  HIP_OK(hipMemsetAsync(fine_state, 0, F->ctl_offset, st));
+  return dispatch<ProlongF>(C->precision, C->D, C, coarse_state, F, fine_state, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1426,8 +1434,7 @@ int dot_prolong(const dot_plan* C, const void* coarse_state, dot_plan* F, void* 
   HIP_OK(hipMemcpyAsync(&cc, static_cast<const char*>(coarse_state) + C->ctl_offset, sizeof(Ctl),
                         hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  HIP_OK(hipMemsetAsync(fine_state, 0, F->ctl_offset, st));
-  int rc = dispatch<ProlongF>(C->precision, C->D, C, coarse_state, F, fine_state, st);
+  int rc = prolong_planes(C, coarse_state, F, fine_state, st);
   if (rc) return rc;
   Ctl h = initial_ctl(F);
   h.sigma = cc.sigma;
@@ -1553,14 +1560,24 @@ struct Arena {
 
 enum { kQueued = 0, kRunning = 1, kDone = 2 };
 
+// A request: one plan per level (coarsest first; one level for a plain
+// solve), all level states in one arena block.
 struct Request {
   uint64_t ticket = 0;
-  dot_plan* plan = nullptr;
+  std::vector<dot_plan*> plans;
+  std::vector<size_t> lvl_off;  // state offset of each level inside the block
+  size_t bytes = 0;             // block size
+  int level = 0;                // level being iterated
+  dot_plan* plan = nullptr;     // plans[level]
   int status = kQueued;
   int slot = -1;
-  size_t off = 0;
+  size_t block = 0;             // arena offset of the block
+  size_t off = 0;               // arena offset of the current level's state
   std::vector<double> rho, m;
   dot_result res{};
+  ~Request() {
+    for (auto* P : plans) dot_plan_destroy(P);
+  }
 };
 
 }  // namespace
@@ -1725,10 +1742,14 @@ int ctx_admit(dot_ctx* C, hipStream_t st) {
         break;
       }
     size_t off = 0;
-    if (sl < 0 || !C->arena.alloc(r->plan->state_bytes, &off)) break;  // head-of-line waits for space
+    if (sl < 0 || !C->arena.alloc(r->bytes, &off)) break;  // head-of-line waits for space
     C->queue.erase(C->queue.begin());
     r->slot = sl;
-    r->off = off;
+    r->block = off;
+    r->level = 0;
+    r->plan = r->plans[0];
+    r->off = off + r->lvl_off[0];
+    off = r->off;
     r->status = kRunning;
     C->slots[sl] = r;
     dot_plan* P = r->plan;
@@ -1754,6 +1775,27 @@ int ctx_retire(dot_ctx* C, hipStream_t st) {
     if (!r) continue;
     Ctl c = *reinterpret_cast<Ctl*>(reinterpret_cast<char*>(C->h_ctl) + (size_t)sl * C->ctl_stride);
     if (!c.stop && c.iter < r->plan->max_iter) continue;
+    if (r->level + 1 < (int)r->plans.size()) {
+      // multilevel: the next finer level starts from the interpolated
+      // iterate, whatever the coarse level's stop reason (as solved alone)
+      dot_plan* Pc = r->plans[r->level];
+      dot_plan* Pf = r->plans[r->level + 1];
+      char* cs = static_cast<char*>(C->arena_mem) + r->off;
+      char* fs = static_cast<char*>(C->arena_mem) + r->block + r->lvl_off[r->level + 1];
+      int rc = prolong_planes(Pc, cs, Pf, fs, st);
+      if (rc) return rc;
+      Ctl h = initial_ctl(Pf);
+      h.sigma = c.sigma;
+      h.iter_limit = Pf->max_iter;
+      HIP_OK(hipMemcpyAsync(reinterpret_cast<char*>(C->d_ctl) + (size_t)sl * C->ctl_stride, &h, sizeof(Ctl),
+                            hipMemcpyHostToDevice, st));
+      HIP_OK(hipStreamSynchronize(st));
+      r->level += 1;
+      r->plan = Pf;
+      r->off = r->block + r->lvl_off[r->level];
+      C->dirty = true;
+      continue;
+    }
     dot_plan* P = r->plan;
     const void* state = static_cast<char*>(C->arena_mem) + r->off;
     r->rho.assign((size_t)P->g.n[0] * P->g.nx, 0.0);
@@ -1764,7 +1806,7 @@ int ctx_retire(dot_ctx* C, hipStream_t st) {
     if (rc) return rc;
     fill_result(c, &r->res);
     r->status = kDone;
-    C->arena.release(r->off, P->state_bytes);
+    C->arena.release(r->block, r->bytes);
     C->slots[sl] = nullptr;
     // a free slot keeps stop = 1 so that polling ignores it
     Ctl dead{};
@@ -1802,8 +1844,7 @@ size_t dot_footprint_bytes(const dot_problem* p) {
 
 void dot_ctx_destroy(dot_ctx* C) {
   if (!C) return;
-  for (auto& r : C->all)
-    if (r && r->plan) dot_plan_destroy(r->plan);
+  C->all.clear();  // requests destroy their plans
   (void)hipFree(C->arena_mem);
   (void)hipFree(C->d_ctl);
   (void)hipHostFree(C->h_ctl);
@@ -1841,22 +1882,66 @@ int dot_ctx_create(int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_
   return DOT_OK;
 }
 
-int dot_ctx_submit(dot_ctx* C, const dot_problem* p, uint64_t* ticket) {
+int dot_ctx_submit_ml(dot_ctx* C, const dot_problem* p, int32_t levels, uint64_t* ticket) {
   if (!C || !p || !ticket) return fail(DOT_EINVAL, "null argument");
+  if (levels < 0 || levels > 8) return fail(DOT_EINVAL, "levels must be in 0..8");
   if (p->D != C->D || p->precision != C->precision) return fail(DOT_EINVAL, "problem D / precision differ from the context");
   if ((p->check_every > 0 ? p->check_every : 5) != 5) return fail(DOT_EINVAL, "serving needs the 5-iteration check cadence");
   if (p->max_iter % 5 != 0) return fail(DOT_EINVAL, "serving needs max_iter to be a multiple of 5");
-  if (dot_footprint_bytes(p) > C->budget) return fail(DOT_EBUSY, "problem can never fit the HBM budget");
-  dot_plan* P = nullptr;
-  int rc = dot_plan_create(p, &P);
+  int rc = validate(p);
   if (rc) return rc;
+  // problems of every level, coarsest first, as dot_solve_multilevel builds them
+  const int D = p->D;
+  std::vector<std::array<int32_t, 4>> n(levels + 1);
+  std::vector<std::vector<double>> r0(levels + 1), r1(levels + 1);
+  std::vector<std::vector<uint8_t>> mk(levels + 1);
+  size_t nx = 1;
+  for (int d = 1; d <= D; ++d) nx *= (size_t)p->n[d] + 1;
+  for (int d = 0; d < 4; ++d) n[levels][d] = p->n[d];
+  r0[levels].assign(p->rho0, p->rho0 + nx);
+  r1[levels].assign(p->rho1, p->rho1 + nx);
+  if (p->mask) mk[levels].assign(p->mask, p->mask + nx);
+  for (int l = levels - 1; l >= 0; --l) {
+    size_t ncx = 1;
+    for (int d = 0; d < 4; ++d) n[l][d] = d <= D ? n[l + 1][d] / 2 : 0;
+    for (int d = 1; d <= D; ++d) ncx *= (size_t)n[l][d] + 1;
+    r0[l].resize(ncx);
+    r1[l].resize(ncx);
+    if (!mk[l + 1].empty()) mk[l].resize(ncx);
+    rc = dot_coarsen_data(D, n[l + 1].data(), r0[l + 1].data(), r1[l + 1].data(),
+                          mk[l + 1].empty() ? nullptr : mk[l + 1].data(), r0[l].data(), r1[l].data(),
+                          mk[l].empty() ? nullptr : mk[l].data());
+    if (rc) return rc;
+  }
   auto r = std::make_unique<Request>();
+  size_t total = 0;
+  for (int l = 0; l <= levels; ++l) {
+    dot_problem q = *p;
+    for (int d = 0; d < 4; ++d) q.n[d] = n[l][d];
+    q.rho0 = r0[l].data();
+    q.rho1 = r1[l].data();
+    q.mask = mk[l].empty() ? nullptr : mk[l].data();
+    const int v = levels - l;  // coarse level v: max{tol 10^-v, 1e-6}
+    if (v > 0) q.tol = std::max(p->tol * std::pow(10.0, -v), 1e-6);
+    dot_plan* P = nullptr;
+    rc = dot_plan_create(&q, &P);
+    if (rc) return rc;
+    r->plans.push_back(P);
+    r->lvl_off.push_back(total);
+    total += align256(P->state_bytes);
+  }
+  if (total > C->budget) return fail(DOT_EBUSY, "problem can never fit the HBM budget");
+  r->bytes = total;
+  r->plan = r->plans[0];
   r->ticket = C->next_ticket++;
-  r->plan = P;
   *ticket = r->ticket;
   C->queue.push_back(r.get());
   C->all.push_back(std::move(r));
   return DOT_OK;
+}
+
+int dot_ctx_submit(dot_ctx* C, const dot_problem* p, uint64_t* ticket) {
+  return dot_ctx_submit_ml(C, p, 0, ticket);
 }
 
 int dot_ctx_step(dot_ctx* C, int32_t iters, void* stream, int32_t* n_active, int32_t* n_queued) {
@@ -1896,7 +1981,6 @@ int dot_ctx_fetch(dot_ctx* C, uint64_t ticket, double* rho_out, double* m_out, d
     if (rho_out) std::memcpy(rho_out, r->rho.data(), r->rho.size() * sizeof(double));
     if (m_out) std::memcpy(m_out, r->m.data(), r->m.size() * sizeof(double));
     if (res) *res = r->res;
-    dot_plan_destroy(r->plan);
     C->all.erase(it);
     return DOT_OK;
   }

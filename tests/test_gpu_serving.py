@@ -153,3 +153,52 @@ def test_server_mixes_2d_and_3d_lanes_and_keeps_each_result():
         for a, b in zip(req.m, ma):
             assert np.array_equal(a, b)
         assert req.latency > 0
+
+
+@pytest.mark.parametrize("prec,tol", [(B.DOT_FP64, 1e-7), (B.DOT_MIXED, 1e-5)])
+def test_multilevel_request_equals_the_multilevel_solve(prec, tol):
+    """Multilevel requests served next to plain ones: each coarse level
+    hands over to the next inside the context, and the target level's result
+    is bitwise that of dot_solve_multilevel."""
+    insts = [dotgen.tiny_instance(2, (16, 32, 24), seed=111, floor=0.01),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=112, floor=0.0, masked=True),
+             dotgen.tiny_instance(2, (8, 16, 16), seed=113, floor=0.0, masked=True),
+             dotgen.tiny_instance(2, (12, 33, 21), seed=114, floor=0.0, n_comp=3)]
+    levels = [2, 0, 1, 0]
+    arrivals = [0, 3, 5, 9]
+    print(f"[case] serving multilevel precision={prec} levels={levels}", flush=True)
+    ctx = B.dot_ctx_create(2, prec, 1 << 26, 3)
+    st = G.stream_handle()
+    tickets, done = {}, {}
+    for k in range(20000):
+        for i, a in enumerate(arrivals):
+            if a == k:
+                tickets[i] = B.dot_ctx_submit_ml(ctx, insts[i], levels[i], tol=tol, max_iter=40000)
+        B.dot_ctx_step(ctx, 10, st)
+        for i, t in list(tickets.items()):
+            if i not in done and B.dot_ctx_poll(ctx, t) == B.CTX_DONE:
+                done[i] = B.dot_ctx_fetch(ctx, t)
+        if len(done) == len(insts):
+            break
+    assert len(done) == len(insts)
+    free, admitted, retired = B.dot_ctx_stats(ctx)
+    assert admitted == retired == len(insts) and free == 1 << 26
+    for i, inst in enumerate(insts):
+        r, rho, m = done[i]
+        ra, rhoa, ma, _ = B.dot_solve_multilevel(2, inst.n, inst.rho0, inst.rho1, inst.mask, levels=levels[i],
+                                                 precision=prec, tol=tol, max_iter=40000)
+        assert B.TERM_NAMES[r.term] == "converged", i
+        _same(r, ra)
+        assert np.array_equal(rho, rhoa), i
+        for a, b in zip(m, ma):
+            assert np.array_equal(a, b), i
+    ctx.close()
+
+
+def test_multilevel_request_rejects_odd_grids():
+    ctx = B.dot_ctx_create(2, B.DOT_FP64, 1 << 24, 2)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_submit_ml(ctx, dotgen.tiny_instance(2, (6, 10, 9), seed=115), 1)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_submit_ml(ctx, dotgen.tiny_instance(2, (8, 16, 16), seed=116), 9)
+    ctx.close()
