@@ -95,8 +95,7 @@ template <typename T>
 __global__ void __launch_bounds__(1024)
 kb_finalize(const Inst<T>* __restrict__ I, int update_ctl) {
   const Inst<T>& s = I[blockIdx.x];
-  if (update_ctl && stopped(s)) return;
-  finalize_body(s.fa, s.partials, s.ctl, update_ctl);
+  finalize_body(s.fa, s.partials, s.ctl, update_ctl);  // returns before the update if the instance stopped
 }
 
 template <typename T, int D, int KIND, int SRC, int DST, int CW>

@@ -132,6 +132,7 @@ __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv
                                                                                   : (odd ? a.fo : a.fe)) +
                            (size_t)m * (ks / kU + 1) * 64 + lane;
     const int col = g * 16 * NACC + (lane & 15);
+    const int kr = (nin + 3) >> 2;  // k-steps holding inputs (the rest of the last chunk is zero padding)
     // coefficient fragments are prefetched one chunk of kU k-steps ahead
     chunk_t cur = tp[0];
     for (int st = 0; st < ks; st += kU) {
@@ -150,6 +151,7 @@ __device__ __forceinline__ void tile_mfma(T* tile, const AxisTab<T>& a, bool inv
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
+        if (st + u >= kr) break;  // zero coefficients only
 #pragma unroll
         for (int h = 0; h < NACC; ++h) acc[b][h] = MfmaOps<T>::mma(cur[u], bv[h][u], acc[b][h]);
       }

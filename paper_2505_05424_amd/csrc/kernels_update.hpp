@@ -628,9 +628,14 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
   __shared__ double acc[1024 / 64][kNumSums];
   __shared__ double tot[kNumSums];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // thread 0 requests the control block first, so that its latency overlaps
+  // the partial sums
+  Ctl c;
+  if (threadIdx.x == 0) c = *ctl;
   // one pass over the workgroup partials: each thread sums every slot of its
   // workgroups (slot-major rows, read coalesced), then the slots are reduced
-  // across the block
+  // across the block; waves past the last workgroup hold zeros and skip the
+  // cross-lane sums
   gp<const double> pr = glob(partials);
   double v[kNumSums];
 #pragma unroll
@@ -639,7 +644,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) v[k] += pr[k * fa.nblocks + j];
   }
-  wave_sums<kNumSums>(v);
+  if ((int64_t)w * 64 < fa.nblocks) wave_sums<kNumSums>(v);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) acc[w][k] = v[k];
@@ -652,6 +657,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
+  if (update_ctl && c.stop) return;  // a stopped instance keeps its last check
   const double vol = fa.vol;
   const double eta_p = eta_ratio(tot[0], tot[1], tot[2], vol);
   const double eta_d = sqrt(vol * tot[3]) / (1.0 + sqrt(vol * fa.c_norm2));
@@ -662,8 +668,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
   const double p2 = sqrt(vol * tot[11]) / (1.0 + sqrt(vol * fa.d_norm2));
   const double d2 = eta_ratio(tot[13], tot[14], tot[15], vol);
   const double eps = fmax(eta_p, p2), eds = fmax(eta_d, d2);
-  // work on a register copy of the control block: one load, one store
-  Ctl c = *ctl;
+  // the register copy of the control block is stored back once
   c.eta[0] = eta_dot;
   c.eta[1] = eta_p;
   c.eta[2] = eta_d;
