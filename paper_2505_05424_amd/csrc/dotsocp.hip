@@ -131,6 +131,7 @@ struct dot_plan {
   int64_t tiles[kMaxAxes] = {0, 0, 0, 0};  // transform tiles per axis at this plan's own tile width
   int64_t lines[kMaxAxes] = {0, 0, 0, 0};  // lines per axis (nb / N[a])
   bool wide_ok[kMaxAxes] = {true, true, true, true};  // the axis fits a tile of kCW lines
+  bool mid_ok[kMaxAxes] = {true, true, true, true};   // a tile of kCWMid lines fits in kMidLds
   // device constant tables
   double* sw_sp = nullptr;  // sqrt(omega/2) on spatial nodes
   double* om_sp = nullptr;  // omega on spatial nodes
@@ -268,10 +269,18 @@ bool axis_fits(int L, int cw, int max_smem) {
 }
 
 // Tile width of a transform launch over `lines` lines in all: the wide tile
-// when every axis of the launch fits it and it still gives many workgroups,
+// when every axis of the launch fits it and it still gives many workgroups;
+// else the middle width when its tile is small enough for several workgroups
+// per CU (kMidLds) and the launch keeps kMidTiles tiles (half the
+// coefficient traffic of the narrow tile; measured: 2D 64x128^2 mixed 167 ->
+// 153 us per iteration, neutral where the LDS or the tile count rule it out);
 // else the narrow one.
-int choose_cw(int64_t lines, bool wide_ok = true) {
-  return wide_ok && (lines + kCW - 1) / kCW >= kManyTiles ? kCW : kCWNarrow;
+constexpr int64_t kMidTiles = 256;
+constexpr size_t kMidLds = 40 << 10;
+int choose_cw(int64_t lines, bool wide_ok, bool mid_ok) {
+  if (wide_ok && (lines + kCW - 1) / kCW >= kManyTiles) return kCW;
+  if (mid_ok && (lines + kCWMid - 1) / kCWMid >= kMidTiles) return kCWMid;
+  return kCWNarrow;
 }
 int64_t tiles_for(int64_t lines, int cw) { return (lines + cw - 1) / cw; }
 
@@ -441,8 +450,11 @@ template <typename T, int D, int KIND, int SRC, int DST>
 int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
   (void)par;
   (void)sigma;
-  return E.cw_axis[a] == kCW ? launch_pass_cw<T, D, KIND, SRC, DST, kCW>(E, a, st)
-                             : launch_pass_cw<T, D, KIND, SRC, DST, kCWNarrow>(E, a, st);
+  switch (E.cw_axis[a]) {
+    case kCW: return launch_pass_cw<T, D, KIND, SRC, DST, kCW>(E, a, st);
+    case kCWMid: return launch_pass_cw<T, D, KIND, SRC, DST, kCWMid>(E, a, st);
+    default: return launch_pass_cw<T, D, KIND, SRC, DST, kCWNarrow>(E, a, st);
+  }
 }
 
 // The 2D+1 transform passes of one Poisson solve (a3 + a4): first pass on the
@@ -663,7 +675,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.grid_nodes = (unsigned)P->nblocks;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = P->d_zero_map;
-    const int cw = choose_cw(P->lines[a], P->wide_ok[a]);
+    const int cw = choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]);
     E.cw_axis[a] = cw;
     E.grid_axis[a] = (unsigned)tiles_for(P->lines[a], cw);
     E.smem_axis[a] = pass_smem(P->g.N[a], P->scalar_bytes, cw);
@@ -971,8 +983,9 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
     if (!fits(kCWNarrow))
       return fail(DOT_EINVAL, "axis of " + std::to_string(g.N[a]) + " nodes exceeds the transform tile capacity");
     P->wide_ok[a] = fits(kCW);
+    P->mid_ok[a] = fits(kCWMid) && pass_smem(g.N[a], P->scalar_bytes, kCWMid) <= kMidLds;
     P->lines[a] = g.nb / g.N[a];
-    P->tiles[a] = tiles_for(P->lines[a], choose_cw(P->lines[a], P->wide_ok[a]));
+    P->tiles[a] = tiles_for(P->lines[a], choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]));
   }
   // problem data
   const int64_t nx = g.nx;
@@ -1209,12 +1222,13 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
     size_t smem = 0;
     int waves = 1;
     int64_t all_lines = 0;
-    bool wide_ok = true;
+    bool wide_ok = true, mid_ok = true;
     for (int i = 0; i < count; ++i) {
       all_lines += B->plans[i]->lines[a];
       wide_ok = wide_ok && B->plans[i]->wide_ok[a];
+      mid_ok = mid_ok && B->plans[i]->mid_ok[a];
     }
-    const int cw = choose_cw(all_lines, wide_ok);
+    const int cw = choose_cw(all_lines, wide_ok, mid_ok);
     E.cw_axis[a] = cw;
     int64_t all_tiles = 0;
     for (int i = 0; i < count; ++i) all_tiles += tiles_for(B->plans[i]->lines[a], cw);
@@ -1643,12 +1657,13 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
   // transform tile width per axis, from the lines of all active instances
   for (int a = 0; a <= C->D; ++a) {
     int64_t all_lines = 0;
-    bool wide_ok = true;
+    bool wide_ok = true, mid_ok = true;
     for (dot_plan* P : act) {
       all_lines += P->lines[a];
       wide_ok = wide_ok && P->wide_ok[a];
+      mid_ok = mid_ok && P->mid_ok[a];
     }
-    E.cw_axis[a] = choose_cw(all_lines, wide_ok);
+    E.cw_axis[a] = choose_cw(all_lines, wide_ok, mid_ok);
   }
   // descriptors of the active instances, in slot order
   uint32_t blk = 0;

@@ -17,6 +17,7 @@
 namespace dot {
 
 constexpr int kCW = 64;        // lines per tile (launches with many tiles)
+constexpr int kCWMid = 32;     // lines per tile where 64 lines do not fit the LDS or give too few tiles
 constexpr int kCWNarrow = 16;  // lines per tile (launches with few tiles: 4x the workgroups)
 constexpr int kMaxWaves = 16;  // waves per workgroup (upper bound)
 constexpr int kU = 8;          // k-steps per prefetch chunk
