@@ -36,14 +36,18 @@ struct Inst {
   uint32_t tile0[kMaxAxes];  // first tile in each axis-pass grid
 };
 
+template <typename T>
+__device__ __forceinline__ bool stopped(const Inst<T>& s) {
+  return s.ctl && s.ctl->stop;
+}
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_cone_q0(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
-  const int32_t stop = stop_flag(s.ctl);
-  cone_q0_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.sw, s.q[par ^ 1], s.W, s.ctl, stop, L - s.blk0);
+  if (stopped(s)) return;
+  cone_q0_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.sw, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
 }
 
 template <typename T, int D>
@@ -51,8 +55,8 @@ __global__ void __launch_bounds__(256)
 kb_qd(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
-  const int32_t stop = stop_flag(s.ctl);
-  qd_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.ctl, stop, L - s.blk0);
+  if (stopped(s)) return;
+  qd_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
 }
 
 template <typename T, int D>
@@ -60,8 +64,8 @@ __global__ void __launch_bounds__(256)
 kb_beta(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par, int check) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
-  const int32_t stop = stop_flag(s.ctl);
-  beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, check, stop, L - s.blk0);
+  if (stopped(s)) return;
+  beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, check, L - s.blk0);
 }
 
 // Right-hand side (or its defect against phi) of the Poisson solve into the
@@ -71,9 +75,9 @@ __global__ void __launch_bounds__(256)
 kb_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par, double sigma_arg) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
-  const int32_t stop = stop_flag(s.ctl);
+  if (stopped(s)) return;
   const double inv_sigma = 1.0 / (s.ctl ? glob(s.ctl)->sigma : sigma_arg);
-  rhs_body<T, D, DEFECT>(s.g, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, stop, L - s.blk0);
+  rhs_body<T, D, DEFECT>(s.g, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
 }
 
 // Residual partials at the iterate held in q[par] (the newest q).
@@ -82,9 +86,8 @@ __global__ void __launch_bounds__(256)
 kb_resid(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
-  const int32_t stop = stop_flag(s.ctl);
-  resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials, stop,
-                   L - s.blk0);
+  if (stopped(s)) return;
+  resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials, L - s.blk0);
 }
 
 // One block per instance.
@@ -100,11 +103,11 @@ __global__ void __launch_bounds__(kMaxWaves * 64)
 kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int axis) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
-  const int32_t stop = stop_flag(s.ctl);
+  if (stopped(s)) return;
   PassArgs pa;
   pa.inner = s.g.stride[axis];
   pa.ncols = s.g.nb / s.g.N[axis];
-  axis_pass_body<T, D, KIND, SRC, DST, CW>(s.g, pa, s.tab[axis], s.work, s.phi, s.lam_other, s.lam_last, stop,
+  axis_pass_body<T, D, KIND, SRC, DST, CW>(s.g, pa, s.tab[axis], s.work, s.phi, s.lam_other, s.lam_last,
                                            (int64_t)(L - s.tile0[axis]));
 }
 

@@ -70,9 +70,4 @@ struct Ctl {
   double growth;         // growth factor of the sigma schedule gaps
 };
 
-// Stop flag of an instance (0 without a control block). Kernels read it at
-// entry and test it before their first store, so that its latency overlaps
-// their first loads; a stopped instance's state is left untouched.
-__device__ __forceinline__ int32_t stop_flag(const Ctl* ctl) { return ctl ? ctl->stop : 0; }
-
 }  // namespace dot

@@ -269,7 +269,7 @@ template <typename T, int D, int KIND, int SRC, int DST, int CW>
 __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa, const AxisTab<T>& a,
                                                T* __restrict__ plane, double* __restrict__ phi,
                                                const T* __restrict__ lam_other, const T* __restrict__ lam_last,
-                                               int32_t stop, int64_t blk) {
+                                               int64_t blk) {
   extern __shared__ unsigned char smem_raw[];
   T* tile = reinterpret_cast<T*>(smem_raw);
   const int L = a.L;
@@ -344,7 +344,6 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
       }
     }
   }
-  if (stop) return;  // uniform over the workgroup, before any store
   __syncthreads();
 
   if (KIND == kFwd || KIND == kFwdScaleInv) tile_forward<T, CW>(tile, a);

@@ -163,7 +163,7 @@ template <typename T, int D>
 __device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restrict__ phi_, const T* __restrict__ q_,
                                              double* __restrict__ alpha_, const T* __restrict__ beta_,
                                              const double* __restrict__ sw_sp, T* __restrict__ qn_, T* __restrict__ W_,
-                                             const Ctl* __restrict__ ctl, int32_t stop, uint32_t blk) {
+                                             const Ctl* __restrict__ ctl, uint32_t blk) {
   constexpr int K = 4 * D + 2;
   const Column c = column_of<D>(g, blk);
   const int tend = min(c.t1, g.n[0]);
@@ -196,7 +196,6 @@ __device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restr
     const double wl = u[K - 1] - 1.0 + (double)bt[K - 1] * inv_sigma;
     const double g0 = (ph1 - ph) * g.inv_h[0];
     const double q0n = (g0 + a0 * inv_sigma + wl - w0) * (1.0 / 3.0);
-    if (stop) return;
     qn[i] = (T)q0n;
     alpha[i] = a0 + tau * sigma * (g0 - q0n);
 #pragma unroll
@@ -241,8 +240,7 @@ __device__ __forceinline__ void qd_load(const Geo& g, const Column& c, int t, ui
 template <typename T, int D>
 __device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__ phi_, double* __restrict__ alpha_,
                                         const double* __restrict__ om_sp, T* __restrict__ qn_,
-                                        const T* __restrict__ W_, const Ctl* __restrict__ ctl, int32_t stop,
-                                        uint32_t blk) {
+                                        const T* __restrict__ W_, const Ctl* __restrict__ ctl, uint32_t blk) {
   const Column c = column_of<D>(g, blk);
   if (!c.live) return;
   gp<const double> phi = glob(phi_);
@@ -260,7 +258,6 @@ __device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__
   qd_load<T, D>(g, c, c.t0, i, phi, alpha, W, cur);
   for (int t = c.t0; t < c.t1; ++t, i += nx) {
     if (t + 1 < c.t1) qd_load<T, D>(g, c, t + 1, i + nx, phi, alpha, W, nxt);
-    if (stop) return;
     const bool has_now = t < g.n[0];
     const bool has_prev = t >= 1;
     const double ct = (double)has_now + (double)has_prev;
@@ -329,7 +326,7 @@ template <typename T, int D, bool DEFECT>
 __device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_, const double* __restrict__ al_,
                                          const double* __restrict__ phi_, const double* __restrict__ c_lo_,
                                          const double* __restrict__ c_hi_, T* __restrict__ out_, double inv_sigma,
-                                         int32_t stop, uint32_t blk) {
+                                         uint32_t blk) {
   const Column c = column_of<D>(g, blk);
   if (!c.live) return;
   gp<const T> q = glob(q_);
@@ -350,7 +347,6 @@ __device__ __forceinline__ void rhs_body(const Geo& g, const T* __restrict__ q_,
   rhs_load<T, D, DEFECT>(g, c, c.t0, i, q, al, phi, c_lo_, c_hi_, cur);
   for (int t = c.t0; t < c.t1; ++t, i += nx) {
     if (t + 1 < c.t1) rhs_load<T, D, DEFECT>(g, c, t + 1, i + nx, q, al, phi, c_lo_, c_hi_, nxt);
-    if (stop) return;
     double b = 0.0;
     if (t >= 1) b += y0m * g.inv_h[0];
     double y0 = 0.0;
@@ -440,7 +436,7 @@ __device__ __forceinline__ void block_slot11(double v, double* __restrict__ part
 template <typename T, int D>
 __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ qn_,
                                           T* __restrict__ beta_, const double* __restrict__ sw_sp, Ctl* __restrict__ ctl,
-                                          double* __restrict__ partials, int check, int32_t stop, uint32_t blk) {
+                                          double* __restrict__ partials, int check, uint32_t blk) {
   constexpr int K = 4 * D + 2;
   const Column c = column_of<D>(g, blk);
   const int tend = min(c.t1, g.n[0]);
@@ -465,7 +461,6 @@ __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_
       double u[K];
       cone_arg<T, D>(bt, (double)q[i], fa, fb, sw, inv_sigma, u);
       soc_project<K>(u);
-      if (stop) return;
       // r = z - (B F q_new + d), component by component
       const double q0 = (double)qn[i];
       auto upd = [&](int k, double bq) {
@@ -487,7 +482,6 @@ __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_
       shift_fq<T, D>(ga, gb);
     }
   }
-  if (stop) return;  // uniform over the workgroup
   if (check) block_slot11(ssq, partials, blk, g.nsweep);
   if (blk == 0 && threadIdx.x == 0) glob(ctl)->iter += 1;
 }
@@ -503,7 +497,7 @@ template <typename T, int D>
 __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, const T* q_, const double* alpha_,
                                            const T* beta_, const double* om_sp, const double* sw_sp,
                                            const double* c_lo_, const double* c_hi_, double* __restrict__ partials,
-                                           int32_t stop, uint32_t blk) {
+                                           uint32_t blk) {
   constexpr int K = 4 * D + 2;
   double s[kNumSums];
 #pragma unroll
@@ -611,7 +605,6 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
       }
     }
   }
-  if (stop) return;  // uniform over the workgroup
   block_partials<kNumSums>(s, partials, blk, g.nsweep, 11);
 }
 
