@@ -149,7 +149,11 @@ int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double
                         void* b, void* stream);
 /* a4: phi = (A^*A)^+ b in place on the node plane (phi-step of Algorithm 2): forward
  * DCT-II on every axis, divide by the eigenvalues, zero mode set to 0 (phi in
- * rge A^*), inverse transform. */
+ * rge A^*), inverse transform. A last axis of 257 or more nodes is not
+ * transformed: after the other axes' transforms each of its lines is a
+ * tridiagonal system (eigenvalue sum of the other axes + path-graph Laplacian
+ * / h^2), solved by elimination in FP64; same linear system, same phi up to
+ * rounding. */
 int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
 /* a3 + a4 as the iteration runs them (right-hand side sweep, then the
  * transform passes): phi from (q, alpha, sigma). */

@@ -34,6 +34,7 @@ struct Inst {
   FinArgs fa;
   uint32_t blk0;             // first block in the per-node grid
   uint32_t tile0[kMaxAxes];  // first tile in each axis-pass grid
+  int32_t tri;               // last axis solved by tridiagonal elimination (else transform, 1/Lambda, transform)
 };
 
 template <typename T>
@@ -104,11 +105,23 @@ kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, in
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[map[L]];
   if (stopped(s)) return;
+  if (KIND == kFwdScaleInv && s.tri) return;  // this instance's last axis takes kb_tri_pass
   PassArgs pa;
   pa.inner = s.g.stride[axis];
   pa.ncols = s.g.nb / s.g.N[axis];
   axis_pass_body<T, D, KIND, SRC, DST, CW>(s.g, pa, s.tab[axis], s.work, s.phi, s.lam_other, s.lam_last,
                                            (int64_t)(L - s.tile0[axis]));
+}
+
+// Last-axis tridiagonal solve over the tiles of the last-axis grid (CW lines
+// each); the c' coefficients go to W plane 0, free between the cone steps.
+template <typename T, int D, int CW>
+__global__ void __launch_bounds__(kTriThreads)
+kb_tri_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map) {
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
+  if (stopped(s) || !s.tri) return;
+  tri_pass_body<T, CW>(s.g, s.work, s.W, s.lam_other, (int64_t)(L - s.tile0[D]));
 }
 
 // ---- step-level kernels (single instance, caller pointers) ----------------

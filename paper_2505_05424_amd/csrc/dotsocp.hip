@@ -132,6 +132,8 @@ struct dot_plan {
   int64_t lines[kMaxAxes] = {0, 0, 0, 0};  // lines per axis (nb / N[a])
   bool wide_ok[kMaxAxes] = {true, true, true, true};  // the axis fits a tile of kCW lines
   bool mid_ok[kMaxAxes] = {true, true, true, true};   // a tile of kCWMid lines fits in kMidLds
+  bool tri = false;      // the last axis is solved by tridiagonal elimination
+  void* step_cbuf = nullptr;  // c' plane of the tridiagonal solve for step-level calls
   // device constant tables
   double* sw_sp = nullptr;  // sqrt(omega/2) on spatial nodes
   double* om_sp = nullptr;  // omega on spatial nodes
@@ -284,6 +286,12 @@ int choose_cw(int64_t lines, bool wide_ok, bool mid_ok) {
 }
 int64_t tiles_for(int64_t lines, int cw) { return (lines + cw - 1) / cw; }
 
+// Last axes of at least this many nodes are solved by tridiagonal elimination
+// (its cost per point does not grow with the axis length; measured per
+// iteration: 2D 32x1024^2 mixed 6.15 -> 5.13 ms, 2D 64x256^2 FP64 844 -> 823 us,
+// mixed 534 -> 531 us; slower than the folded transform at 129 nodes and below).
+constexpr int kTriMinNodes = 257;
+
 double axis_eig(int N, int nseg, int k) {
   const double s = std::sin(M_PI * k / (2.0 * N));
   return 4.0 * (double)nseg * (double)nseg * s * s;
@@ -381,6 +389,7 @@ Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, double* alp
   s.lam_last = (const T*)P->lam_last;
   for (int a = 0; a < kMaxAxes; ++a) s.tab[a] = tab_of<T>(P, a);
   s.fa = fin_args(P);
+  s.tri = P->tri;
   return s;
 }
 
@@ -419,6 +428,7 @@ struct Exec {
   size_t smem_axis[kMaxAxes] = {0, 0, 0, 0};
   int waves_axis[kMaxAxes] = {0, 0, 0, 0};
   int cw_axis[kMaxAxes] = {kCW, kCW, kCW, kCW};  // transform tile width per axis
+  int ntri = 0;  // instances whose last axis takes the tridiagonal solve
   Prof* prof = nullptr;
   int device = 0;
   struct GraphCache* graphs = nullptr;  // captured 10-iteration blocks (nullptr: plain launches)
@@ -459,9 +469,30 @@ int launch_pass(const Exec& E, int a, int par, double sigma, hipStream_t st) {
   }
 }
 
+// Tridiagonal last-axis solve over the last-axis tile grid (tiles of cw
+// lines).
+template <typename T, int D, int CW>
+int launch_tri_cw(const Exec& E, hipStream_t st) {
+  ProfScope ps(E.prof, DOT_K_DCT_LAST, st);
+  hipLaunchKernelGGL((kb_tri_pass<T, D, CW>), dim3(E.grid_axis[D]), dim3(kTriThreads), 0, st, (const Inst<T>*)E.d_inst,
+                     E.map_axis[D]);
+  HIP_OK(hipGetLastError());
+  return DOT_OK;
+}
+
+template <typename T, int D>
+int launch_tri(const Exec& E, hipStream_t st) {
+  switch (E.cw_axis[D]) {
+    case kCW: return launch_tri_cw<T, D, kCW>(E, st);
+    case kCWMid: return launch_tri_cw<T, D, kCWMid>(E, st);
+    default: return launch_tri_cw<T, D, kCWNarrow>(E, st);
+  }
+}
+
 // The 2D+1 transform passes of one Poisson solve (a3 + a4): first pass on the
 // time axis loads according to SRC, forward passes on the middle axes, the
-// fused forward/scale/inverse pass on the last axis, inverse passes back to
+// fused forward/scale/inverse pass on the last axis (or, for instances with
+// a long last axis, the tridiagonal solve along it), inverse passes back to
 // the time axis, which stores according to DST.
 template <typename T, int D, int SRC, int DST>
 int run_passes(const Exec& E, int par, double sigma, hipStream_t st) {
@@ -469,7 +500,9 @@ int run_passes(const Exec& E, int par, double sigma, hipStream_t st) {
   if ((rc = launch_pass<T, D, kFwd, SRC, kDstPlane>(E, 0, par, sigma, st))) return rc;
   for (int a = 1; a < D; ++a)
     if ((rc = launch_pass<T, D, kFwd, kSrcPlane, kDstPlane>(E, a, par, sigma, st))) return rc;
-  if ((rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane, kDstPlane>(E, D, par, sigma, st))) return rc;
+  if (E.ntri < E.ninst && (rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane, kDstPlane>(E, D, par, sigma, st)))
+    return rc;
+  if (E.ntri > 0 && (rc = launch_tri<T, D>(E, st))) return rc;
   for (int a = D - 1; a >= 1; --a)
     if ((rc = launch_pass<T, D, kInv, kSrcPlane, kDstPlane>(E, a, par, sigma, st))) return rc;
   return launch_pass<T, D, kInv, kSrcPlane, DST>(E, 0, par, sigma, st);
@@ -675,9 +708,11 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.d_inst = static_cast<char*>(P->d_inst) + slot * inst_slot_bytes();
   E.map_nodes = P->d_zero_map;
   E.grid_nodes = (unsigned)P->nblocks;
+  E.ntri = P->tri ? 1 : 0;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = P->d_zero_map;
-    const int cw = choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]);
+    // the tridiagonal last-axis solve takes full waves of 64 lines
+    const int cw = (a == P->D && P->tri) ? kCW : choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]);
     E.cw_axis[a] = cw;
     E.grid_axis[a] = (unsigned)tiles_for(P->lines[a], cw);
     E.smem_axis[a] = pass_smem(P->g.N[a], P->scalar_bytes, cw);
@@ -743,7 +778,8 @@ struct PoissonF {
   static int run(dot_plan* P, void* phi, const void* q, const void* al, double sigma, hipStream_t st) {
     Exec E = plan_exec(P, 1);
     E.prof = nullptr;
-    int rc = upload_inst(E, step_inst<T>(P, phi, q, al, nullptr, nullptr, nullptr, nullptr), st);
+    if (P->tri && !P->step_cbuf) HIP_OK(hipMalloc(&P->step_cbuf, (size_t)P->g.nb * sizeof(T)));
+    int rc = upload_inst(E, step_inst<T>(P, phi, q, al, nullptr, nullptr, P->step_cbuf, nullptr), st);
     if (rc) return rc;
     if (q && (rc = launch_rhs<T, D, false>(E, 0, sigma, st))) return rc;
     if constexpr (std::is_same<T, double>::value) {
@@ -930,6 +966,7 @@ void dot_plan_destroy(dot_plan* P) {
   (void)hipFree(P->d_zero_map);
   (void)hipFree(P->step_ctl);
   (void)hipFree(P->step_partials);
+  (void)hipFree(P->step_cbuf);
   (void)hipFree(P->step_scratch);
   (void)hipHostFree(P->host_ctl);
   delete P;
@@ -989,6 +1026,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
     P->lines[a] = g.nb / g.N[a];
     P->tiles[a] = tiles_for(P->lines[a], choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]));
   }
+  P->tri = g.N[D] >= kTriMinNodes;
   // problem data
   const int64_t nx = g.nx;
   double vol = 1.0;
@@ -1218,19 +1256,21 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
   E.device = B->plans[0]->device;
   for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)B->plans[i]->nblocks, (uint16_t)i);
   E.grid_nodes = (unsigned)maps.size();
+  for (auto* P : B->plans) E.ntri += P->tri ? 1 : 0;
   size_t map_off[kMaxAxes] = {0, 0, 0, 0};
   for (int a = 0; a <= D; ++a) {
     map_off[a] = maps.size();
     size_t smem = 0;
     int waves = 1;
     int64_t all_lines = 0;
-    bool wide_ok = true, mid_ok = true;
+    bool wide_ok = true, mid_ok = true, all_tri = true;
     for (int i = 0; i < count; ++i) {
       all_lines += B->plans[i]->lines[a];
       wide_ok = wide_ok && B->plans[i]->wide_ok[a];
       mid_ok = mid_ok && B->plans[i]->mid_ok[a];
+      all_tri = all_tri && B->plans[i]->tri;
     }
-    const int cw = choose_cw(all_lines, wide_ok, mid_ok);
+    const int cw = (a == D && all_tri) ? kCW : choose_cw(all_lines, wide_ok, mid_ok);
     E.cw_axis[a] = cw;
     int64_t all_tiles = 0;
     for (int i = 0; i < count; ++i) all_tiles += tiles_for(B->plans[i]->lines[a], cw);
@@ -1659,13 +1699,14 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
   // transform tile width per axis, from the lines of all active instances
   for (int a = 0; a <= C->D; ++a) {
     int64_t all_lines = 0;
-    bool wide_ok = true, mid_ok = true;
+    bool wide_ok = true, mid_ok = true, all_tri = true;
     for (dot_plan* P : act) {
       all_lines += P->lines[a];
       wide_ok = wide_ok && P->wide_ok[a];
       mid_ok = mid_ok && P->mid_ok[a];
+      all_tri = all_tri && P->tri;
     }
-    E.cw_axis[a] = choose_cw(all_lines, wide_ok, mid_ok);
+    E.cw_axis[a] = (a == C->D && all_tri) ? kCW : choose_cw(all_lines, wide_ok, mid_ok);
   }
   // descriptors of the active instances, in slot order
   uint32_t blk = 0;
@@ -1689,6 +1730,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
   }
   E.ninst = idx;
   E.grid_nodes = blk;
+  for (dot_plan* P : act) E.ntri += P->tri ? 1 : 0;
   size_t map_off[kMaxAxes] = {0, 0, 0, 0};
   for (int a = 0; a <= C->D; ++a) {
     map_off[a] = maps.size();

@@ -409,4 +409,180 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
   }
 }
 
+// Last-axis solve by tridiagonal elimination instead of forward transform,
+// 1/Lambda and inverse transform. After the transforms of the other axes the
+// system decouples into one tridiagonal system per line of the last axis:
+//   lambda x_i + n^2 (deg_i x_i - x_{i-1} - x_{i+1}) = b_i,
+// deg_i = 1 at the two ends and 2 inside (the path-graph Laplacian / h^2 that
+// the DCT-II diagonalises), lambda = the line's eigenvalue sum over the other
+// axes. lambda > 0: Thomas elimination in FP64 (diagonally dominant, no
+// pivoting; the pivot reciprocal is the hardware reciprocal refined by one
+// Newton step). lambda = 0 (the line of mode 0 on every other axis): the
+// singular Neumann system is solved through its fluxes
+// f_i = n^2 (x_{i+1} - x_i), f_0 = -b_0, f_i = f_{i-1} - b_i, and the line
+// mean is removed (the constant mode of phi is zero). A workgroup takes CW
+// consecutive lines (contiguous, stride 1 along the line) and walks them in
+// chunks of kTriChunk points: the next chunk is loaded coalesced (all
+// threads) while the current one is eliminated, one thread per line running
+// the recurrence on its chunk in registers; chunks pass through LDS. The
+// forward sweep stores d' in place and c' in `cpl`; the backward sweep
+// stores x.
+constexpr int kTriChunk = 32;
+constexpr int kTriThreads = 256;
+
+template <typename T, int CW>
+struct TriTile {
+  T a[2][CW][kTriChunk + 1];  // b, then d', then x (double buffered)
+  T c[2][CW][kTriChunk + 1];  // c'
+};
+
+// Coalesced copy of one chunk (CW lines x kTriChunk points; element e is
+// line e / kTriChunk, point e % kTriChunk) from a plane into registers, and
+// from there into one buffer of the tile.
+template <typename T, int CW>
+struct TriChunk {
+  static constexpr int kPer = (CW * kTriChunk + kTriThreads - 1) / kTriThreads;
+  T v[kPer];
+  __device__ __forceinline__ void load(gp<const T> src, uint32_t base, int L, int nl, int i0, int m) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int e = threadIdx.x + r * kTriThreads;
+      const int l = e / kTriChunk, j = e - l * kTriChunk;
+      v[r] = (l < nl && j < m) ? src[base + (uint32_t)l * L + i0 + j] : T(0);
+    }
+  }
+  __device__ __forceinline__ void put(T (&buf)[CW][kTriChunk + 1]) const {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const int e = threadIdx.x + r * kTriThreads;
+      const int l = e / kTriChunk, j = e - l * kTriChunk;
+      if (l < CW) buf[l][j] = v[r];
+    }
+  }
+};
+
+template <typename T, int CW>
+__device__ __forceinline__ void tri_store(gp<T> dst, const T (&buf)[CW][kTriChunk + 1], uint32_t base, int L, int nl,
+                                          int i0, int m) {
+  for (int e = threadIdx.x; e < CW * kTriChunk; e += kTriThreads) {
+    const int l = e / kTriChunk, j = e - l * kTriChunk;
+    if (l < nl && j < m) dst[base + (uint32_t)l * L + i0 + j] = buf[l][j];
+  }
+}
+
+__device__ __forceinline__ double tri_recip(double b) {
+  const double r = __builtin_amdgcn_rcp(b);
+  return r * fma(-b, r, 2.0);
+}
+
+template <typename T, int CW>
+__device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plane, T* __restrict__ cpl,
+                                              const T* __restrict__ lam_other, int64_t blk) {
+  const int D = g.D;
+  const int L = g.N[D];
+  const double s2 = (double)g.n[D] * (double)g.n[D];
+  const int64_t ncols = g.nb / L;
+  const int64_t c0 = blk * CW;
+  const int nl = (int)((ncols - c0) < CW ? (ncols - c0) : CW);  // lines of this tile
+  __shared__ TriTile<T, CW> tt;
+  gp<T> pl = glob(plane);
+  gp<T> cq = glob(cpl);
+  const uint32_t base = (uint32_t)c0 * (uint32_t)L;
+  const int me = threadIdx.x;
+  const bool owner = me < nl;
+  const double lam = owner ? (double)glob(lam_other)[c0 + me] : 1.0;
+  const bool zero = lam == 0.0;
+  const int nch = (L + kTriChunk - 1) / kTriChunk;
+  auto len = [&](int k) { return L - k * kTriChunk < kTriChunk ? L - k * kTriChunk : kTriChunk; };
+  double cp = 0.0, dp = 0.0, sum = 0.0;
+  TriChunk<T, CW> nx, nc;
+  // forward sweep
+  nx.load(pl, base, L, nl, 0, len(0));
+  nx.put(tt.a[0]);
+  __syncthreads();
+  for (int k = 0; k < nch; ++k) {
+    const int i0 = k * kTriChunk, m = len(k);
+    const int b = k & 1;
+    if (k + 1 < nch) nx.load(pl, base, L, nl, i0 + kTriChunk, len(k + 1));
+    if (owner) {
+      T rv[kTriChunk], cv[kTriChunk];
+#pragma unroll
+      for (int j = 0; j < kTriChunk; ++j) rv[j] = tt.a[b][me][j];
+#pragma unroll
+      for (int j = 0; j < kTriChunk; ++j) {
+        cv[j] = T(0);
+        if (j < m) {
+          const int i = i0 + j;
+          const double bj = (double)rv[j];
+          if (zero) {
+            // x_0 = 0, x_{i+1} = x_i + f_i / n^2 with f_i = f_{i-1} - b_i
+            rv[j] = (T)dp;
+            sum += dp;
+            cp -= bj;
+            dp += cp / s2;
+          } else {
+            const double diag = lam + s2 * ((i == 0 || i == L - 1) ? 1.0 : 2.0);
+            const double r = tri_recip(diag + s2 * cp);
+            cp = -s2 * r;
+            dp = (bj + s2 * dp) * r;
+            rv[j] = (T)dp;
+            cv[j] = (T)cp;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kTriChunk; ++j) {
+        tt.a[b][me][j] = rv[j];
+        tt.c[b][me][j] = cv[j];
+      }
+    }
+    __syncthreads();
+    tri_store<T, CW>(pl, tt.a[b], base, L, nl, i0, m);
+    tri_store<T, CW>(cq, tt.c[b], base, L, nl, i0, m);
+    if (k + 1 < nch) nx.put(tt.a[b ^ 1]);
+    __syncthreads();
+  }
+  // backward sweep: x_{L-1} = d'_{L-1}, x_i = d'_i - c'_i x_{i+1}, minus the
+  // line mean on the zero line
+  const double mean = zero ? sum / (double)L : 0.0;
+  double x = 0.0;
+  nx.load(pl, base, L, nl, (nch - 1) * kTriChunk, len(nch - 1));
+  nc.load(cq, base, L, nl, (nch - 1) * kTriChunk, len(nch - 1));
+  nx.put(tt.a[0]);
+  nc.put(tt.c[0]);
+  __syncthreads();
+  for (int k = nch - 1, u = 0; k >= 0; --k, ++u) {
+    const int i0 = k * kTriChunk, m = len(k);
+    const int b = u & 1;
+    if (k > 0) {
+      nx.load(pl, base, L, nl, i0 - kTriChunk, kTriChunk);
+      nc.load(cq, base, L, nl, i0 - kTriChunk, kTriChunk);
+    }
+    if (owner) {
+      T dv[kTriChunk], cv[kTriChunk];
+#pragma unroll
+      for (int j = 0; j < kTriChunk; ++j) {
+        dv[j] = tt.a[b][me][j];
+        cv[j] = tt.c[b][me][j];
+      }
+#pragma unroll
+      for (int j = kTriChunk - 1; j >= 0; --j) {
+        if (j < m) {
+          x = (double)dv[j] - (double)cv[j] * x;
+          dv[j] = (T)(x - mean);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kTriChunk; ++j) tt.a[b][me][j] = dv[j];
+    }
+    __syncthreads();
+    tri_store<T, CW>(pl, tt.a[b], base, L, nl, i0, m);
+    if (k > 0) {
+      nx.put(tt.a[b ^ 1]);
+      nc.put(tt.c[b ^ 1]);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace dot

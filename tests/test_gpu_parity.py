@@ -20,6 +20,8 @@ CASES = {
     "2d-1x1x1": lambda: dotgen.tiny_instance(2, (1, 1, 1), seed=24, floor=0.1),
     "1d-1x5": lambda: dotgen.tiny_instance(1, (1, 5), seed=25, floor=0.1),
     "1d-3x300": lambda: dotgen.tiny_instance(1, (3, 300), seed=26, floor=0.0),
+    # last axis of 301 nodes: solved by tridiagonal elimination, not transformed
+    "2d-long-last-4x7x300": lambda: dotgen.tiny_instance(2, (4, 7, 300), seed=27, floor=0.0, masked=True),
 }
 
 
@@ -41,7 +43,8 @@ def _random_state(P, seed):
     return phi, q, al, be
 
 
-STEP_CASES = ["1d-16x32", "2d-ragged-12x70x45", "2d-mask-8x20x24", "3d-6x9x10x7", "2d-1x1x1", "1d-1x5", "1d-3x300"]
+STEP_CASES = ["1d-16x32", "2d-ragged-12x70x45", "2d-mask-8x20x24", "3d-6x9x10x7", "2d-1x1x1", "1d-1x5", "1d-3x300",
+              "2d-long-last-4x7x300"]
 
 
 @pytest.mark.parametrize("name", STEP_CASES)
@@ -135,7 +138,7 @@ def test_step_residuals(name):
 
 
 RUN_CASES = [("1d-16x32", 400), ("2d-ragged-12x70x45", 150), ("2d-mask-8x20x24", 200), ("3d-6x9x10x7", 80),
-             ("2d-32x64x64", 60), ("1d-1x5", 100)]
+             ("2d-32x64x64", 60), ("1d-1x5", 100), ("2d-long-last-4x7x300", 60)]
 
 
 @pytest.mark.parametrize("name,iters", RUN_CASES)
