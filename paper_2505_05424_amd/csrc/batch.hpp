@@ -69,6 +69,22 @@ kb_beta(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par
   beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, check, L - s.blk0);
 }
 
+// beta update of iteration it (no residual check) and the right-hand side of
+// iteration it + 1 in one launch: both are sweeps over the same workgroups
+// and neither reads what the other writes (rhs reads the new q and alpha, and
+// phi for the defect; beta reads q, q_new and beta). sigma does not change
+// between them (no check).
+template <typename T, int D, bool DEFECT>
+__global__ void __launch_bounds__(256)
+kb_beta_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[map[L]];
+  if (stopped(s)) return;
+  const double inv_sigma = 1.0 / glob(s.ctl)->sigma;
+  beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, 0, L - s.blk0);
+  rhs_body<T, D, DEFECT>(s.g, s.q[par ^ 1], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
+}
+
 // Right-hand side (or its defect against phi) of the Poisson solve into the
 // transform work plane, from (q[par], alpha).
 template <typename T, int D, bool DEFECT>

@@ -524,10 +524,10 @@ int launch_rhs(const Exec& E, int par, double sigma, hipStream_t st) {
 }
 
 template <typename T, int D>
-int poisson_iter(const Exec& E, int par, hipStream_t st) {
+int poisson_iter(const Exec& E, int par, hipStream_t st, bool rhs_ready = false) {
   constexpr bool kMixed = !std::is_same<T, double>::value;
-  int rc = launch_rhs<T, D, kMixed>(E, par, 0.0, st);
-  if (rc) return rc;
+  int rc;
+  if (!rhs_ready && (rc = launch_rhs<T, D, kMixed>(E, par, 0.0, st))) return rc;
   if constexpr (kMixed)
     return run_passes<T, D, kSrcPlane, kDstPhiAdd>(E, par, 0.0, st);
   else
@@ -535,7 +535,7 @@ int poisson_iter(const Exec& E, int par, hipStream_t st) {
 }
 
 template <typename T, int D>
-int update_iter(const Exec& E, int par, int check, hipStream_t st) {
+int update_iter(const Exec& E, int par, int check, hipStream_t st, bool rhs_next = false) {
   const Inst<T>* I = (const Inst<T>*)E.d_inst;
   {
     ProfScope ps(E.prof, DOT_K_CONE, st);
@@ -547,7 +547,11 @@ int update_iter(const Exec& E, int par, int check, hipStream_t st) {
     hipLaunchKernelGGL((kb_qd<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
   }
   HIP_OK(hipGetLastError());
-  {
+  if (rhs_next) {
+    constexpr bool kMixed = !std::is_same<T, double>::value;
+    ProfScope ps(E.prof, DOT_K_BETA, st);
+    hipLaunchKernelGGL((kb_beta_rhs<T, D, kMixed>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
+  } else {
     ProfScope ps(E.prof, DOT_K_BETA, st);
     hipLaunchKernelGGL((kb_beta<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par, check);
   }
@@ -575,14 +579,21 @@ int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
 
 // One iteration of every instance of E: Poisson solve, cone and updates, and
 // on check iterations the residual reductions and the control update.
+// rhs_ready: the previous iteration's beta launch already computed this
+// iteration's right-hand side. Returns through *rhs_next whether this one
+// computed the next iteration's (it does when it has no residual check and
+// `more` says another iteration follows in the same launch sequence).
 template <typename T, int D>
-int one_iter(const Exec& E, int it, hipStream_t st) {
+int one_iter(const Exec& E, int it, hipStream_t st, bool rhs_ready, bool more, bool* rhs_next) {
   const int par = it & 1;
   int rc;
-  if ((rc = poisson_iter<T, D>(E, par, st))) return rc;
+  if ((rc = poisson_iter<T, D>(E, par, st, rhs_ready))) return rc;
   const int check = ((it + 1) % E.cadence) == 0;
-  if ((rc = update_iter<T, D>(E, par, check, st))) return rc;
+  // kernel classes timed one by one run unfused
+  const bool fuse = !check && more && !(E.prof && E.prof->cls >= 0);
+  if ((rc = update_iter<T, D>(E, par, check, st, fuse))) return rc;
   if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
+  *rhs_next = fuse;
   return DOT_OK;
 }
 
@@ -599,7 +610,8 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
   hipGraph_t graph = nullptr;
   HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   int rc = DOT_OK;
-  for (int k = 0; k < kGraphIters && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st);
+  bool ready = false;
+  for (int k = 0; k < kGraphIters && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st, ready, k + 1 < kGraphIters, &ready);
   hipError_t e = hipStreamEndCapture(st, &graph);
   if (rc) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -631,6 +643,7 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
   const bool graphs = E.graphs && E.graphs->enabled && !(E.prof && E.prof->cls >= 0) && E.cadence == 5;
   int j = 0;
   int since_poll = 0;
+  bool ready = false;  // this iteration's right-hand side was computed by the previous beta launch
   while (j < max_iters) {
     const int it = it0 + j;
     int rc;
@@ -638,10 +651,11 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
       hipGraphExec_t& ex = E.graphs->exec;
       if (!ex && (rc = capture_block<T, D>(E, it, &ex))) return rc;
       HIP_OK(hipGraphLaunch(ex, st));
+      ready = false;  // a block starts with its own right-hand side and ends with a check
       j += kGraphIters;
       since_poll += kGraphIters;
     } else {
-      if ((rc = one_iter<T, D>(E, it, st))) return rc;
+      if ((rc = one_iter<T, D>(E, it, st, ready, j + 1 < max_iters, &ready))) return rc;
       if (E.graphs) E.graphs->warm = true;
       ++j;
       ++since_poll;
