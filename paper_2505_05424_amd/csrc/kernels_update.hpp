@@ -492,7 +492,59 @@ __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_
 // 5 |alpha0 - max(0, f + alpha0)|^2, 6 |alpha0|^2, 7 |f|^2,
 // 8 |alpha_bar - g|^2, 9 |alpha_bar|^2, 10 |g|^2, 13 |F^*B^*beta + alpha|^2,
 // 14 |F^*B^*beta|^2, 15 |alpha|^2, 16 <c, phi>, 17 sum m^2 / r over r > 0.
-// (4, 11, 12 are filled elsewhere.)
+// (4, 11, 12 are filled elsewhere.) Values of node slice t that slice t+1
+// needs again (alpha0, phi, q_d on the time node, the cell's last two beta
+// components of each axis, alpha0 at x + e_d) are carried, and the loads of
+// slice t+1 are issued before slice t is summed.
+template <typename T, int D>
+struct ResSlice {
+  double a0;               // alpha0 at the cell t (t < n0)
+  double ad_lo[kMaxAxes];  // alpha_d at x - e_d (x_d >= 1)
+  double ad[kMaxAxes];     // alpha_d at x (x_d < n_d)
+  double cc;               // c~ on the boundary slices
+  double ph1;              // phi at t+1 (t < n0)
+  double phd[kMaxAxes];    // phi at x + e_d (x_d < n_d)
+  T q0, bK, b0;            // q0, beta_{K-1}, beta_0 at the cell t (t < n0)
+  T fq1[kMaxAxes][2];      // q_d at node t+1: x - e_d (x_d >= 1), x (x_d < n_d); t < n0
+  T b01[kMaxAxes][2];      // beta_{k}[x + e_d], beta_{k+1}[x] of the cell t (t < n0, x_d < n_d)
+  T b23[kMaxAxes][2];      // beta_{k+2}[x + e_d], beta_{k+3}[x] of the cell t (t < n0, x_d < n_d)
+  double a0s[kMaxAxes];    // alpha0 at x + e_d of the cell t (t < n0, x_d < n_d)
+};
+
+template <typename T, int D>
+__device__ __forceinline__ void res_load(const Geo& g, const Column& c, int t, uint32_t i, gp<const double> phi,
+                                         gp<const T> q, gp<const double> alpha, gp<const T> beta,
+                                         const double* c_lo, const double* c_hi, ResSlice<T, D>& s) {
+  constexpr int K = 4 * D + 2;
+  const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+  const int n0 = g.n[0];
+  const bool cell = t < n0;
+  s.a0 = cell ? alpha[i] : 0.0;
+  s.cc = t == 0 ? glob(c_lo)[c.xs] : (t == n0 ? glob(c_hi)[c.xs] : 0.0);
+  s.ph1 = cell ? phi[i + nx] : 0.0;
+  s.q0 = cell ? q[i] : T(0);
+  s.bK = cell ? beta[(size_t)(K - 1) * nb + i] : T(0);
+  s.b0 = cell ? beta[i] : T(0);
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    const uint32_t sd = (uint32_t)g.stride[d];
+    const bool lo = c.x[d] >= 1, hi = c.x[d] < g.n[d];
+    gp<const double> ad = alpha + (size_t)d * nb;
+    gp<const T> qd = q + (size_t)d * nb;
+    const int k = 1 + 4 * (d - 1);
+    s.ad_lo[d] = lo ? ad[i - sd] : 0.0;
+    s.ad[d] = hi ? ad[i] : 0.0;
+    s.phd[d] = hi ? phi[i + sd] : 0.0;
+    s.fq1[d][0] = cell && lo ? qd[i + nx - sd] : T(0);
+    s.fq1[d][1] = cell && hi ? qd[i + nx] : T(0);
+    s.b01[d][0] = cell && hi ? beta[(size_t)(k + 0) * nb + i + sd] : T(0);
+    s.b01[d][1] = cell && hi ? beta[(size_t)(k + 1) * nb + i] : T(0);
+    s.b23[d][0] = cell && hi ? beta[(size_t)(k + 2) * nb + i + sd] : T(0);
+    s.b23[d][1] = cell && hi ? beta[(size_t)(k + 3) * nb + i] : T(0);
+    s.a0s[d] = cell && hi ? alpha[i + sd] : 0.0;
+  }
+}
+
 template <typename T, int D>
 __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, const T* q_, const double* alpha_,
                                            const T* beta_, const double* om_sp, const double* sw_sp,
@@ -521,32 +573,49 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
       swb[d] = in ? swp[xs + (uint32_t)g.stride[d]] : 0.0;
     }
     uint32_t i = (uint32_t)c.t0 * nx + xs;
+    // carried values of node slice t: alpha0 at t-1, phi at t, q_d at node t,
+    // the last two beta components of cell t-1, alpha0 at x + e_d of cell t-1
+    double a0p = 0.0, ph = phi[i];
+    T fq0[kMaxAxes][2], b23p[kMaxAxes][2];
+    double a0sp[kMaxAxes];
+#pragma unroll
+    for (int d = 1; d <= D; ++d) {
+      const uint32_t sd = (uint32_t)g.stride[d];
+      const bool lo = c.x[d] >= 1, hi = c.x[d] < g.n[d];
+      gp<const T> qd = q + (size_t)d * nb;
+      const int k = 1 + 4 * (d - 1);
+      fq0[d][0] = lo ? qd[i - sd] : T(0);
+      fq0[d][1] = hi ? qd[i] : T(0);
+      const bool prev = c.t0 >= 1 && hi;
+      b23p[d][0] = prev ? beta[(size_t)(k + 2) * nb + i - nx + sd] : T(0);
+      b23p[d][1] = prev ? beta[(size_t)(k + 3) * nb + i - nx] : T(0);
+      a0sp[d] = prev ? alpha[i - nx + sd] : 0.0;
+    }
+    if (c.t0 >= 1) a0p = alpha[i - nx];
+    ResSlice<T, D> cur, nxt;
+    res_load<T, D>(g, c, c.t0, i, phi, q, alpha, beta, c_lo_, c_hi_, cur);
     for (int t = c.t0; t < c.t1; ++t, i += nx) {
+      if (t + 1 < c.t1) res_load<T, D>(g, c, t + 1, i + nx, phi, q, alpha, beta, c_lo_, c_hi_, nxt);
       // divergence residual at the node
       double div = 0.0;
-      if (t >= 1) div += (double)alpha[i - nx] * g.inv_h[0];
-      if (t < n0) div -= (double)alpha[i] * g.inv_h[0];
+      if (t >= 1) div += a0p * g.inv_h[0];
+      if (t < n0) div -= cur.a0 * g.inv_h[0];
 #pragma unroll
       for (int d = 1; d <= D; ++d) {
-        gp<const double> ad = alpha + (size_t)d * nb;
-        if (c.x[d] >= 1) div += (double)ad[i - (uint32_t)g.stride[d]] * g.inv_h[d];
-        if (c.x[d] < g.n[d]) div -= (double)ad[i] * g.inv_h[d];
+        if (c.x[d] >= 1) div += cur.ad_lo[d] * g.inv_h[d];
+        if (c.x[d] < g.n[d]) div -= cur.ad[d] * g.inv_h[d];
       }
-      double cc = 0.0;
-      if (t == 0) cc = glob(c_lo_)[xs];
-      if (t == n0) cc = glob(c_hi_)[xs];
-      div += cc;
-      const double ph = phi[i];
+      div += cur.cc;
       s[3] += div * div;
-      s[16] += cc * ph;
+      s[16] += cur.cc * ph;
       if (t < n0) {
         // q0, alpha0 at the cell
-        const double g0 = (phi[i + nx] - ph) * g.inv_h[0];
-        const double q0 = (double)q[i], a0 = (double)alpha[i];
+        const double g0 = (cur.ph1 - ph) * g.inv_h[0];
+        const double q0 = (double)cur.q0, a0 = cur.a0;
         s[0] += (g0 - q0) * (g0 - q0);
         s[1] += g0 * g0;
         s[2] += q0 * q0;
-        const double fb = (double)beta[(size_t)(K - 1) * nb + i] - (double)beta[i];
+        const double fb = (double)cur.bK - (double)cur.b0;
         s[13] += (fb + a0) * (fb + a0);
         s[14] += fb * fb;
         s[15] += a0 * a0;
@@ -554,14 +623,12 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
         double sq = 0.0;
 #pragma unroll
         for (int d = 1; d <= D; ++d) {
-          gp<const T> qd = q + (size_t)d * nb;
-          const uint32_t sd = (uint32_t)g.stride[d];
           if (c.x[d] >= 1) {
-            const double f1 = (double)qd[i - sd], f3 = (double)qd[i + nx - sd];
+            const double f1 = (double)fq0[d][0], f3 = (double)cur.fq1[d][0];
             sq += f1 * f1 + f3 * f3;
           }
           if (c.x[d] < g.n[d]) {
-            const double f2 = (double)qd[i], f4 = (double)qd[i + nx];
+            const double f2 = (double)fq0[d][1], f4 = (double)cur.fq1[d][1];
             sq += f2 * f2 + f4 * f4;
           }
         }
@@ -574,25 +641,22 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
 #pragma unroll
       for (int d = 1; d <= D; ++d) {
         if (c.x[d] >= g.n[d]) continue;
-        const uint32_t sd = (uint32_t)g.stride[d];
-        const double gd = (phi[i + sd] - ph) * g.inv_h[d];
-        const double qd = (double)q[(size_t)d * nb + i];
-        const double ad = (double)alpha[(size_t)d * nb + i];
+        const double gd = (cur.phd[d] - ph) * g.inv_h[d];
+        const double qd = (double)fq0[d][1];
+        const double ad = cur.ad[d];
         s[0] += (gd - qd) * (gd - qd);
         s[1] += gd * gd;
         s[2] += qd * qd;
         s[15] += ad * ad;
         // F^*B^* beta at this point, and r_d = L_X^d L_T^*(omega alpha0)
-        const int k = 1 + 4 * (d - 1);
         double fb = 0.0, r = 0.0;
         if (t < n0) {
-          fb += swb[d] * (double)beta[(size_t)(k + 0) * nb + i + sd] + swa * (double)beta[(size_t)(k + 1) * nb + i];
-          r += omb[d] * (double)alpha[i + sd] + oma * (double)alpha[i];
+          fb += swb[d] * (double)cur.b01[d][0] + swa * (double)cur.b01[d][1];
+          r += omb[d] * cur.a0s[d] + oma * cur.a0;
         }
         if (t >= 1) {
-          fb += swb[d] * (double)beta[(size_t)(k + 2) * nb + i - nx + sd] +
-                swa * (double)beta[(size_t)(k + 3) * nb + i - nx];
-          r += omb[d] * (double)alpha[i - nx + sd] + oma * (double)alpha[i - nx];
+          fb += swb[d] * (double)b23p[d][0] + swa * (double)b23p[d][1];
+          r += omb[d] * a0sp[d] + oma * a0p;
         }
         r *= 0.25;
         s[13] += (fb + ad) * (fb + ad);
@@ -603,6 +667,18 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
         s[10] += gg * gg;
         if (r > 0.0) s[17] += ad * ad / r;
       }
+      // carry to slice t+1
+      a0p = cur.a0;
+      ph = cur.ph1;
+#pragma unroll
+      for (int d = 1; d <= D; ++d) {
+        fq0[d][0] = cur.fq1[d][0];
+        fq0[d][1] = cur.fq1[d][1];
+        b23p[d][0] = cur.b23[d][0];
+        b23p[d][1] = cur.b23[d][1];
+        a0sp[d] = cur.a0s[d];
+      }
+      cur = nxt;
     }
   }
   block_partials<kNumSums>(s, partials, blk, g.nsweep, 11);
