@@ -194,7 +194,9 @@ typedef enum {
 /* Record HIP events around every launch of one kernel class inside dot_run
  * on its stream (DOT_K_NONE switches recording off); dot_profile_read returns
  * the summed event time in ms and the number of launches since the last read
- * and clears them. */
+ * and clears them. While a class is recorded, graphs are off and every class
+ * runs as its own launch (otherwise an iteration without a residual check
+ * computes the next iteration's right-hand side inside its beta launch). */
 int dot_profile_select(dot_plan* plan, int32_t kernel_class);
 int dot_profile_read(dot_plan* plan, double* total_ms, int64_t* launches);
 

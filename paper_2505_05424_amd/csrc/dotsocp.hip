@@ -1,8 +1,10 @@
 // Host driver and C ABI of the gfx950 inexact proximal ALM for dynamic OT
 // (arXiv 2505.05424, Algorithm 2). See include/dotsocp.h for the contract.
 //
-// Every iteration is a fixed sequence of launches (2D+1 cosine-transform
-// passes, three update sweeps, and at residual checks two reduction kernels).
+// Every iteration is a fixed sequence of launches: the right-hand side sweep
+// (or nothing, when the previous iteration's beta launch computed it), 2D+1
+// cosine-transform passes (the last-axis one a tridiagonal solve for long last
+// axes), three update sweeps, and at residual checks two reduction kernels.
 // Each launch covers all instances of an executor: one plan (dot_run, a batch
 // of one) or a batch (dot_batch_run), through the descriptor arrays of
 // batch.hpp.
