@@ -84,3 +84,26 @@ def test_batch_rejects_mixed_dimensions():
     b = dotgen.tiny_instance(1, (3, 4), seed=2)
     with pytest.raises(B.DotError):
         B.dot_batch_create([a, b])
+
+
+@pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
+def test_batch_mixing_tridiagonal_and_transform_last_axes(prec):
+    """A long last axis (301 nodes: tridiagonal solve) next to short ones
+    (transform, 1/Lambda, transform) in one batch: each instance gives bitwise
+    its solve alone."""
+    insts = [dotgen.tiny_instance(2, (4, 7, 300), seed=151, floor=0.0, masked=True),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=152, floor=0.0)]
+    print(f"[case] tridiagonal + transform batch precision={prec}", flush=True)
+    batch = B.dot_batch_create(insts, tol=-1.0, max_iter=100000, precision=prec)
+    ws = _torch_ws(batch.workspace_bytes)
+    st = G.stream_handle()
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    iters = 45
+    res = B.dot_batch_run(batch, ws.data_ptr(), iters, st)
+    for i, inst in enumerate(insts):
+        r, rho, m = _alone(inst, iters, prec, tol=-1.0, max_iter=100000)
+        rb, mb = B.dot_batch_extract(batch, ws.data_ptr(), i, st)
+        assert res[i].objective == r.objective, i
+        assert np.array_equal(rb, rho), i
+        for a, b in zip(mb, m):
+            assert np.array_equal(a, b), i
