@@ -37,16 +37,22 @@ struct Inst {
   int32_t tri;               // last axis solved by tridiagonal elimination (else transform, 1/Lambda, transform)
 };
 
+// Instance of logical block L: map[L], or 0 without a map (an executor of
+// one instance launches without one, saving the map load at every entry).
+__device__ __forceinline__ uint32_t inst_of_block(const uint16_t* __restrict__ map, uint32_t L) {
+  return map ? glob(map)[L] : 0u;
+}
+
 template <typename T>
 __device__ __forceinline__ bool stopped(const Inst<T>& s) {
-  return s.ctl && s.ctl->stop;
+  return s.ctl && glob(s.ctl)->stop;
 }
 
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_cone_q0(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
   cone_q0_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.sw, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
 }
@@ -55,7 +61,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_qd(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
   qd_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
 }
@@ -64,7 +70,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_beta(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par, int check) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
   beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, check, L - s.blk0);
 }
@@ -78,7 +84,7 @@ template <typename T, int D, bool DEFECT>
 __global__ void __launch_bounds__(256)
 kb_beta_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
   const double inv_sigma = 1.0 / glob(s.ctl)->sigma;
   beta_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.ctl, s.partials, 0, L - s.blk0);
@@ -91,7 +97,7 @@ template <typename T, int D, bool DEFECT>
 __global__ void __launch_bounds__(256)
 kb_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par, double sigma_arg) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
   const double inv_sigma = 1.0 / (s.ctl ? glob(s.ctl)->sigma : sigma_arg);
   rhs_body<T, D, DEFECT>(s.g, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
@@ -102,7 +108,7 @@ template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_resid(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
   resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials, L - s.blk0);
 }
@@ -119,7 +125,7 @@ template <typename T, int D, int KIND, int SRC, int DST, int CW>
 __global__ void __launch_bounds__(kMaxWaves * 64)
 kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int axis) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
   if (KIND == kFwdScaleInv && s.tri) return;  // this instance's last axis takes kb_tri_pass
   PassArgs pa;
@@ -135,7 +141,7 @@ template <typename T, int D, int CW>
 __global__ void __launch_bounds__(kTriThreads)
 kb_tri_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
-  const Inst<T>& s = I[map[L]];
+  const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s) || !s.tri) return;
   tri_pass_body<T, CW>(s.g, s.work, s.W, s.lam_other, (int64_t)(L - s.tile0[D]));
 }

@@ -148,7 +148,6 @@ struct dot_plan {
   AxisTab<float> tab32[kMaxAxes]{};
   // single-instance executor resources
   void* d_inst = nullptr;  // two descriptor slots: [0] dot_run, [1] step calls
-  uint16_t* d_zero_map = nullptr;
   Ctl* step_ctl = nullptr;
   double* step_partials = nullptr;
   void* step_scratch = nullptr;  // FP32 transform plane (mixed precision)
@@ -723,11 +722,11 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.ninst = 1;
   E.cadence = P->cadence;
   E.d_inst = static_cast<char*>(P->d_inst) + slot * inst_slot_bytes();
-  E.map_nodes = P->d_zero_map;
+  E.map_nodes = nullptr;  // one instance: blocks need no map
   E.grid_nodes = (unsigned)P->nblocks;
   E.ntri = P->tri ? 1 : 0;
   for (int a = 0; a <= P->D; ++a) {
-    E.map_axis[a] = P->d_zero_map;
+    E.map_axis[a] = nullptr;
     // the tridiagonal last-axis solve takes full waves of 64 lines
     const int cw = (a == P->D && P->tri) ? kCW : choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]);
     E.cw_axis[a] = cw;
@@ -980,7 +979,6 @@ void dot_plan_destroy(dot_plan* P) {
   (void)hipFree(P->lam_last);
   for (auto* b : P->axis_buf) (void)hipFree(b);
   (void)hipFree(P->d_inst);
-  (void)hipFree(P->d_zero_map);
   (void)hipFree(P->step_ctl);
   (void)hipFree(P->step_partials);
   (void)hipFree(P->step_cbuf);
@@ -1093,10 +1091,6 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   HIP_OK(hipMemset(P->step_partials, 0, (size_t)P->partial_rows * kNumSums * sizeof(double)));
   HIP_OK(hipHostMalloc((void**)&P->host_ctl, sizeof(Ctl), hipHostMallocDefault));
   HIP_OK(hipMalloc(&P->d_inst, 2 * inst_slot_bytes()));
-  int64_t maxgrid = P->partial_rows;
-  for (int a = 0; a <= D; ++a) maxgrid = std::max(maxgrid, tiles_for(P->lines[a], kCWNarrow));
-  HIP_OK(hipMalloc((void**)&P->d_zero_map, (size_t)maxgrid * sizeof(uint16_t)));
-  HIP_OK(hipMemset(P->d_zero_map, 0, (size_t)maxgrid * sizeof(uint16_t)));
   *out = P.release();
   return DOT_OK;
 }
