@@ -572,7 +572,7 @@ int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
   HIP_OK(hipGetLastError());
   {
     ProfScope ps(E.prof, DOT_K_FINAL, st);
-    hipLaunchKernelGGL((kb_finalize<T>), dim3(E.ninst), dim3(1024), 0, st, I, update_ctl);
+    hipLaunchKernelGGL((kb_finalize<T>), dim3(E.ninst), dim3(256), 0, st, I, update_ctl);
   }
   HIP_OK(hipGetLastError());
   return DOT_OK;
