@@ -218,14 +218,24 @@ def large_section(torch, st, iters=40, max_solve_s=60.0):
         plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, None, tol=1e-4, max_iter=10 ** 6,
                                  precision=prec)
         buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
-        B.dot_state_reset(plan, buf.data_ptr(), st)
-        B.dot_run(plan, buf.data_ptr(), 20, st)
-        torch.cuda.synchronize()
+
+        def ms_per_iter():
+            B.dot_state_reset(plan, buf.data_ptr(), st)
+            B.dot_run(plan, buf.data_ptr(), 20, st)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            B.dot_run(plan, buf.data_ptr(), iters, st)
+            torch.cuda.synchronize()
+            return 1e3 * (time.perf_counter() - t0) / iters
+
+        ms_rule = ms_per_iter()
+        # transform schedule measured on this instance (setup, before the timed runs)
         t0 = time.perf_counter()
-        B.dot_run(plan, buf.data_ptr(), iters, st)
-        torch.cuda.synchronize()
-        ms = 1e3 * (time.perf_counter() - t0) / iters
-        rec = {"state_GB": plan.info.state_bytes / 1e9, "ms_per_iter": ms,
+        sched = B.dot_plan_autotune(plan, buf.data_ptr(), st)
+        tune_s = time.perf_counter() - t0
+        ms = ms_per_iter()
+        rec = {"state_GB": plan.info.state_bytes / 1e9, "ms_per_iter": ms, "ms_per_iter_rule_schedule": ms_rule,
+               "transform_schedule": sched, "autotune_s": tune_s,
                "min_bytes_frac_of_hbm_peak": PM.iteration_min_bytes(inst.D, inst.n, 8 if name == "fp64" else 4)
                / (ms * 1e-3) / 1e9 / PM.HBM_PEAK_GBS}
         if name == "mixed":
@@ -254,8 +264,12 @@ def batched_section(torch, st, count, sample, seed=4000):
     insts = dotgen.config4_instances(count, seed=seed)
     batch = B.dot_batch_create(insts, tol=TOL, max_iter=BATCH_MAX_ITER, precision=B.DOT_MIXED)
     ws = torch.zeros(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
+    # transform schedule of this batch's launches, measured before the timed run
+    t0 = time.perf_counter()
+    sched = B.dot_batch_autotune(batch, ws.data_ptr(), st)
+    tune_s = time.perf_counter() - t0
     B.dot_batch_reset(batch, ws.data_ptr(), st)
-    log(f"batched: {count} instances, workspace {batch.workspace_bytes / 2**30:.2f} GiB")
+    log(f"batched: {count} instances, workspace {batch.workspace_bytes / 2**30:.2f} GiB, schedule {sched}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
@@ -291,6 +305,8 @@ def batched_section(torch, st, count, sample, seed=4000):
         "iteration_cap": BATCH_MAX_ITER,
         "mean_iters": inst_iters / count,
         "nodes_total": nodes,
+        "transform_schedule": sched,
+        "autotune_s": tune_s,
         "beta_kernel": {"avg_launch_us_first_400_iters": avg_us, "algorithmic_bytes": kb,
                         "achieved_GBs": kb / (avg_us * 1e-6) / 1e9,
                         "frac_of_hbm_peak": kb / (avg_us * 1e-6) / 1e9 / PM.HBM_PEAK_GBS},
@@ -314,6 +330,7 @@ def batched_section(torch, st, count, sample, seed=4000):
     log("batched sample")
     sub = B.dot_batch_create(insts[:sample], tol=TOL, max_iter=BATCH_MAX_ITER, precision=B.DOT_MIXED)
     ws2 = torch.zeros(sub.workspace_bytes, dtype=torch.uint8, device="cuda")
+    B.dot_batch_autotune(sub, ws2.data_ptr(), st)
     B.dot_batch_reset(sub, ws2.data_ptr(), st)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -489,6 +506,9 @@ def main():
         "config": {"workload": f"2d-{n[0]}x{n[1]}x{n[2]}-gaussmix3-fp64", "D": D, "n": list(n),
                    "tol": TOL, "precision": "fp64", "instances": 1, "hip_graphs": True},
         "palm_iters_per_s": sum(iters) / el,
+        # the launch-size rule's schedule (the autotuner gains < 1% at this size and its
+        # choice may vary run to run; the roofline kernel must match the committed profile)
+        "transform_schedule": B.dot_plan_get_schedule(plan),
         "iters_per_solve": iters[0],
         "eta_dot": last.eta_dot,
         "objective": last.objective,

@@ -231,6 +231,43 @@ int dot_batch_profile_read(dot_batch* batch, double* total_ms, int64_t* launches
 int dot_plan_set_graphs(dot_plan* plan, int32_t enable);
 int dot_batch_set_graphs(dot_batch* batch, int32_t enable);
 
+/* ---- transform schedules and their autotuner ----------------------------- */
+/* The cosine-transform passes of the phi-step (Sec. 4, the Poisson solve of
+ * Algorithm 2) run one workgroup per tile of cw lines of an axis, with `waves`
+ * 64-lane wavefronts per workgroup. By default both come from a rule on the
+ * launch's line count. A schedule changes no computed value: every line's
+ * products run in one wavefront in a fixed order, so results are bitwise
+ * those of any other schedule (and a batch member still equals its solve
+ * alone). The last axis of instances solved by tridiagonal elimination (>= 257
+ * nodes) keeps 64-line tiles when every instance of the launch takes it. */
+typedef struct {
+  int32_t cw[4];       /* lines per tile, axes 0..D: 16, 32 or 64 (set calls: 0 keeps the rule's) */
+  int32_t waves[4];    /* wavefronts per workgroup, 1..16, enough for the axis's work items
+                          (set calls: 0 keeps the rule's for that tile width) */
+  int32_t tuned;       /* out: 1 when the schedule was chosen by an autotune call */
+  int32_t candidates;  /* out: schedules the autotune call timed */
+  double us;           /* out (autotune): one transform sequence (all passes of one phi-step), us */
+  double us_rule;      /* out (autotune): the same with the rule's schedule */
+} dot_schedule;
+
+/* Install a schedule (NULL: the rule's) for later runs; DOT_EINVAL when an
+ * axis's tile does not fit the LDS of some instance or the waves cannot hold
+ * its work items. Captured graphs are dropped and re-captured on the next run. */
+int dot_plan_set_schedule(dot_plan* plan, const dot_schedule* schedule);
+int dot_batch_set_schedule(dot_batch* batch, const dot_schedule* schedule);
+/* The schedule in use (the rule's values written out when none is set). */
+int dot_plan_get_schedule(const dot_plan* plan, dot_schedule* out);
+int dot_batch_get_schedule(const dot_batch* batch, dot_schedule* out);
+/* Autotuner: times the transform sequence with HIP events on `stream` for
+ * every candidate schedule (each tile width the axis fits; per width the
+ * fewest waves that hold its work items, 4, 8, 16, one per item and the
+ * rule's), one axis at a time with the others at their best so far, and
+ * installs the fastest (the rule's unless a measured schedule beats it).
+ * The state / workspace is overwritten and left as after dot_state_reset /
+ * dot_batch_reset. Blocks; fills *out (may be NULL). */
+int dot_plan_autotune(dot_plan* plan, void* state, void* stream, dot_schedule* out);
+int dot_batch_autotune(dot_batch* batch, void* workspace, void* stream, dot_schedule* out);
+
 /* One-shot, blocking: allocate, solve, copy rho/m out (either may be NULL),
  * free. rho_out: n0*prod(n_d+1); m_out: sum_d |G^s_d| doubles. */
 int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* res);

@@ -29,6 +29,8 @@ EXPORTED = [
     "dot_batch_create", "dot_batch_destroy", "dot_batch_workspace_bytes", "dot_batch_size", "dot_batch_reset",
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
     "dot_plan_set_graphs", "dot_batch_set_graphs",
+    "dot_plan_set_schedule", "dot_batch_set_schedule", "dot_plan_get_schedule", "dot_batch_get_schedule",
+    "dot_plan_autotune", "dot_batch_autotune",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
 ]
@@ -98,6 +100,17 @@ class dot_plan_info(ctypes.Structure):
     ]
 
 
+class dot_schedule(ctypes.Structure):
+    _fields_ = [
+        ("cw", ctypes.c_int32 * 4),
+        ("waves", ctypes.c_int32 * 4),
+        ("tuned", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("us", ctypes.c_double),
+        ("us_rule", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -150,6 +163,11 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_double), vp]
     lib.dot_plan_set_graphs.argtypes = [vp, i32]
     lib.dot_batch_set_graphs.argtypes = [vp, i32]
+    for fn in ("dot_plan_set_schedule", "dot_batch_set_schedule", "dot_plan_get_schedule",
+               "dot_batch_get_schedule"):
+        getattr(lib, fn).argtypes = [vp, ctypes.POINTER(dot_schedule)]
+    lib.dot_plan_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(dot_schedule)]
+    lib.dot_batch_autotune.argtypes = [vp, vp, vp, ctypes.POINTER(dot_schedule)]
     lib.dot_batch_profile_select.argtypes = [vp, i32]
     lib.dot_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.dot_footprint_bytes.argtypes = [ctypes.POINTER(dot_problem)]
@@ -330,6 +348,57 @@ def dot_plan_set_graphs(plan, enable: bool):
 
 def dot_batch_set_graphs(batch, enable: bool):
     _check(load().dot_batch_set_graphs(batch.handle, int(bool(enable))))
+
+
+def _schedule_dict(s: dot_schedule, D: int) -> dict:
+    return {"cw": list(s.cw)[:D + 1], "waves": list(s.waves)[:D + 1], "tuned": bool(s.tuned),
+            "candidates": int(s.candidates), "us": float(s.us), "us_rule": float(s.us_rule)}
+
+
+def _schedule_struct(cw=None, waves=None) -> dot_schedule:
+    s = dot_schedule()
+    for a, v in enumerate(cw or []):
+        s.cw[a] = int(v)
+    for a, v in enumerate(waves or []):
+        s.waves[a] = int(v)
+    return s
+
+
+def dot_plan_set_schedule(plan, cw=None, waves=None):
+    """cw / waves: per-axis lists (0 keeps the rule's); both None restores the rule."""
+    s = None if cw is None and waves is None else ctypes.byref(_schedule_struct(cw, waves))
+    _check(load().dot_plan_set_schedule(plan.handle, s))
+
+
+def dot_batch_set_schedule(batch, cw=None, waves=None):
+    s = None if cw is None and waves is None else ctypes.byref(_schedule_struct(cw, waves))
+    _check(load().dot_batch_set_schedule(batch.handle, s))
+
+
+def dot_plan_get_schedule(plan) -> dict:
+    s = dot_schedule()
+    _check(load().dot_plan_get_schedule(plan.handle, ctypes.byref(s)))
+    return _schedule_dict(s, plan.D)
+
+
+def dot_batch_get_schedule(batch) -> dict:
+    s = dot_schedule()
+    _check(load().dot_batch_get_schedule(batch.handle, ctypes.byref(s)))
+    return _schedule_dict(s, batch.insts[0].D)
+
+
+def dot_plan_autotune(plan, state_ptr: int, stream: int = 0) -> dict:
+    s = dot_schedule()
+    _check(load().dot_plan_autotune(plan.handle, ctypes.c_void_p(state_ptr), ctypes.c_void_p(stream),
+                                    ctypes.byref(s)))
+    return _schedule_dict(s, plan.D)
+
+
+def dot_batch_autotune(batch, ws_ptr: int, stream: int = 0) -> dict:
+    s = dot_schedule()
+    _check(load().dot_batch_autotune(batch.handle, ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream),
+                                     ctypes.byref(s)))
+    return _schedule_dict(s, batch.insts[0].D)
 
 
 def dot_profile_select(plan, kernel_class: int):

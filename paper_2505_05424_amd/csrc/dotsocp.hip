@@ -116,6 +116,19 @@ struct GraphCache {
   }
 };
 
+// Transform schedule of an executor: tile width (lines per workgroup) and
+// waves per workgroup of the passes over each axis; 0 takes the launch-size
+// rule. Neither changes a computed value (each line's products run in one
+// wave in a fixed order whatever the tile and wave count).
+struct Sched {
+  int cw[kMaxAxes] = {0, 0, 0, 0};
+  int waves[kMaxAxes] = {0, 0, 0, 0};
+  bool tuned = false;   // set by the autotuner (measured), not by the rule or the caller
+  int candidates = 0;   // schedules the autotuner timed
+  double us = 0.0;      // one transform sequence with this schedule (autotuner), us
+  double us_rule = 0.0; // the same with the rule's schedule
+};
+
 }  // namespace
 
 struct dot_plan {
@@ -130,12 +143,12 @@ struct dot_plan {
   double vol = 1.0, c_norm2 = 0.0, d_norm2 = 0.0;
   int64_t nblocks = 0;       // workgroups of one node sweep (g.nsweep)
   int64_t partial_rows = 0;  // capacity of the partial-sum rows (nsweep at one slice per workgroup)
-  int64_t tiles[kMaxAxes] = {0, 0, 0, 0};  // transform tiles per axis at this plan's own tile width
   int64_t lines[kMaxAxes] = {0, 0, 0, 0};  // lines per axis (nb / N[a])
   bool wide_ok[kMaxAxes] = {true, true, true, true};  // the axis fits a tile of kCW lines
   bool mid_ok[kMaxAxes] = {true, true, true, true};   // a tile of kCWMid lines fits in kMidLds
   bool tri = false;      // the last axis is solved by tridiagonal elimination
   void* step_cbuf = nullptr;  // c' plane of the tridiagonal solve for step-level calls
+  Sched sched;                // transform schedule of this plan's own launches
   // device constant tables
   double* sw_sp = nullptr;  // sqrt(omega/2) on spatial nodes
   double* om_sp = nullptr;  // omega on spatial nodes
@@ -286,6 +299,78 @@ int choose_cw(int64_t lines, bool wide_ok, bool mid_ok) {
   return kCWNarrow;
 }
 int64_t tiles_for(int64_t lines, int cw) { return (lines + cw - 1) / cw; }
+
+// Launch geometry of the passes over axis a of one launch covering the
+// instances plans[0..count): tile width and waves from s where it sets them,
+// else from the rules above (the tridiagonal-only last axis keeps the wide
+// tile: its pass takes a full wave of lines), and the LDS bytes.
+struct AxisGeom {
+  int cw = kCW, waves = 4;
+  int64_t tiles = 0;
+  size_t smem = 0;
+};
+template <typename T>
+AxisGeom axis_geom(dot_plan* const* plans, int count, int a, const Sched& s) {
+  int64_t all_lines = 0;
+  bool wide_ok = true, mid_ok = true, all_tri = true;
+  for (int i = 0; i < count; ++i) {
+    all_lines += plans[i]->lines[a];
+    wide_ok = wide_ok && plans[i]->wide_ok[a];
+    mid_ok = mid_ok && plans[i]->mid_ok[a];
+    all_tri = all_tri && plans[i]->tri;
+  }
+  AxisGeom ag;
+  ag.cw = s.cw[a] ? s.cw[a] : ((a == plans[0]->D && all_tri) ? kCW : choose_cw(all_lines, wide_ok, mid_ok));
+  for (int i = 0; i < count; ++i) ag.tiles += tiles_for(plans[i]->lines[a], ag.cw);
+  int waves = 1;
+  for (int i = 0; i < count; ++i) {
+    ag.smem = std::max(ag.smem, pass_smem(plans[i]->g.N[a], (int)sizeof(T), ag.cw));
+    waves = std::max(waves, pass_waves<T>(plans[i]->g.N[a], ag.tiles, ag.cw));
+  }
+  ag.waves = s.waves[a] ? s.waves[a] : waves;
+  return ag;
+}
+
+// Schedules of axis a that every instance of a launch can take: the tile
+// widths its LDS and waves hold (the wide one only where the rule may pick
+// it; the tridiagonal-only last axis keeps its tile) and, per width, the wave
+// counts from the fewest that hold every work item up to kMaxWaves (that
+// fewest, 4, 8, 16, one wave per item, the rule's).
+template <typename T>
+std::vector<std::pair<int, int>> axis_candidates(dot_plan* const* plans, int count, int a, int max_smem) {
+  std::vector<std::pair<int, int>> out;
+  bool all_tri = true, wide_ok = true, mid_fits = true;
+  for (int i = 0; i < count; ++i) {
+    all_tri = all_tri && plans[i]->tri;
+    wide_ok = wide_ok && plans[i]->wide_ok[a];
+    mid_fits = mid_fits && axis_fits<T>(plans[i]->g.N[a], kCWMid, max_smem);
+  }
+  if (a == plans[0]->D && all_tri) {
+    Sched s;
+    s.cw[a] = kCW;
+    out.push_back({kCW, axis_geom<T>(plans, count, a, s).waves});
+    return out;
+  }
+  for (int cw : {kCWNarrow, kCWMid, kCW}) {
+    if ((cw == kCW && !wide_ok) || (cw == kCWMid && !mid_fits)) continue;
+    int lo = 1, items = 1;
+    for (int i = 0; i < count; ++i) {
+      const int it = pass_items(plans[i]->g.N[a], cw);
+      items = std::max(items, it);
+      lo = std::max(lo, (it + wave_items<T>(cw) - 1) / wave_items<T>(cw));
+    }
+    if (lo > kMaxWaves) continue;
+    Sched s;
+    s.cw[a] = cw;
+    const int rule = axis_geom<T>(plans, count, a, s).waves;
+    std::vector<int> ws = {lo, 4, 8, 16, std::min(items, kMaxWaves), rule};
+    std::sort(ws.begin(), ws.end());
+    ws.erase(std::unique(ws.begin(), ws.end()), ws.end());
+    for (int w : ws)
+      if (w >= lo && w <= kMaxWaves) out.push_back({cw, w});
+  }
+  return out;
+}
 
 // Last axes of at least this many nodes are solved by tridiagonal elimination
 // (its cost per point does not grow with the axis length; measured per
@@ -727,13 +812,12 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.ntri = P->tri ? 1 : 0;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = nullptr;
-    // the tridiagonal last-axis solve takes full waves of 64 lines
-    const int cw = (a == P->D && P->tri) ? kCW : choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]);
-    E.cw_axis[a] = cw;
-    E.grid_axis[a] = (unsigned)tiles_for(P->lines[a], cw);
-    E.smem_axis[a] = pass_smem(P->g.N[a], P->scalar_bytes, cw);
-    E.waves_axis[a] = P->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], E.grid_axis[a], cw)
-                                               : pass_waves<float>(P->g.N[a], E.grid_axis[a], cw);
+    const AxisGeom ag = P->precision == DOT_FP64 ? axis_geom<double>(&P, 1, a, P->sched)
+                                                 : axis_geom<float>(&P, 1, a, P->sched);
+    E.cw_axis[a] = ag.cw;
+    E.grid_axis[a] = (unsigned)ag.tiles;
+    E.smem_axis[a] = ag.smem;
+    E.waves_axis[a] = ag.waves;
   }
   E.prof = &P->prof;
   E.device = P->device;
@@ -923,6 +1007,7 @@ struct dot_batch {
   size_t ws_bytes = 0;
   void* d_inst = nullptr;
   uint16_t* d_maps = nullptr;  // node map, then one map per axis
+  Sched sched;                 // transform schedule of the batch launches
   Exec E;
   Ctl* host_ctl = nullptr;     // pinned, one entry per instance at ctl_stride
   int it = 0;                  // iterations done (all instances in lockstep)
@@ -931,6 +1016,41 @@ struct dot_batch {
 };
 
 namespace {
+
+// Block maps (block -> instance; the node grid first, then one per axis) and
+// the per-axis launch geometry of a batch under its schedule; replaces the
+// maps of an earlier layout.
+int batch_layout(dot_batch* B) {
+  const int count = (int)B->plans.size();
+  dot_plan* const* plans = B->plans.data();
+  Exec& E = B->E;
+  std::vector<uint16_t> maps;
+  for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)plans[i]->nblocks, (uint16_t)i);
+  E.grid_nodes = (unsigned)maps.size();
+  E.ntri = 0;
+  for (int i = 0; i < count; ++i) E.ntri += plans[i]->tri ? 1 : 0;
+  size_t map_off[kMaxAxes] = {0, 0, 0, 0};
+  for (int a = 0; a <= B->D; ++a) {
+    map_off[a] = maps.size();
+    const AxisGeom ag = B->precision == DOT_FP64 ? axis_geom<double>(plans, count, a, B->sched)
+                                                 : axis_geom<float>(plans, count, a, B->sched);
+    for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)tiles_for(plans[i]->lines[a], ag.cw), (uint16_t)i);
+    E.cw_axis[a] = ag.cw;
+    E.grid_axis[a] = (unsigned)ag.tiles;
+    E.smem_axis[a] = ag.smem;
+    E.waves_axis[a] = ag.waves;
+  }
+  if (B->d_maps) {
+    HIP_OK(hipDeviceSynchronize());  // no launch of the old layout is still reading its maps
+    HIP_OK(hipFree(B->d_maps));
+    B->d_maps = nullptr;
+  }
+  HIP_OK(hipMalloc((void**)&B->d_maps, maps.size() * sizeof(uint16_t)));
+  HIP_OK(hipMemcpy(B->d_maps, maps.data(), maps.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  E.map_nodes = B->d_maps;
+  for (int a = 0; a <= B->D; ++a) E.map_axis[a] = B->d_maps + map_off[a];
+  return DOT_OK;
+}
 
 template <typename T>
 int batch_descriptors(dot_batch* B, void* ws, hipStream_t st) {
@@ -962,6 +1082,217 @@ struct BatchRunF {
     return run_iters<T, D>(B->E, B->it, max_iters, ws, B->ctl_stride, B->host_ctl, st, done);
   }
 };
+
+// ---- transform schedule autotuning ----------------------------------------
+
+// Whether every instance of a launch can run the passes over axis a with
+// tiles of cw lines and `waves` waves per workgroup.
+template <typename T>
+bool schedule_ok(dot_plan* const* plans, int count, int a, int cw, int waves, int max_smem) {
+  bool all_tri = true;
+  for (int i = 0; i < count; ++i) all_tri = all_tri && plans[i]->tri;
+  if (waves < 1 || waves > kMaxWaves) return false;
+  if (a == plans[0]->D && all_tri) return cw == kCW;
+  if (cw != kCWNarrow && cw != kCWMid && cw != kCW) return false;
+  for (int i = 0; i < count; ++i) {
+    const int L = plans[i]->g.N[a];
+    if (!axis_fits<T>(L, cw, max_smem)) return false;
+    if (waves * wave_items<T>(cw) < pass_items(L, cw)) return false;
+  }
+  return true;
+}
+
+// A caller's schedule (zeros: the rule's) checked against the instances.
+template <typename T>
+int schedule_from(dot_plan* const* plans, int count, const dot_schedule* in, Sched* out) {
+  Sched s;
+  if (in) {
+    int max_smem = 0;
+    HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, plans[0]->device));
+    for (int a = 0; a <= plans[0]->D; ++a) {
+      if (!in->cw[a] && !in->waves[a]) continue;
+      Sched t;
+      t.cw[a] = in->cw[a];
+      const AxisGeom ag = axis_geom<T>(plans, count, a, t);
+      const int cw = ag.cw, w = in->waves[a] ? in->waves[a] : ag.waves;
+      if (!schedule_ok<T>(plans, count, a, cw, w, max_smem))
+        return fail(DOT_EINVAL, "axis " + std::to_string(a) + ": no launch of " + std::to_string(cw) +
+                                    "-line tiles with " + std::to_string(w) + " waves for these instances");
+      s.cw[a] = cw;
+      s.waves[a] = w;
+    }
+  }
+  *out = s;
+  return DOT_OK;
+}
+
+// One transform sequence of an executor (every pass of one phi-step, as an
+// iteration launches them), timed with HIP events on its stream: one warm-up
+// sequence, then the fastest of three runs of about 2 ms each.
+template <typename T, int D>
+int time_passes(const Exec& E, hipStream_t st, hipEvent_t e0, hipEvent_t e1, double* us) {
+  auto seq = [&]() -> int {
+    if constexpr (std::is_same<T, double>::value)
+      return run_passes<double, D, kSrcPlane, kDstPlane>(E, 0, 0.0, st);
+    else
+      return run_passes<T, D, kSrcPlane, kDstPhiAdd>(E, 0, 0.0, st);
+  };
+  int rc = seq();
+  if (rc) return rc;
+  float ms = 0.f;
+  HIP_OK(hipEventRecord(e0, st));
+  if ((rc = seq())) return rc;
+  HIP_OK(hipEventRecord(e1, st));
+  HIP_OK(hipEventSynchronize(e1));
+  HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+  const int reps = std::max(3, std::min(64, (int)(2.0 / std::max(1e-3, (double)ms))));
+  double best = 1e300;
+  for (int trial = 0; trial < 3; ++trial) {
+    HIP_OK(hipEventRecord(e0, st));
+    for (int r = 0; r < reps && !rc; ++r) rc = seq();
+    HIP_OK(hipEventRecord(e1, st));
+    HIP_OK(hipEventSynchronize(e1));
+    if (rc) return rc;
+    HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    best = std::min(best, 1000.0 * ms / reps);
+  }
+  *us = best;
+  return DOT_OK;
+}
+
+struct EventPair {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~EventPair() {
+    for (auto x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
+// Coordinate descent over the axes: on each axis in turn every candidate is
+// timed with the other axes at their best so far; the result is compared
+// once more with the rule's schedule, alternating, and the rule is kept
+// unless the measured schedule is faster. apply(s, &E) installs s on the
+// executor under test and returns its geometry.
+template <typename T, int D, typename Apply>
+int tune_schedule(Apply&& apply, const std::vector<std::vector<std::pair<int, int>>>& cands, hipStream_t st,
+                  Sched* out) {
+  EventPair ev;
+  HIP_OK(hipEventCreate(&ev.e[0]));
+  HIP_OK(hipEventCreate(&ev.e[1]));
+  Exec E;
+  const Sched rule;
+  int rc = apply(rule, &E);
+  double t_best = 0.0;
+  if (rc || (rc = time_passes<T, D>(E, st, ev.e[0], ev.e[1], &t_best))) return rc;
+  Sched rule_x;  // the rule's schedule written out
+  for (int a = 0; a <= D; ++a) {
+    rule_x.cw[a] = E.cw_axis[a];
+    rule_x.waves[a] = E.waves_axis[a];
+  }
+  Sched best = rule_x;
+  int n = 1;
+  for (int a = 0; a <= D; ++a) {
+    for (const auto& c : cands[a]) {
+      if (c.first == best.cw[a] && c.second == best.waves[a]) continue;
+      Sched s = best;
+      s.cw[a] = c.first;
+      s.waves[a] = c.second;
+      double t = 0.0;
+      if ((rc = apply(s, &E)) || (rc = time_passes<T, D>(E, st, ev.e[0], ev.e[1], &t))) return rc;
+      ++n;
+      if (t < t_best) {
+        t_best = t;
+        best = s;
+      }
+    }
+  }
+  double t_rule = 1e300, t_tuned = 1e300;
+  for (int k = 0; k < 2; ++k) {
+    double t = 0.0;
+    if ((rc = apply(rule_x, &E)) || (rc = time_passes<T, D>(E, st, ev.e[0], ev.e[1], &t))) return rc;
+    t_rule = std::min(t_rule, t);
+    if ((rc = apply(best, &E)) || (rc = time_passes<T, D>(E, st, ev.e[0], ev.e[1], &t))) return rc;
+    t_tuned = std::min(t_tuned, t);
+  }
+  if (!(t_tuned < t_rule)) {
+    best = rule_x;
+    t_tuned = t_rule;
+  }
+  best.tuned = true;
+  best.candidates = n;
+  best.us = t_tuned;
+  best.us_rule = t_rule;
+  if ((rc = apply(best, &E))) return rc;
+  *out = best;
+  return DOT_OK;
+}
+
+template <typename T>
+std::vector<std::vector<std::pair<int, int>>> all_candidates(dot_plan* const* plans, int count) {
+  int max_smem = 0;
+  (void)hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, plans[0]->device);
+  std::vector<std::vector<std::pair<int, int>>> c;
+  for (int a = 0; a <= plans[0]->D; ++a) c.push_back(axis_candidates<T>(plans, count, a, max_smem));
+  return c;
+}
+
+void drop_graph(GraphCache& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+}
+
+template <typename T, int D>
+struct PlanTuneF {
+  static int run(dot_plan* P, void* state, hipStream_t st) {
+    Ctl* ctl = at<Ctl>(state, P->ctl_offset);
+    int rc = upload_inst(plan_exec(P, 0), state_inst<T>(P, state, ctl), st);
+    if (rc) return rc;
+    auto apply = [&](const Sched& s, Exec* E) -> int {
+      P->sched = s;
+      *E = plan_exec(P, 0);
+      E->prof = nullptr;
+      E->graphs = nullptr;
+      return DOT_OK;
+    };
+    Sched out;
+    rc = tune_schedule<T, D>(apply, all_candidates<T>(&P, 1), st, &out);
+    if (rc) return rc;
+    P->sched = out;
+    return DOT_OK;
+  }
+};
+
+template <typename T, int D>
+struct BatchTuneF {
+  static int run(dot_batch* B, void* ws, hipStream_t st) {
+    auto apply = [&](const Sched& s, Exec* E) -> int {
+      B->sched = s;
+      int rc = batch_layout(B);
+      if (rc || (rc = batch_descriptors<T>(B, ws, st))) return rc;
+      *E = B->E;
+      E->prof = nullptr;
+      E->graphs = nullptr;
+      return DOT_OK;
+    };
+    Sched out;
+    int rc = tune_schedule<T, D>(apply, all_candidates<T>(B->plans.data(), (int)B->plans.size()), st, &out);
+    if (rc) return rc;
+    B->sched = out;
+    return DOT_OK;
+  }
+};
+
+void schedule_out(const Sched& s, const Exec& E, int D, dot_schedule* o) {
+  std::memset(o, 0, sizeof(*o));
+  for (int a = 0; a <= D; ++a) {
+    o->cw[a] = E.cw_axis[a];
+    o->waves[a] = E.waves_axis[a];
+  }
+  o->tuned = s.tuned ? 1 : 0;
+  o->candidates = s.candidates;
+  o->us = s.us;
+  o->us_rule = s.us_rule;
+}
 
 }  // namespace
 
@@ -1039,7 +1370,6 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
     P->wide_ok[a] = fits(kCW);
     P->mid_ok[a] = fits(kCWMid) && pass_smem(g.N[a], P->scalar_bytes, kCWMid) <= kMidLds;
     P->lines[a] = g.nb / g.N[a];
-    P->tiles[a] = tiles_for(P->lines[a], choose_cw(P->lines[a], P->wide_ok[a], P->mid_ok[a]));
   }
   P->tri = g.N[D] >= kTriMinNodes;
   // problem data
@@ -1257,49 +1587,14 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
     off += align256(P->state_bytes);
   }
   B->ws_bytes = off;
-  // block maps (block -> instance): node grid first, then one per axis
-  std::vector<uint16_t> maps;
   Exec& E = B->E;
   E.D = D;
   E.precision = B->precision;
   E.ninst = count;
   E.cadence = B->cadence;
   E.device = B->plans[0]->device;
-  for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)B->plans[i]->nblocks, (uint16_t)i);
-  E.grid_nodes = (unsigned)maps.size();
-  for (auto* P : B->plans) E.ntri += P->tri ? 1 : 0;
-  size_t map_off[kMaxAxes] = {0, 0, 0, 0};
-  for (int a = 0; a <= D; ++a) {
-    map_off[a] = maps.size();
-    size_t smem = 0;
-    int waves = 1;
-    int64_t all_lines = 0;
-    bool wide_ok = true, mid_ok = true, all_tri = true;
-    for (int i = 0; i < count; ++i) {
-      all_lines += B->plans[i]->lines[a];
-      wide_ok = wide_ok && B->plans[i]->wide_ok[a];
-      mid_ok = mid_ok && B->plans[i]->mid_ok[a];
-      all_tri = all_tri && B->plans[i]->tri;
-    }
-    const int cw = (a == D && all_tri) ? kCW : choose_cw(all_lines, wide_ok, mid_ok);
-    E.cw_axis[a] = cw;
-    int64_t all_tiles = 0;
-    for (int i = 0; i < count; ++i) all_tiles += tiles_for(B->plans[i]->lines[a], cw);
-    for (int i = 0; i < count; ++i) {
-      dot_plan* P = B->plans[i];
-      maps.insert(maps.end(), (size_t)tiles_for(P->lines[a], cw), (uint16_t)i);
-      smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes, cw));
-      waves = std::max(waves, B->precision == DOT_FP64 ? pass_waves<double>(P->g.N[a], all_tiles, cw)
-                                                       : pass_waves<float>(P->g.N[a], all_tiles, cw));
-    }
-    E.grid_axis[a] = (unsigned)(maps.size() - map_off[a]);
-    E.smem_axis[a] = smem;
-    E.waves_axis[a] = waves;
-  }
-  HIP_OK(hipMalloc((void**)&B->d_maps, maps.size() * sizeof(uint16_t)));
-  HIP_OK(hipMemcpy(B->d_maps, maps.data(), maps.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
-  E.map_nodes = B->d_maps;
-  for (int a = 0; a <= D; ++a) E.map_axis[a] = B->d_maps + map_off[a];
+  int rc = batch_layout(B.get());
+  if (rc) return rc;
   const size_t isz = B->precision == DOT_FP64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
   HIP_OK(hipMalloc(&B->d_inst, isz * count));
   E.d_inst = B->d_inst;
@@ -1352,6 +1647,76 @@ int dot_batch_extract(dot_batch* B, const void* ws, int32_t index, double* rho_o
 int dot_batch_set_graphs(dot_batch* B, int32_t enable) {
   if (!B) return fail(DOT_EINVAL, "null batch");
   B->graphs.enabled = enable != 0;
+  return DOT_OK;
+}
+
+int dot_plan_set_schedule(dot_plan* P, const dot_schedule* s) {
+  if (!P) return fail(DOT_EINVAL, "null plan");
+  Sched x;
+  int rc = P->precision == DOT_FP64 ? schedule_from<double>(&P, 1, s, &x) : schedule_from<float>(&P, 1, s, &x);
+  if (rc) return rc;
+  P->sched = x;
+  drop_graph(P->graphs);
+  return DOT_OK;
+}
+
+int dot_plan_get_schedule(const dot_plan* P, dot_schedule* out) {
+  if (!P || !out) return fail(DOT_EINVAL, "null argument");
+  schedule_out(P->sched, plan_exec(const_cast<dot_plan*>(P), 0), P->D, out);
+  return DOT_OK;
+}
+
+int dot_plan_autotune(dot_plan* P, void* state, void* stream, dot_schedule* out) {
+  if (!P || !state) return fail(DOT_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = dot_state_reset(P, state, stream);
+  if (rc) return rc;
+  drop_graph(P->graphs);
+  const Sched keep = P->sched;
+  rc = dispatch<PlanTuneF>(P->precision, P->D, P, state, st);
+  if (rc) {
+    P->sched = keep;
+    return rc;
+  }
+  if ((rc = dot_state_reset(P, state, stream))) return rc;
+  if (out) return dot_plan_get_schedule(P, out);
+  return DOT_OK;
+}
+
+int dot_batch_set_schedule(dot_batch* B, const dot_schedule* s) {
+  if (!B) return fail(DOT_EINVAL, "null batch");
+  dot_plan* const* plans = B->plans.data();
+  const int count = (int)B->plans.size();
+  Sched x;
+  int rc = B->precision == DOT_FP64 ? schedule_from<double>(plans, count, s, &x)
+                                    : schedule_from<float>(plans, count, s, &x);
+  if (rc) return rc;
+  B->sched = x;
+  drop_graph(B->graphs);
+  return batch_layout(B);
+}
+
+int dot_batch_get_schedule(const dot_batch* B, dot_schedule* out) {
+  if (!B || !out) return fail(DOT_EINVAL, "null argument");
+  schedule_out(B->sched, B->E, B->D, out);
+  return DOT_OK;
+}
+
+int dot_batch_autotune(dot_batch* B, void* ws, void* stream, dot_schedule* out) {
+  if (!B || !ws) return fail(DOT_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = dot_batch_reset(B, ws, stream);
+  if (rc) return rc;
+  drop_graph(B->graphs);
+  const Sched keep = B->sched;
+  rc = dispatch<BatchTuneF>(B->precision, B->D, B, ws, st);
+  if (rc) {
+    B->sched = keep;
+    (void)batch_layout(B);
+    return rc;
+  }
+  if ((rc = dot_batch_reset(B, ws, stream))) return rc;
+  if (out) return dot_batch_get_schedule(B, out);
   return DOT_OK;
 }
 

@@ -7,7 +7,9 @@ counter collection:
 Workloads: 1d-16x32, 2d-32x64x64, 2d-64x256x256, 3d-32x64x64x64, 2d-32x1024x1024 (add
 --mixed for the mixed-precision mode). --copy-mib M first runs one plain
 device-to-device copy of M MiB (torch), the calibration of the HBM byte
-counters."""
+counters. --cw / --waves install an explicit transform schedule (comma lists
+over the axes, 0 keeps the rule's; e.g. one the autotuner chose in another
+run), so that no tuning launches enter the trace."""
 import argparse
 import os
 import sys
@@ -34,6 +36,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=0)
     ap.add_argument("--iters", type=int, action="append")
     ap.add_argument("--mixed", action="store_true")
+    ap.add_argument("--cw", type=str, default="")
+    ap.add_argument("--waves", type=str, default="")
     a = ap.parse_args()
     import torch
     st = torch.cuda.current_stream().cuda_stream
@@ -50,6 +54,12 @@ def main():
         inst = WORKLOADS[name]()
         plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=-1.0, max_iter=its,
                                  precision=B.DOT_MIXED if a.mixed else B.DOT_FP64)
+        if a.cw or a.waves:
+            cw = [int(v) for v in a.cw.split(",")] if a.cw else None
+            waves = [int(v) for v in a.waves.split(",")] if a.waves else None
+            B.dot_plan_set_schedule(plan, cw=cw, waves=waves)
+        sched = B.dot_plan_get_schedule(plan)
+        print(f"{name} schedule cw={sched['cw']} waves={sched['waves']}", flush=True)
         s = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
         B.dot_state_reset(plan, s.data_ptr(), st)
         r = B.dot_run(plan, s.data_ptr(), its, st)
