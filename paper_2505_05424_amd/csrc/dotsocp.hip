@@ -82,7 +82,9 @@ struct ProfScope {
     if (pr->used + 2 > pr->ev.size()) {
       for (int k = 0; k < 64; ++k) {
         hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) {
+        // timing-only events: no system-scope fence (cache writeback and
+        // invalidate) when they complete, which would add to each bracket
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
           on = false;
           return;
         }
