@@ -1020,37 +1020,47 @@ struct dot_batch {
 namespace {
 
 // Block maps (block -> instance; the node grid first, then one per axis) and
-// the per-axis launch geometry of a batch under its schedule; replaces the
-// maps of an earlier layout.
-int batch_layout(dot_batch* B) {
+// the per-axis launch geometry of a batch under schedule s. The new maps are
+// uploaded before anything of the old layout changes, so on failure the batch
+// keeps its previous layout and schedule; on success s becomes B->sched.
+int batch_layout(dot_batch* B, const Sched& s) {
   const int count = (int)B->plans.size();
   dot_plan* const* plans = B->plans.data();
-  Exec& E = B->E;
   std::vector<uint16_t> maps;
   for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)plans[i]->nblocks, (uint16_t)i);
-  E.grid_nodes = (unsigned)maps.size();
-  E.ntri = 0;
-  for (int i = 0; i < count; ++i) E.ntri += plans[i]->tri ? 1 : 0;
   size_t map_off[kMaxAxes] = {0, 0, 0, 0};
+  AxisGeom ag[kMaxAxes];
   for (int a = 0; a <= B->D; ++a) {
     map_off[a] = maps.size();
-    const AxisGeom ag = B->precision == DOT_FP64 ? axis_geom<double>(plans, count, a, B->sched)
-                                                 : axis_geom<float>(plans, count, a, B->sched);
-    for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)tiles_for(plans[i]->lines[a], ag.cw), (uint16_t)i);
-    E.cw_axis[a] = ag.cw;
-    E.grid_axis[a] = (unsigned)ag.tiles;
-    E.smem_axis[a] = ag.smem;
-    E.waves_axis[a] = ag.waves;
+    ag[a] = B->precision == DOT_FP64 ? axis_geom<double>(plans, count, a, s) : axis_geom<float>(plans, count, a, s);
+    for (int i = 0; i < count; ++i)
+      maps.insert(maps.end(), (size_t)tiles_for(plans[i]->lines[a], ag[a].cw), (uint16_t)i);
+  }
+  uint16_t* fresh = nullptr;
+  HIP_OK(hipMalloc((void**)&fresh, maps.size() * sizeof(uint16_t)));
+  const hipError_t e = hipMemcpy(fresh, maps.data(), maps.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(fresh);
+    return fail(DOT_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
   }
   if (B->d_maps) {
     HIP_OK(hipDeviceSynchronize());  // no launch of the old layout is still reading its maps
-    HIP_OK(hipFree(B->d_maps));
-    B->d_maps = nullptr;
+    (void)hipFree(B->d_maps);
   }
-  HIP_OK(hipMalloc((void**)&B->d_maps, maps.size() * sizeof(uint16_t)));
-  HIP_OK(hipMemcpy(B->d_maps, maps.data(), maps.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  B->d_maps = fresh;
+  B->sched = s;
+  Exec& E = B->E;
+  E.grid_nodes = (unsigned)map_off[0];
+  E.ntri = 0;
+  for (int i = 0; i < count; ++i) E.ntri += plans[i]->tri ? 1 : 0;
   E.map_nodes = B->d_maps;
-  for (int a = 0; a <= B->D; ++a) E.map_axis[a] = B->d_maps + map_off[a];
+  for (int a = 0; a <= B->D; ++a) {
+    E.map_axis[a] = B->d_maps + map_off[a];
+    E.cw_axis[a] = ag[a].cw;
+    E.grid_axis[a] = (unsigned)ag[a].tiles;
+    E.smem_axis[a] = ag[a].smem;
+    E.waves_axis[a] = ag[a].waves;
+  }
   return DOT_OK;
 }
 
@@ -1268,8 +1278,7 @@ template <typename T, int D>
 struct BatchTuneF {
   static int run(dot_batch* B, void* ws, hipStream_t st) {
     auto apply = [&](const Sched& s, Exec* E) -> int {
-      B->sched = s;
-      int rc = batch_layout(B);
+      int rc = batch_layout(B, s);
       if (rc || (rc = batch_descriptors<T>(B, ws, st))) return rc;
       *E = B->E;
       E->prof = nullptr;
@@ -1279,7 +1288,7 @@ struct BatchTuneF {
     Sched out;
     int rc = tune_schedule<T, D>(apply, all_candidates<T>(B->plans.data(), (int)B->plans.size()), st, &out);
     if (rc) return rc;
-    B->sched = out;
+    B->sched = out;  // the layout of `out` is in place (tune_schedule applies it last)
     return DOT_OK;
   }
 };
@@ -1595,7 +1604,7 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
   E.ninst = count;
   E.cadence = B->cadence;
   E.device = B->plans[0]->device;
-  int rc = batch_layout(B.get());
+  int rc = batch_layout(B.get(), Sched());
   if (rc) return rc;
   const size_t isz = B->precision == DOT_FP64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
   HIP_OK(hipMalloc(&B->d_inst, isz * count));
@@ -1693,9 +1702,8 @@ int dot_batch_set_schedule(dot_batch* B, const dot_schedule* s) {
   int rc = B->precision == DOT_FP64 ? schedule_from<double>(plans, count, s, &x)
                                     : schedule_from<float>(plans, count, s, &x);
   if (rc) return rc;
-  B->sched = x;
   drop_graph(B->graphs);
-  return batch_layout(B);
+  return batch_layout(B, x);
 }
 
 int dot_batch_get_schedule(const dot_batch* B, dot_schedule* out) {
@@ -1713,8 +1721,7 @@ int dot_batch_autotune(dot_batch* B, void* ws, void* stream, dot_schedule* out) 
   const Sched keep = B->sched;
   rc = dispatch<BatchTuneF>(B->precision, B->D, B, ws, st);
   if (rc) {
-    B->sched = keep;
-    (void)batch_layout(B);
+    (void)batch_layout(B, keep);  // back to the schedule in use before the call
     return rc;
   }
   if ((rc = dot_batch_reset(B, ws, stream))) return rc;

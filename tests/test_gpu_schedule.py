@@ -147,3 +147,37 @@ def test_batch_autotune_members_equal_their_solves_alone(prec):
     res2 = B.dot_batch_run(batch, ws.data_ptr(), ITERS, st)
     for a, b in zip(res, res2):
         assert a.objective == b.objective and a.eta_dot == b.eta_dot
+
+
+@pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
+@pytest.mark.parametrize("D,n", [(1, (16, 32)), (3, (8, 12, 16, 20))], ids=["1d-16x32", "3d-8x12x16x20"])
+def test_autotune_1d_3d_plans_keep_the_results(D, n, prec):
+    inst = dotgen.tiny_instance(D, n, seed=64, floor=0.0)
+    print(f"[case] autotune {D}d {n} precision={prec}", flush=True)
+    ref = _run(_plan(inst, prec))
+    plan = _plan(inst, prec)
+    s = G.GpuState(plan)
+    sched = B.dot_plan_autotune(plan, s.ptr, G.stream_handle())
+    assert sched["tuned"] and len(sched["cw"]) == D + 1
+    r = s.run(ITERS)
+    rho, m = s.extract()
+    _same((r, rho, m), ref)
+
+
+@pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
+def test_autotuned_3d_batch_members_equal_their_solves_alone(prec):
+    insts = [dotgen.tiny_instance(3, (4, 6, 8, 10), seed=71, floor=0.0),
+             dotgen.tiny_instance(3, (8, 12, 10, 14), seed=72, floor=0.02),
+             dotgen.tiny_instance(3, (6, 16, 8, 9), seed=73, floor=0.0)]
+    print(f"[case] 3d batch autotune precision={prec}", flush=True)
+    batch = B.dot_batch_create(insts, tol=-1.0, max_iter=100000, precision=prec)
+    torch = G.torch_mod()
+    ws = torch.zeros(int(batch.workspace_bytes), dtype=torch.uint8, device="cuda")
+    st = G.stream_handle()
+    sched = B.dot_batch_autotune(batch, ws.data_ptr(), st)
+    assert sched["tuned"] and len(sched["cw"]) == 4
+    res = B.dot_batch_run(batch, ws.data_ptr(), ITERS, st)
+    for i, inst in enumerate(insts):
+        r, rho, m = _run(_plan(inst, prec))
+        rb, mb = B.dot_batch_extract(batch, ws.data_ptr(), i, st)
+        _same((res[i], rb, mb), (r, rho, m))
