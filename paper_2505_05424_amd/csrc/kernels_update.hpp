@@ -550,7 +550,6 @@ __device__ __forceinline__ void resid_body(const Geo& g, const double* phi_, con
                                            const T* beta_, const double* om_sp, const double* sw_sp,
                                            const double* c_lo_, const double* c_hi_, double* __restrict__ partials,
                                            uint32_t blk) {
-  constexpr int K = 4 * D + 2;
   double s[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) s[k] = 0.0;
