@@ -252,7 +252,11 @@ typedef struct {
 
 /* Install a schedule (NULL: the rule's) for later runs; DOT_EINVAL when an
  * axis's tile does not fit the LDS of some instance or the waves cannot hold
- * its work items. Captured graphs are dropped and re-captured on the next run. */
+ * its work items (the schedule in use is then kept). Captured graphs are
+ * dropped and re-captured on the next run. The batch call waits until the
+ * device is idle before it releases the previous block maps. None of the
+ * schedule calls may overlap a run of the same plan or batch, or be made
+ * inside a graph capture. */
 int dot_plan_set_schedule(dot_plan* plan, const dot_schedule* schedule);
 int dot_batch_set_schedule(dot_batch* batch, const dot_schedule* schedule);
 /* The schedule in use (the rule's values written out when none is set). */
