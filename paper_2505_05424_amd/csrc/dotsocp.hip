@@ -326,6 +326,7 @@ AxisGeom axis_geom(dot_plan* const* plans, int count, int a, const Sched& s) {
   for (int i = 0; i < count; ++i) ag.tiles += tiles_for(plans[i]->lines[a], ag.cw);
   int waves = 1;
   for (int i = 0; i < count; ++i) {
+    if (a == plans[i]->D && plans[i]->tri) continue;  // takes the tridiagonal solve on this axis
     ag.smem = std::max(ag.smem, pass_smem(plans[i]->g.N[a], (int)sizeof(T), ag.cw));
     waves = std::max(waves, pass_waves<T>(plans[i]->g.N[a], ag.tiles, ag.cw));
   }
@@ -344,19 +345,25 @@ std::vector<std::pair<int, int>> axis_candidates(dot_plan* const* plans, int cou
   bool all_tri = true, wide_ok = true, mid_fits = true;
   for (int i = 0; i < count; ++i) {
     all_tri = all_tri && plans[i]->tri;
+    if (a == plans[i]->D && plans[i]->tri) continue;  // no transform pass for this one
     wide_ok = wide_ok && plans[i]->wide_ok[a];
     mid_fits = mid_fits && axis_fits<T>(plans[i]->g.N[a], kCWMid, max_smem);
   }
   if (a == plans[0]->D && all_tri) {
-    Sched s;
-    s.cw[a] = kCW;
-    out.push_back({kCW, axis_geom<T>(plans, count, a, s).waves});
+    // only the tridiagonal solve runs on this axis: 256 threads whatever the
+    // waves; the width sets the lines per workgroup (and its LDS)
+    for (int cw : {kCWNarrow, kCWMid, kCW}) {
+      Sched s;
+      s.cw[a] = cw;
+      out.push_back({cw, axis_geom<T>(plans, count, a, s).waves});
+    }
     return out;
   }
   for (int cw : {kCWNarrow, kCWMid, kCW}) {
     if ((cw == kCW && !wide_ok) || (cw == kCWMid && !mid_fits)) continue;
     int lo = 1, items = 1;
     for (int i = 0; i < count; ++i) {
+      if (a == plans[i]->D && plans[i]->tri) continue;
       const int it = pass_items(plans[i]->g.N[a], cw);
       items = std::max(items, it);
       lo = std::max(lo, (it + wave_items<T>(cw) - 1) / wave_items<T>(cw));
@@ -1104,9 +1111,10 @@ bool schedule_ok(dot_plan* const* plans, int count, int a, int cw, int waves, in
   bool all_tri = true;
   for (int i = 0; i < count; ++i) all_tri = all_tri && plans[i]->tri;
   if (waves < 1 || waves > kMaxWaves) return false;
-  if (a == plans[0]->D && all_tri) return cw == kCW;
+  if (a == plans[0]->D && all_tri) return cw == kCW || cw == kCWMid || cw == kCWNarrow;
   if (cw != kCWNarrow && cw != kCWMid && cw != kCW) return false;
   for (int i = 0; i < count; ++i) {
+    if (a == plans[i]->D && plans[i]->tri) continue;  // only the tridiagonal solve runs there
     const int L = plans[i]->g.N[a];
     if (!axis_fits<T>(L, cw, max_smem)) return false;
     if (waves * wave_items<T>(cw) < pass_items(L, cw)) return false;
@@ -1371,7 +1379,12 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   // LDS capacity of one transform tile
   int max_smem = 0;
   HIP_OK(hipDeviceGetAttribute(&max_smem, hipDeviceAttributeMaxSharedMemoryPerBlock, P->device));
+  P->tri = g.N[D] >= kTriMinNodes;
   for (int a = 0; a <= D; ++a) {
+    P->lines[a] = g.nb / g.N[a];
+    // a last axis solved by tridiagonal elimination is never transformed,
+    // whatever its length: no tile limits apply to it
+    if (a == D && P->tri) continue;
     auto fits = [&](int cw) {
       return P->precision == DOT_FP64 ? axis_fits<double>(g.N[a], cw, max_smem)
                                       : axis_fits<float>(g.N[a], cw, max_smem);
@@ -1380,9 +1393,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
       return fail(DOT_EINVAL, "axis of " + std::to_string(g.N[a]) + " nodes exceeds the transform tile capacity");
     P->wide_ok[a] = fits(kCW);
     P->mid_ok[a] = fits(kCWMid) && pass_smem(g.N[a], P->scalar_bytes, kCWMid) <= kMidLds;
-    P->lines[a] = g.nb / g.N[a];
   }
-  P->tri = g.N[D] >= kTriMinNodes;
   // problem data
   const int64_t nx = g.nx;
   double vol = 1.0;
@@ -1403,6 +1414,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
       (rc = upload(&P->sw_sp, sw)))
     return rc;
   for (int a = 0; a <= D; ++a) {
+    if (a == D && P->tri) continue;  // no transform tables for an eliminated axis
     rc = P->precision == DOT_FP64 ? build_axis<double>(P.get(), a, &P->axis_buf[a], &P->tab64[a])
                                   : build_axis<float>(P.get(), a, &P->axis_buf[a], &P->tab32[a]);
     if (rc) return rc;
@@ -2130,6 +2142,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
       dot_plan* P = r->plan;
       maps.insert(maps.end(), (size_t)tiles_for(P->lines[a], cw), (uint16_t)k);
       ++k;
+      if (a == C->D && P->tri) continue;  // takes the tridiagonal solve on this axis
       smem = std::max(smem, pass_smem(P->g.N[a], P->scalar_bytes, cw));
       waves = std::max(waves, pass_waves<T>(P->g.N[a], all_tiles, cw));
     }

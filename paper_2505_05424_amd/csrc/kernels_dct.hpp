@@ -425,15 +425,14 @@ __device__ __forceinline__ void axis_pass_body(const Geo& g, const PassArgs& pa,
 // chunks of kTriChunk points: the next chunk is loaded coalesced (all
 // threads) while the current one is eliminated, one thread per line running
 // the recurrence on its chunk in registers; chunks pass through LDS. The
-// forward sweep stores d' in place and c' in `cpl`; the backward sweep
-// stores x.
+// forward sweep stores d' in place and one c' checkpoint per chunk in `cpl`;
+// the backward sweep recomputes c' from the checkpoints and stores x.
 constexpr int kTriChunk = 32;
 constexpr int kTriThreads = 256;
 
 template <typename T, int CW>
 struct TriTile {
   T a[2][CW][kTriChunk + 1];  // b, then d', then x (double buffered)
-  T c[2][CW][kTriChunk + 1];  // c'
 };
 
 // Coalesced copy of one chunk (CW lines x kTriChunk points; element e is
@@ -475,6 +474,24 @@ __device__ __forceinline__ double tri_recip(double b) {
   return r * fma(-b, r, 2.0);
 }
 
+// One step of the elimination coefficients of a line of the tridiagonal
+// system (lam + n^2 L_path) x = b: pivot reciprocal r_i of node i given
+// c'_{i-1} (0 before the first node) and the new c'_i = -n^2 r_i. The forward
+// and the backward sweep both call it, so the c' that the backward sweep
+// recomputes are those the forward sweep used, bit for bit.
+__device__ __forceinline__ double tri_cstep(double lam, double s2, int i, int L, double cp, double* r) {
+  const double diag = lam + s2 * ((i == 0 || i == L - 1) ? 1.0 : 2.0);
+  *r = tri_recip(diag + s2 * cp);
+  return -s2 * *r;
+}
+
+// Tridiagonal solve along the last axis for one tile of CW lines (one owner
+// thread per line runs the recurrences; all threads stage chunks of
+// kTriChunk points through LDS). The forward sweep overwrites b with d' and
+// keeps, per line and chunk, only the c' carried into the chunk (FP64, in
+// `cpl` reused as an array [chunk][line]); the backward sweep re-runs the c'
+// recurrence of each chunk from that checkpoint, so c' never goes through HBM
+// (per point 4 plane accesses instead of 6).
 template <typename T, int CW>
 __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plane, T* __restrict__ cpl,
                                               const T* __restrict__ lam_other, int64_t blk) {
@@ -486,7 +503,9 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
   const int nl = (int)((ncols - c0) < CW ? (ncols - c0) : CW);  // lines of this tile
   __shared__ TriTile<T, CW> tt;
   gp<T> pl = glob(plane);
-  gp<T> cq = glob(cpl);
+  // checkpoints: nch * ncols doubles, within the plane's nb * sizeof(T) bytes
+  // for every L >= 2 (nch = ceil(L / 32) <= L / 2)
+  gp<double> ck = glob(reinterpret_cast<double*>(cpl));
   const uint32_t base = (uint32_t)c0 * (uint32_t)L;
   const int me = threadIdx.x;
   const bool owner = me < nl;
@@ -494,8 +513,9 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
   const bool zero = lam == 0.0;
   const int nch = (L + kTriChunk - 1) / kTriChunk;
   auto len = [&](int k) { return L - k * kTriChunk < kTriChunk ? L - k * kTriChunk : kTriChunk; };
+  auto ck_at = [&](int k) { return (size_t)k * (size_t)ncols + (size_t)(c0 + me); };
   double cp = 0.0, dp = 0.0, sum = 0.0;
-  TriChunk<T, CW> nx, nc;
+  TriChunk<T, CW> nx;
   // forward sweep
   nx.load(pl, base, L, nl, 0, len(0));
   nx.put(tt.a[0]);
@@ -505,12 +525,12 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
     const int b = k & 1;
     if (k + 1 < nch) nx.load(pl, base, L, nl, i0 + kTriChunk, len(k + 1));
     if (owner) {
-      T rv[kTriChunk], cv[kTriChunk];
+      if (!zero) ck[ck_at(k)] = cp;
+      T rv[kTriChunk];
 #pragma unroll
       for (int j = 0; j < kTriChunk; ++j) rv[j] = tt.a[b][me][j];
 #pragma unroll
       for (int j = 0; j < kTriChunk; ++j) {
-        cv[j] = T(0);
         if (j < m) {
           const int i = i0 + j;
           const double bj = (double)rv[j];
@@ -521,50 +541,51 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
             cp -= bj;
             dp += cp / s2;
           } else {
-            const double diag = lam + s2 * ((i == 0 || i == L - 1) ? 1.0 : 2.0);
-            const double r = tri_recip(diag + s2 * cp);
-            cp = -s2 * r;
+            double r;
+            cp = tri_cstep(lam, s2, i, L, cp, &r);
             dp = (bj + s2 * dp) * r;
             rv[j] = (T)dp;
-            cv[j] = (T)cp;
           }
         }
       }
 #pragma unroll
-      for (int j = 0; j < kTriChunk; ++j) {
-        tt.a[b][me][j] = rv[j];
-        tt.c[b][me][j] = cv[j];
-      }
+      for (int j = 0; j < kTriChunk; ++j) tt.a[b][me][j] = rv[j];
     }
     __syncthreads();
     tri_store<T, CW>(pl, tt.a[b], base, L, nl, i0, m);
-    tri_store<T, CW>(cq, tt.c[b], base, L, nl, i0, m);
     if (k + 1 < nch) nx.put(tt.a[b ^ 1]);
     __syncthreads();
   }
-  // backward sweep: x_{L-1} = d'_{L-1}, x_i = d'_i - c'_i x_{i+1}, minus the
-  // line mean on the zero line
+  // backward sweep: x_{L-1} = d'_{L-1}, x_i = d'_i - c'_i x_{i+1} (c' = 0 on
+  // the zero line, whose d' already is x), minus the line mean on the zero line
   const double mean = zero ? sum / (double)L : 0.0;
   double x = 0.0;
+  double cnext = (owner && !zero) ? ck[ck_at(nch - 1)] : 0.0;
   nx.load(pl, base, L, nl, (nch - 1) * kTriChunk, len(nch - 1));
-  nc.load(cq, base, L, nl, (nch - 1) * kTriChunk, len(nch - 1));
   nx.put(tt.a[0]);
-  nc.put(tt.c[0]);
   __syncthreads();
   for (int k = nch - 1, u = 0; k >= 0; --k, ++u) {
     const int i0 = k * kTriChunk, m = len(k);
     const int b = u & 1;
+    const double cstart = cnext;
     if (k > 0) {
       nx.load(pl, base, L, nl, i0 - kTriChunk, kTriChunk);
-      nc.load(cq, base, L, nl, i0 - kTriChunk, kTriChunk);
+      if (owner && !zero) cnext = ck[ck_at(k - 1)];
     }
     if (owner) {
       T dv[kTriChunk], cv[kTriChunk];
+      double c = cstart;
 #pragma unroll
       for (int j = 0; j < kTriChunk; ++j) {
-        dv[j] = tt.a[b][me][j];
-        cv[j] = tt.c[b][me][j];
+        cv[j] = T(0);
+        if (j < m && !zero) {
+          double r;
+          c = tri_cstep(lam, s2, i0 + j, L, c, &r);
+          cv[j] = (T)c;
+        }
       }
+#pragma unroll
+      for (int j = 0; j < kTriChunk; ++j) dv[j] = tt.a[b][me][j];
 #pragma unroll
       for (int j = kTriChunk - 1; j >= 0; --j) {
         if (j < m) {
@@ -577,10 +598,7 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
     }
     __syncthreads();
     tri_store<T, CW>(pl, tt.a[b], base, L, nl, i0, m);
-    if (k > 0) {
-      nx.put(tt.a[b ^ 1]);
-      nc.put(tt.c[b ^ 1]);
-    }
+    if (k > 0) nx.put(tt.a[b ^ 1]);
     __syncthreads();
   }
 }

@@ -79,15 +79,17 @@ def test_every_schedule_gives_the_rule_bits(name, D, n, prec):
 
 
 @pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
-def test_tridiagonal_last_axis_keeps_its_tile(prec):
-    inst = dotgen.tiny_instance(2, (4, 7, 300), seed=62, floor=0.0)
+@pytest.mark.parametrize("n", [(4, 7, 300), (3, 5, 1200)], ids=["last-301", "last-1201"])
+def test_tridiagonal_last_axis_widths_give_the_same_bits(n, prec):
+    # the elimination runs one line per thread: the lines per workgroup
+    # change no value (1201 nodes: longer than a transform tile holds)
+    inst = dotgen.tiny_instance(2, n, seed=62, floor=0.0)
     plan = _plan(inst, prec)
     ref = _run(plan, 20)
     assert B.dot_plan_get_schedule(plan)["cw"][2] == 64
-    with pytest.raises(B.DotError):
-        B.dot_plan_set_schedule(plan, cw=[0, 0, 16])
-    B.dot_plan_set_schedule(plan, cw=[16, 32, 64], waves=[8, 16, 0])
-    _same(_run(plan, 20), ref)
+    for cw in (16, 32):
+        B.dot_plan_set_schedule(plan, cw=[16, 32, cw], waves=[8, 16, 0])
+        _same(_run(plan, 20), ref)
 
 
 def test_invalid_schedules_are_rejected():
