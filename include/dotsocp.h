@@ -121,7 +121,9 @@ const char* dot_last_error(void);
 
 /* Validate p (mass balance, sizes, finite data), build c, omega, the cosine
  * transform tables and eigenvalues of A^*A (Sec. 4, phi-step of Algorithm 2) on the
- * current HIP device. The plan copies everything it needs from p. */
+ * current HIP device. The plan copies everything it needs from p. DOT_EINVAL
+ * if a transformed axis (every axis but a last one of >= 257 nodes) exceeds
+ * what one transform tile holds (about 1100 nodes in FP64, 2200 mixed). */
 int dot_plan_create(const dot_problem* p, dot_plan** out);
 void dot_plan_destroy(dot_plan* plan);
 int dot_plan_get_info(const dot_plan* plan, dot_plan_info* out);
@@ -153,7 +155,9 @@ int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double
  * transformed: after the other axes' transforms each of its lines is a
  * tridiagonal system (eigenvalue sum of the other axes + path-graph Laplacian
  * / h^2), solved by elimination in FP64; same linear system, same phi up to
- * rounding. */
+ * rounding (forward error within the condition number of the line systems
+ * times the FP64 unit, which grows with the square of the axis length). Such
+ * an axis has no length limit; the other axes must fit a transform tile. */
 int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
 /* a3 + a4 as the iteration runs them (right-hand side sweep, then the
  * transform passes): phi from (q, alpha, sigma). */
@@ -238,8 +242,9 @@ int dot_batch_set_graphs(dot_batch* batch, int32_t enable);
  * launch's line count. A schedule changes no computed value: every line's
  * products run in one wavefront in a fixed order, so results are bitwise
  * those of any other schedule (and a batch member still equals its solve
- * alone). The last axis of instances solved by tridiagonal elimination (>= 257
- * nodes) keeps 64-line tiles when every instance of the launch takes it. */
+ * alone). On a last axis that every instance of the launch solves by
+ * tridiagonal elimination (>= 257 nodes) cw is the number of lines (one per
+ * thread) of each 256-thread workgroup, 64 by default; waves do not apply. */
 typedef struct {
   int32_t cw[4];       /* lines per tile, axes 0..D: 16, 32 or 64 (set calls: 0 keeps the rule's) */
   int32_t waves[4];    /* wavefronts per workgroup, 1..16, enough for the axis's work items
