@@ -498,6 +498,10 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
   const int D = g.D;
   const int L = g.N[D];
   const double s2 = (double)g.n[D] * (double)g.n[D];
+  // the zero line's flux steps multiply by 1 / n^2 (exact for n_D a power of
+  // two) rather than divide: an FP64 division per step made its workgroup the
+  // last to finish
+  const double inv_s2 = 1.0 / s2;
   const int64_t ncols = g.nb / L;
   const int64_t c0 = blk * CW;
   const int nl = (int)((ncols - c0) < CW ? (ncols - c0) : CW);  // lines of this tile
@@ -539,7 +543,7 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
             rv[j] = (T)dp;
             sum += dp;
             cp -= bj;
-            dp += cp / s2;
+            dp += cp * inv_s2;
           } else {
             double r;
             cp = tri_cstep(lam, s2, i, L, cp, &r);
