@@ -303,6 +303,21 @@ int dot_coarsen_data(int32_t D, const int32_t* n, const double* rho0, const doub
  * and the iteration counter and sigma schedule restart. The plans need the
  * same D and precision and fine n[d] = 2 * coarse n[d]. Blocks. */
 int dot_prolong(const dot_plan* coarse, const void* coarse_state, dot_plan* fine, void* fine_state, void* stream);
+
+/* ---- finishing a mixed-precision solve in FP64 -------------------------- */
+/* Continue the iterate of Algorithm 2 held in `mixed_state` (a state of
+ * `mixed_plan`, DOT_MIXED) in `fp64_state` (a state of `fp64_plan`, DOT_FP64,
+ * made from the same problem: same grid, data and check cadence; grid and
+ * cadence are checked). phi and alpha are copied (FP64 in both layouts), q,
+ * q_new and beta widened exactly from FP32, the z-weight planes cleared (they
+ * carry values only inside an iteration); sigma, the residuals of the last
+ * check, the iteration and check counters and the sigma schedule carry over,
+ * tau / tol / the sigma-rule switch come from fp64_plan, and the stop flag is
+ * cleared. dot_run on fp64_plan then continues where the mixed run stopped.
+ * For mixed runs that level off above their tolerance at the FP32 storage
+ * floor. mixed_state is not modified. Blocks. */
+int dot_state_promote(const dot_plan* mixed_plan, const void* mixed_state, dot_plan* fp64_plan, void* fp64_state,
+                      void* stream);
 /* One-shot multilevel solve with `levels` coarser grids (0 = plain solve):
  * allocates, solves level by level on the default stream, copies rho / m of
  * the target grid (as dot_solve) and frees. res: the target level;

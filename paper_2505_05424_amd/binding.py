@@ -30,7 +30,7 @@ EXPORTED = [
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
     "dot_plan_set_graphs", "dot_batch_set_graphs",
     "dot_plan_set_schedule", "dot_batch_set_schedule", "dot_plan_get_schedule", "dot_batch_get_schedule",
-    "dot_plan_autotune", "dot_batch_autotune",
+    "dot_plan_autotune", "dot_batch_autotune", "dot_state_promote",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
 ]
@@ -188,6 +188,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_uint8)]
     lib.dot_prolong.argtypes = [vp, vp, vp, vp, vp]
+    lib.dot_state_promote.argtypes = [vp, vp, vp, vp, vp]
     lib.dot_solve_multilevel.argtypes = [ctypes.POINTER(dot_problem), i32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result),
                                          ctypes.POINTER(dot_result)]
@@ -563,6 +564,11 @@ def dot_coarsen_data(D, n, rho0, rho1, mask=None):
                                    mk.ctypes.data_as(u8) if mk is not None else None, _dptr(o0), _dptr(o1),
                                    mo.ctypes.data_as(u8) if mo is not None else None))
     return nc, o0, o1, mo
+
+
+def dot_state_promote(mixed_plan, mixed_state_ptr: int, fp64_plan, fp64_state_ptr: int, stream: int = 0):
+    _check(load().dot_state_promote(mixed_plan.handle, ctypes.c_void_p(mixed_state_ptr), fp64_plan.handle,
+                                    ctypes.c_void_p(fp64_state_ptr), ctypes.c_void_p(stream)))
 
 
 def dot_prolong(coarse: Plan, coarse_state_ptr: int, fine: Plan, fine_state_ptr: int, stream: int = 0):

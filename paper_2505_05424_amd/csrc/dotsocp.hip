@@ -1876,6 +1876,54 @@ int prolong_planes(const dot_plan* C, const void* coarse_state, dot_plan* F, voi
 
 extern "C" {
 
+int dot_state_promote(const dot_plan* M, const void* mixed_state, dot_plan* F, void* fp64_state, void* stream) {
+  if (!M || !mixed_state || !F || !fp64_state) return fail(DOT_EINVAL, "null argument");
+  if (M->precision != DOT_MIXED || F->precision != DOT_FP64)
+    return fail(DOT_EINVAL, "promotion goes from a mixed-precision plan to an FP64 plan");
+  bool same = M->D == F->D && M->cadence == F->cadence;
+  for (int a = 0; a <= M->D; ++a) same = same && M->n[a] == F->n[a];
+  if (!same) return fail(DOT_EINVAL, "the two plans differ in grid or check cadence");
+  hipStream_t st = (hipStream_t)stream;
+  const int D = M->D;
+  const int64_t nb = M->g.nb;
+  const char* ms = static_cast<const char*>(mixed_state);
+  char* fs = static_cast<char*>(fp64_state);
+  // phi and alpha are FP64 in both layouts
+  HIP_OK(hipMemcpyAsync(fs + F->off_phi, ms + M->off_phi, (size_t)nb * 8, hipMemcpyDeviceToDevice, st));
+  HIP_OK(hipMemcpyAsync(fs + F->off_alpha, ms + M->off_alpha, (size_t)(D + 1) * nb * 8, hipMemcpyDeviceToDevice, st));
+  // q and q_new (adjacent in both layouts), then beta: widened
+  auto widen = [&](size_t src_off, size_t dst_off, int64_t n) -> int {
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(kb_widen, dim3(std::max(1u, grid)), dim3(256), 0, st,
+                       reinterpret_cast<const float*>(ms + src_off), reinterpret_cast<double*>(fs + dst_off), n);
+    HIP_OK(hipGetLastError());
+    return DOT_OK;
+  };
+  int rc = widen(M->off_q, F->off_q, (int64_t)(2 * (D + 1)) * nb);
+  if (rc || (rc = widen(M->off_beta, F->off_beta, (int64_t)M->K * nb))) return rc;
+  // the W planes only carry values inside an iteration
+  HIP_OK(hipMemsetAsync(fs + F->off_w, 0, (size_t)(4 * D) * nb * 8, st));
+  // control block: the FP64 plan's parameters, the iterate's sigma, counters
+  // and sigma schedule
+  HIP_OK(hipMemcpyAsync(M->host_ctl, ms + M->ctl_offset, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  const Ctl m = *M->host_ctl;
+  Ctl f = initial_ctl(F);
+  f.sigma = m.sigma;
+  for (int k = 0; k < 8; ++k) f.eta[k] = m.eta[k];
+  f.objective = m.objective;
+  f.dual_objective = m.dual_objective;
+  f.iter = m.iter;
+  f.checks = m.checks;
+  f.sigma_changes = m.sigma_changes;
+  f.next_update = m.next_update;
+  f.gap = m.gap;
+  *F->host_ctl = f;
+  HIP_OK(hipMemcpyAsync(fs + F->ctl_offset, F->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return DOT_OK;
+}
+
 int dot_prolong(const dot_plan* C, const void* coarse_state, dot_plan* F, void* fine_state, void* stream) {
   if (!C || !F || !coarse_state || !fine_state) return fail(DOT_EINVAL, "null argument");
   if (C->D != F->D || C->precision != F->precision) return fail(DOT_EINVAL, "plans differ in D or precision");

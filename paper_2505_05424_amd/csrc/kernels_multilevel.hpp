@@ -66,4 +66,13 @@ kb_prolong(const Geo gc, const Geo gf, const T* __restrict__ src, T* __restrict_
   o[i] = (T)v;
 }
 
+// FP32 planes of a mixed-precision state widened to FP64 (exact), for
+// continuing a solve in FP64.
+__global__ void __launch_bounds__(256) kb_widen(const float* __restrict__ src, double* __restrict__ dst, int64_t n) {
+  gp<const float> s = glob(src);
+  gp<double> o = glob(dst);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    o[i] = (double)s[i];
+}
+
 }  // namespace dot
