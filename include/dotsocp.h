@@ -304,6 +304,26 @@ int dot_coarsen_data(int32_t D, const int32_t* n, const double* rho0, const doub
  * same D and precision and fine n[d] = 2 * coarse n[d]. Blocks. */
 int dot_prolong(const dot_plan* coarse, const void* coarse_state, dot_plan* fine, void* fine_state, void* stream);
 
+/* ---- checkpoint / warm start --------------------------------------------- */
+/* The iterate of Algorithm 2 (q, alpha, beta and sigma) in and out of a state
+ * (restarting from the latest iterate, as the paper does when sigma changes,
+ * Sec. 5.3). Host FP64 arrays in the padded-box layout of dot_plan_info: nb
+ * scalars per plane in node order (time slowest, last spatial axis fastest);
+ * q and alpha hold D+1 planes (q0 / alpha0 on cells: time slices t < n0;
+ * q_d / alpha_d on G^s_d: x_d < n_d), beta K planes (cells). */
+/* Copies out the newest iterate and sigma (any output may be NULL); positions
+ * outside a plane's set are zero. Mixed precision: q and beta widened exactly
+ * from FP32. Blocks. */
+int dot_state_export(const dot_plan* plan, const void* state, double* q, double* alpha, double* beta, double* sigma,
+                     void* stream);
+/* Starts `state` from a given iterate: zero state, then q, alpha, beta (values
+ * outside a plane's set are ignored; mixed precision rounds q and beta to
+ * FP32) and sigma (> 0); phi and the z-weights start at zero and the
+ * iteration and check counters and the sigma schedule start anew, as for a
+ * new solve. DOT_EINVAL for a non-finite value or sigma. Blocks. */
+int dot_state_import(dot_plan* plan, void* state, const double* q, const double* alpha, const double* beta,
+                     double sigma, void* stream);
+
 /* ---- finishing a mixed-precision solve in FP64 -------------------------- */
 /* Continue the iterate of Algorithm 2 held in `mixed_state` (a state of
  * `mixed_plan`, DOT_MIXED) in `fp64_state` (a state of `fp64_plan`, DOT_FP64,

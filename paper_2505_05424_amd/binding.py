@@ -30,7 +30,7 @@ EXPORTED = [
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
     "dot_plan_set_graphs", "dot_batch_set_graphs",
     "dot_plan_set_schedule", "dot_batch_set_schedule", "dot_plan_get_schedule", "dot_batch_get_schedule",
-    "dot_plan_autotune", "dot_batch_autotune", "dot_state_promote",
+    "dot_plan_autotune", "dot_batch_autotune", "dot_state_promote", "dot_state_export", "dot_state_import",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
 ]
@@ -189,6 +189,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                      ctypes.POINTER(ctypes.c_uint8)]
     lib.dot_prolong.argtypes = [vp, vp, vp, vp, vp]
     lib.dot_state_promote.argtypes = [vp, vp, vp, vp, vp]
+    pd = ctypes.POINTER(ctypes.c_double)
+    lib.dot_state_export.argtypes = [vp, vp, pd, pd, pd, pd, vp]
+    lib.dot_state_import.argtypes = [vp, vp, pd, pd, pd, dbl, vp]
     lib.dot_solve_multilevel.argtypes = [ctypes.POINTER(dot_problem), i32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result),
                                          ctypes.POINTER(dot_result)]
@@ -564,6 +567,29 @@ def dot_coarsen_data(D, n, rho0, rho1, mask=None):
                                    mk.ctypes.data_as(u8) if mk is not None else None, _dptr(o0), _dptr(o1),
                                    mo.ctypes.data_as(u8) if mo is not None else None))
     return nc, o0, o1, mo
+
+
+def dot_state_export(plan, state_ptr: int, stream: int = 0):
+    """Returns (q, alpha, beta, sigma): padded-box planes, shapes (D+1, nb), (D+1, nb), (K, nb)."""
+    nb, D, K = int(plan.info.nb), plan.D, int(plan.info.K)
+    q = np.zeros((D + 1, nb))
+    alpha = np.zeros((D + 1, nb))
+    beta = np.zeros((K, nb))
+    sigma = ctypes.c_double()
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    _check(load().dot_state_export(plan.handle, ctypes.c_void_p(state_ptr), dp(q), dp(alpha), dp(beta),
+                                   ctypes.byref(sigma), ctypes.c_void_p(stream)))
+    return q, alpha, beta, float(sigma.value)
+
+
+def dot_state_import(plan, state_ptr: int, q, alpha, beta, sigma: float, stream: int = 0):
+    nb, D, K = int(plan.info.nb), plan.D, int(plan.info.K)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(D + 1, nb)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64).reshape(D + 1, nb)
+    beta = np.ascontiguousarray(beta, dtype=np.float64).reshape(K, nb)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    _check(load().dot_state_import(plan.handle, ctypes.c_void_p(state_ptr), dp(q), dp(alpha), dp(beta),
+                                   float(sigma), ctypes.c_void_p(stream)))
 
 
 def dot_state_promote(mixed_plan, mixed_state_ptr: int, fp64_plan, fp64_state_ptr: int, stream: int = 0):

@@ -1874,7 +1874,99 @@ int prolong_planes(const dot_plan* C, const void* coarse_state, dot_plan* F, voi
 
 }  // namespace
 
+namespace {
+
+// Whether node i of the padded box lies in a plane of kind `axis`: 0 for cell
+// planes (time slices t < n0), d >= 1 for the G^s_d planes of q_d / alpha_d
+// (x_d < n_d).
+bool in_plane(const Geo& g, int axis, int64_t i) {
+  if (axis == 0) return i / g.stride[0] < g.n[0];
+  return (i / g.stride[axis]) % g.N[axis] < g.n[axis];
+}
+
+}  // namespace
+
 extern "C" {
+
+int dot_state_export(const dot_plan* P, const void* state, double* q, double* alpha, double* beta, double* sigma,
+                     void* stream) {
+  if (!P || !state) return fail(DOT_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  const char* s = static_cast<const char*>(state);
+  HIP_OK(hipMemcpyAsync(P->host_ctl, s + P->ctl_offset, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  const Ctl c = *P->host_ctl;
+  const int64_t nb = P->g.nb;
+  // after k iterations the newest q is the buffer k & 1 (q, then q_new)
+  auto fetch = [&](size_t off, int planes, double* out) -> int {
+    if (!out) return DOT_OK;
+    const size_t n = (size_t)planes * nb;
+    if (P->precision == DOT_FP64) {
+      HIP_OK(hipMemcpyAsync(out, s + off, n * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+    } else {
+      std::vector<float> tmp(n);
+      HIP_OK(hipMemcpyAsync(tmp.data(), s + off, n * sizeof(float), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      for (size_t i = 0; i < n; ++i) out[i] = (double)tmp[i];
+    }
+    return DOT_OK;
+  };
+  int rc = fetch((c.iter & 1) ? P->off_qn : P->off_q, P->D + 1, q);
+  if (rc || (rc = fetch(P->off_beta, P->K, beta))) return rc;
+  if (alpha) {
+    HIP_OK(hipMemcpyAsync(alpha, s + P->off_alpha, (size_t)(P->D + 1) * nb * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+    HIP_OK(hipStreamSynchronize(st));
+  }
+  if (sigma) *sigma = c.sigma;
+  return DOT_OK;
+}
+
+int dot_state_import(dot_plan* P, void* state, const double* q, const double* alpha, const double* beta, double sigma,
+                     void* stream) {
+  if (!P || !state || !q || !alpha || !beta) return fail(DOT_EINVAL, "null argument");
+  if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(DOT_EINVAL, "sigma must be positive and finite");
+  const Geo& g = P->g;
+  const int64_t nb = g.nb;
+  const int D = P->D;
+  for (const auto& arr : {std::make_pair(q, D + 1), std::make_pair(alpha, D + 1), std::make_pair(beta, P->K)})
+    for (int64_t i = 0; i < (int64_t)arr.second * nb; ++i)
+      if (!std::isfinite(arr.first[i])) return fail(DOT_EINVAL, "non-finite value in the iterate");
+  hipStream_t st = (hipStream_t)stream;
+  int rc = dot_state_reset(P, state, stream);
+  if (rc) return rc;
+  char* s = static_cast<char*>(state);
+  // planes in the storage type, positions outside each plane's set zeroed
+  auto put = [&](size_t off, int planes, const double* src, bool is_q_or_alpha, bool fp64) -> int {
+    const size_t n = (size_t)planes * nb;
+    std::vector<double> v(n);
+    for (int p = 0; p < planes; ++p) {
+      const int kind = is_q_or_alpha ? p : 0;
+      for (int64_t i = 0; i < nb; ++i) v[(size_t)p * nb + i] = in_plane(g, kind, i) ? src[(size_t)p * nb + i] : 0.0;
+    }
+    if (fp64) {
+      HIP_OK(hipMemcpyAsync(s + off, v.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_OK(hipStreamSynchronize(st));
+    } else {
+      std::vector<float> f(n);
+      for (size_t i = 0; i < n; ++i) f[i] = (float)v[i];
+      HIP_OK(hipMemcpyAsync(s + off, f.data(), n * sizeof(float), hipMemcpyHostToDevice, st));
+      HIP_OK(hipStreamSynchronize(st));
+    }
+    return DOT_OK;
+  };
+  const bool fp64 = P->precision == DOT_FP64;
+  if ((rc = put(P->off_q, D + 1, q, true, fp64)) || (rc = put(P->off_alpha, D + 1, alpha, true, true)) ||
+      (rc = put(P->off_beta, P->K, beta, false, fp64)))
+    return rc;
+  Ctl c = initial_ctl(P);
+  c.sigma = sigma;
+  *P->host_ctl = c;
+  HIP_OK(hipMemcpyAsync(s + P->ctl_offset, P->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return DOT_OK;
+}
 
 int dot_state_promote(const dot_plan* M, const void* mixed_state, dot_plan* F, void* fp64_state, void* stream) {
   if (!M || !mixed_state || !F || !fp64_state) return fail(DOT_EINVAL, "null argument");
