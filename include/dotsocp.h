@@ -70,7 +70,7 @@ typedef enum {
   DOT_RUNNING = -1,
   DOT_CONVERGED = 0, /* eta_dot <= tol at a residual check */
   DOT_MAXITER = 1,   /* iteration cap reached */
-  DOT_TIMEOUT = 2,
+  DOT_TIMEOUT = 2,   /* time_limit_s ran out (the state can be continued) */
   DOT_DIVERGED = 3   /* a residual became NaN or Inf */
 } dot_term;
 
@@ -90,6 +90,10 @@ typedef struct {
   int32_t sigma_gap0;     /* first sigma decision after this many iterations; 0 selects 10 */
   double sigma_growth;    /* gap growth g' = floor(growth*g) + check_every, rounded down
                              to a multiple of check_every; 0 selects 1.2 */
+  double time_limit_s;    /* wall-clock budget of one dot_run / dot_batch_run call in seconds
+                             (0: none). When it runs out the call returns at its next poll
+                             of the control blocks (every 40 iterations) with term
+                             DOT_TIMEOUT; the state is left resumable (a later call goes on) */
 } dot_problem;
 
 typedef struct {
@@ -157,7 +161,8 @@ int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double
  * / h^2), solved by elimination in FP64; same linear system, same phi up to
  * rounding (forward error within the condition number of the line systems
  * times the FP64 unit, which grows with the square of the axis length). Such
- * an axis has no length limit; the other axes must fit a transform tile. */
+ * an axis has no transform-tile limit (every axis stays within the 4096
+ * segments dot_plan_create accepts); the other axes must fit a tile. */
 int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
 /* a3 + a4 as the iteration runs them (right-hand side sweep, then the
  * transform passes): phi from (q, alpha, sigma). */

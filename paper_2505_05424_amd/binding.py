@@ -57,6 +57,7 @@ class dot_problem(ctypes.Structure):
         ("adapt_sigma", ctypes.c_int32),
         ("sigma_gap0", ctypes.c_int32),
         ("sigma_growth", ctypes.c_double),
+        ("time_limit_s", ctypes.c_double),
     ]
 
 
@@ -219,7 +220,7 @@ def _dptr(a: np.ndarray):
 
 def make_problem(D: int, n: Sequence[int], rho0, rho1, mask=None, tol=1e-6, max_iter=10000,
                  precision=DOT_FP64, tau=0.0, sigma0=0.0, check_every=0, adapt_sigma=1,
-                 sigma_gap0=0, sigma_growth=0.0):
+                 sigma_gap0=0, sigma_growth=0.0, time_limit_s=0.0):
     """Fill a dot_problem; returns (struct, keepalive) — keep both alive while in use."""
     r0 = np.ascontiguousarray(rho0, dtype=np.float64).ravel()
     r1 = np.ascontiguousarray(rho1, dtype=np.float64).ravel()
@@ -243,6 +244,7 @@ def make_problem(D: int, n: Sequence[int], rho0, rho1, mask=None, tol=1e-6, max_
     p.adapt_sigma = adapt_sigma
     p.sigma_gap0 = sigma_gap0
     p.sigma_growth = sigma_growth
+    p.time_limit_s = time_limit_s
     return p, keep
 
 

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -142,6 +143,7 @@ struct dot_plan {
   double tau = 1.9, sigma0 = 30.0, tol = 1e-6;
   int max_iter = 1000, cadence = 5, adapt = 1, gap0 = 10;
   double growth = 1.2;
+  double time_limit = 0.0;  // seconds per run call (0: none)
   double vol = 1.0, c_norm2 = 0.0, d_norm2 = 0.0;
   int64_t nblocks = 0;       // workgroups of one node sweep (g.nsweep)
   int64_t partial_rows = 0;  // capacity of the partial-sum rows (nsweep at one slice per workgroup)
@@ -727,8 +729,9 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
 // executor has a graph cache and no kernel class is being timed.
 template <typename T, int D>
 int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t ctl_stride, void* ctl_host,
-              hipStream_t st, int* done_iters, int nctl = -1) {
+              hipStream_t st, int* done_iters, int nctl = -1, double time_limit = 0.0, bool* timed_out = nullptr) {
   const int poll = 40;
+  const auto t_start = std::chrono::steady_clock::now();
   if (nctl < 0) nctl = E.ninst;
   auto all_stopped = [&]() {
     for (int i = 0; i < nctl; ++i)
@@ -761,6 +764,12 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
       HIP_OK(hipStreamSynchronize(st));
       if (E.prof) E.prof->collect();
       if (all_stopped()) break;
+      // wall-clock budget: return with the state as it is (resumable)
+      if (time_limit > 0.0 &&
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count() >= time_limit) {
+        if (timed_out) *timed_out = true;
+        break;
+      }
     }
   }
   HIP_OK(hipMemcpyAsync(ctl_host, ctl_dev, ctl_stride * nctl, hipMemcpyDeviceToHost, st));
@@ -851,8 +860,13 @@ struct RunF {
     int rc = upload_inst(E, state_inst<T>(P, state, ctl), st);
     if (rc) return rc;
     if (!P->host_ctl->stop) {
-      rc = run_iters<T, D>(E, it0, max_iters, ctl, sizeof(Ctl), P->host_ctl, st, nullptr);
+      bool timed_out = false;
+      rc = run_iters<T, D>(E, it0, max_iters, ctl, sizeof(Ctl), P->host_ctl, st, nullptr, -1, P->time_limit,
+                           &timed_out);
       if (rc) return rc;
+      fill_result(*P->host_ctl, res);
+      if (timed_out && !P->host_ctl->stop && res) res->term = DOT_TIMEOUT;
+      return DOT_OK;
     }
     fill_result(*P->host_ctl, res);
     return DOT_OK;
@@ -961,6 +975,8 @@ int validate(const dot_problem* p) {
   if (p->sigma0 < 0 || !std::isfinite(p->sigma0)) return fail(DOT_EINVAL, "sigma0 must be > 0 (0 selects 30)");
   if (p->check_every < 0) return fail(DOT_EINVAL, "check_every must be >= 0");
   if (p->sigma_gap0 < 0 || p->sigma_growth < 0) return fail(DOT_EINVAL, "sigma schedule must be >= 0");
+  if (!(p->time_limit_s >= 0) || !std::isfinite(p->time_limit_s))
+    return fail(DOT_EINVAL, "time_limit_s must be >= 0 and finite");
   int64_t nx = 1;
   for (int d = 1; d <= p->D; ++d) nx *= (int64_t)p->n[d] + 1;
   double m0 = 0.0, m1 = 0.0;
@@ -1095,10 +1111,14 @@ int batch_descriptors(dot_batch* B, void* ws, hipStream_t st) {
 
 template <typename T, int D>
 struct BatchRunF {
-  static int run(dot_batch* B, void* ws, int max_iters, hipStream_t st, int* done) {
+  static int run(dot_batch* B, void* ws, int max_iters, hipStream_t st, int* done, bool* timed_out) {
     int rc = batch_descriptors<T>(B, ws, st);
     if (rc) return rc;
-    return run_iters<T, D>(B->E, B->it, max_iters, ws, B->ctl_stride, B->host_ctl, st, done);
+    // the smallest time budget of the instances bounds the call
+    double limit = 0.0;
+    for (auto* P : B->plans)
+      if (P->time_limit > 0.0) limit = limit > 0.0 ? std::min(limit, P->time_limit) : P->time_limit;
+    return run_iters<T, D>(B->E, B->it, max_iters, ws, B->ctl_stride, B->host_ctl, st, done, -1, limit, timed_out);
   }
 };
 
@@ -1357,6 +1377,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   P->adapt = p->adapt_sigma;
   P->gap0 = p->sigma_gap0 > 0 ? p->sigma_gap0 : 10;
   P->growth = p->sigma_growth > 0 ? p->sigma_growth : 1.2;
+  P->time_limit = p->time_limit_s;
   HIP_OK(hipGetDevice(&P->device));
   Geo& g = P->g;
   g.D = D;
@@ -1651,13 +1672,16 @@ int dot_batch_run(dot_batch* B, void* ws, int32_t max_iters, void* stream, dot_r
   if (!B || !ws || max_iters < 0) return fail(DOT_EINVAL, "bad argument");
   hipStream_t st = (hipStream_t)stream;
   int done = 0;
-  int rc = dispatch<BatchRunF>(B->precision, B->D, B, ws, (int)max_iters, st, &done);
+  bool timed_out = false;
+  int rc = dispatch<BatchRunF>(B->precision, B->D, B, ws, (int)max_iters, st, &done, &timed_out);
   if (rc) return rc;
   B->it += done;
   if (results)
-    for (size_t i = 0; i < B->plans.size(); ++i)
-      fill_result(*reinterpret_cast<const Ctl*>(reinterpret_cast<char*>(B->host_ctl) + i * B->ctl_stride),
-                  &results[i]);
+    for (size_t i = 0; i < B->plans.size(); ++i) {
+      const Ctl& c = *reinterpret_cast<const Ctl*>(reinterpret_cast<char*>(B->host_ctl) + i * B->ctl_stride);
+      fill_result(c, &results[i]);
+      if (timed_out && !c.stop) results[i].term = DOT_TIMEOUT;
+    }
   return DOT_OK;
 }
 

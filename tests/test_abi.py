@@ -64,3 +64,35 @@ def test_coarsen_data_matches_the_oracle(D, n, masked):
     np.testing.assert_allclose(r1, q1, rtol=1e-14, atol=1e-17)
     if masked:
         np.testing.assert_array_equal(mk, mk2)
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """sizeof and every field offset of the ctypes structures equal those the
+    C compiler gives the header's structures (plain gcc, no GPU)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = {"dot_problem": B.dot_problem, "dot_result": B.dot_result, "dot_plan_info": B.dot_plan_info,
+               "dot_schedule": B.dot_schedule}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dotsocp.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            parts = line.split()
+            got[tuple(parts[:-1])] = int(parts[-1])
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)

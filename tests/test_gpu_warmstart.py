@@ -115,3 +115,41 @@ def test_import_rejects_invalid_input():
     bad[0, 3] = np.inf
     with pytest.raises(B.DotError):
         B.dot_state_import(plan, s.ptr, q, bad, be, sg, st)
+
+
+def test_time_budget_returns_timeout_and_the_state_resumes():
+    """A wall-clock budget ends dot_run at its next poll (every 40 iterations)
+    with DOT_TIMEOUT; the state goes on where it stopped, bitwise as an
+    uninterrupted run."""
+    inst = dotgen.config2_instance()
+    timed = _plan(inst, tol=1e-6, max_iter=100000, time_limit_s=1e-6)
+    s = G.GpuState(timed)
+    s.reset()
+    r1 = s.run(100000)
+    assert B.TERM_NAMES[r1.term] == "timeout" and r1.iters == 40
+    r2 = s.run(100000)
+    assert B.TERM_NAMES[r2.term] == "timeout" and r2.iters == 80
+    plain = _plan(inst, tol=1e-6, max_iter=100000)
+    p = G.GpuState(plain)
+    p.reset()
+    r = p.run(80)
+    assert r.iters == 80 and r.objective == r2.objective and r.eta_dot == r2.eta_dot and r.sigma == r2.sigma
+    rho, m = s.extract()
+    rho_p, m_p = p.extract()
+    assert np.array_equal(rho, rho_p)
+    # a batch stops at the smallest budget of its instances
+    insts = [inst, dotgen.tiny_instance(2, (8, 20, 24), seed=95, floor=0.02)]
+    batch = B.dot_batch_create(insts, tol=1e-6, max_iter=100000, time_limit_s=1e-6)
+    torch = G.torch_mod()
+    ws = torch.zeros(int(batch.workspace_bytes), dtype=torch.uint8, device="cuda")
+    st = G.stream_handle()
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    res = B.dot_batch_run(batch, ws.data_ptr(), 100000, st)
+    assert all(B.TERM_NAMES[x.term] == "timeout" and x.iters == 40 for x in res)
+
+
+def test_invalid_time_budget_is_rejected():
+    inst = dotgen.tiny_instance(2, (8, 20, 24), seed=96, floor=0.02)
+    for bad in (-1.0, float("inf"), float("nan")):
+        with pytest.raises(B.DotError):
+            _plan(inst, time_limit_s=bad)
