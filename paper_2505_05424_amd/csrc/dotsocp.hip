@@ -1612,9 +1612,14 @@ int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
   std::unique_ptr<dot_batch, void (*)(dot_batch*)> B(new (std::nothrow) dot_batch(), dot_batch_destroy);
   if (!B) return fail(DOT_ENOMEM, "host allocation failed");
   auto cad = [](const dot_problem& p) { return p.check_every > 0 ? p.check_every : 5; };
+  // every problem is checked before any device work
   for (int i = 0; i < count; ++i) {
     if (probs[i].D != probs[0].D || probs[i].precision != probs[0].precision || cad(probs[i]) != cad(probs[0]))
       return fail(DOT_EINVAL, "all problems of a batch need the same D, precision and check cadence");
+    const int rc = validate(&probs[i]);
+    if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
+  }
+  for (int i = 0; i < count; ++i) {
     dot_plan* P = nullptr;
     int rc = dot_plan_create(&probs[i], &P);
     if (rc) return fail(rc, "problem " + std::to_string(i) + ": " + g_err);
