@@ -329,6 +329,17 @@ int dot_state_export(const dot_plan* plan, const void* state, double* q, double*
 int dot_state_import(dot_plan* plan, void* state, const double* q, const double* alpha, const double* beta,
                      double sigma, void* stream);
 
+/* ---- sigma history -------------------------------------------------------- */
+/* The penalty changes of the sigma rule (Sec. 5.3) made so far in `state`:
+ * the new sigma and the iteration count of the check that made each change,
+ * oldest first; the control block keeps the last 32, and at most `cap` of
+ * them (the newest) are written. *count receives the number of changes
+ * overall (equal to dot_result.sigma_changes). Outputs may be NULL. Blocks. */
+int dot_sigma_history(const dot_plan* plan, const void* state, double* sigma, int32_t* at_iter, int32_t cap,
+                      int32_t* count, void* stream);
+int dot_batch_sigma_history(const dot_batch* batch, const void* workspace, int32_t index, double* sigma,
+                            int32_t* at_iter, int32_t cap, int32_t* count, void* stream);
+
 /* ---- finishing a mixed-precision solve in FP64 -------------------------- */
 /* Continue the iterate of Algorithm 2 held in `mixed_state` (a state of
  * `mixed_plan`, DOT_MIXED) in `fp64_state` (a state of `fp64_plan`, DOT_FP64,

@@ -31,6 +31,7 @@ EXPORTED = [
     "dot_plan_set_graphs", "dot_batch_set_graphs",
     "dot_plan_set_schedule", "dot_batch_set_schedule", "dot_plan_get_schedule", "dot_batch_get_schedule",
     "dot_plan_autotune", "dot_batch_autotune", "dot_state_promote", "dot_state_export", "dot_state_import",
+    "dot_sigma_history", "dot_batch_sigma_history",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
 ]
@@ -193,6 +194,9 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     pd = ctypes.POINTER(ctypes.c_double)
     lib.dot_state_export.argtypes = [vp, vp, pd, pd, pd, pd, vp]
     lib.dot_state_import.argtypes = [vp, vp, pd, pd, pd, dbl, vp]
+    pi = ctypes.POINTER(ctypes.c_int32)
+    lib.dot_sigma_history.argtypes = [vp, vp, pd, pi, i32, pi, vp]
+    lib.dot_batch_sigma_history.argtypes = [vp, vp, i32, pd, pi, i32, pi, vp]
     lib.dot_solve_multilevel.argtypes = [ctypes.POINTER(dot_problem), i32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(dot_result),
                                          ctypes.POINTER(dot_result)]
@@ -592,6 +596,27 @@ def dot_state_import(plan, state_ptr: int, q, alpha, beta, sigma: float, stream:
     dp = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
     _check(load().dot_state_import(plan.handle, ctypes.c_void_p(state_ptr), dp(q), dp(alpha), dp(beta),
                                    float(sigma), ctypes.c_void_p(stream)))
+
+
+def _history(call, cap):
+    sig = np.zeros(cap)
+    its = np.zeros(cap, dtype=np.int32)
+    n = ctypes.c_int32()
+    _check(call(sig.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                its.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(n)))
+    k = min(int(n.value), cap, 32)
+    return [(int(its[j]), float(sig[j])) for j in range(k)], int(n.value)
+
+
+def dot_sigma_history(plan, state_ptr: int, cap: int = 32, stream: int = 0):
+    """Returns ([(iteration, sigma) of the kept changes, oldest first], changes overall)."""
+    return _history(lambda s, i, n: load().dot_sigma_history(plan.handle, ctypes.c_void_p(state_ptr), s, i, cap, n,
+                                                             ctypes.c_void_p(stream)), cap)
+
+
+def dot_batch_sigma_history(batch, ws_ptr: int, index: int, cap: int = 32, stream: int = 0):
+    return _history(lambda s, i, n: load().dot_batch_sigma_history(batch.handle, ctypes.c_void_p(ws_ptr), int(index),
+                                                                   s, i, cap, n, ctypes.c_void_p(stream)), cap)
 
 
 def dot_state_promote(mixed_plan, mixed_state_ptr: int, fp64_plan, fp64_state_ptr: int, stream: int = 0):

@@ -1913,6 +1913,21 @@ bool in_plane(const Geo& g, int axis, int64_t i) {
   return (i / g.stride[axis]) % g.N[axis] < g.n[axis];
 }
 
+// The sigma changes held in a control block, oldest first (at most cap).
+int sigma_history(const Ctl& c, double* sigma, int32_t* at_iter, int32_t cap, int32_t* count) {
+  if (cap < 0) return fail(DOT_EINVAL, "cap must be >= 0");
+  const int n = c.sigma_changes;
+  const int kept = std::min(n, kSigmaHist), first = n - kept;
+  const int out = std::min(kept, (int)cap);
+  for (int j = 0; j < out; ++j) {
+    const int slot = (first + kept - out + j) % kSigmaHist;  // the newest `out` changes
+    if (sigma) sigma[j] = c.hist_sigma[slot];
+    if (at_iter) at_iter[j] = c.hist_iter[slot];
+  }
+  if (count) *count = n;
+  return DOT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1950,6 +1965,27 @@ int dot_state_export(const dot_plan* P, const void* state, double* q, double* al
   }
   if (sigma) *sigma = c.sigma;
   return DOT_OK;
+}
+
+int dot_sigma_history(const dot_plan* P, const void* state, double* sigma, int32_t* at_iter, int32_t cap,
+                      int32_t* count, void* stream) {
+  if (!P || !state) return fail(DOT_EINVAL, "null argument");
+  hipStream_t st = (hipStream_t)stream;
+  HIP_OK(hipMemcpyAsync(P->host_ctl, static_cast<const char*>(state) + P->ctl_offset, sizeof(Ctl),
+                        hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return sigma_history(*P->host_ctl, sigma, at_iter, cap, count);
+}
+
+int dot_batch_sigma_history(const dot_batch* B, const void* ws, int32_t index, double* sigma, int32_t* at_iter,
+                            int32_t cap, int32_t* count, void* stream) {
+  if (!B || !ws || index < 0 || index >= (int)B->plans.size()) return fail(DOT_EINVAL, "bad argument");
+  hipStream_t st = (hipStream_t)stream;
+  Ctl c;
+  HIP_OK(hipMemcpyAsync(&c, static_cast<const char*>(ws) + (size_t)index * B->ctl_stride, sizeof(Ctl),
+                        hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return sigma_history(c, sigma, at_iter, cap, count);
 }
 
 int dot_state_import(dot_plan* P, void* state, const double* q, const double* alpha, const double* beta, double sigma,
@@ -2039,6 +2075,10 @@ int dot_state_promote(const dot_plan* M, const void* mixed_state, dot_plan* F, v
   f.sigma_changes = m.sigma_changes;
   f.next_update = m.next_update;
   f.gap = m.gap;
+  for (int k = 0; k < kSigmaHist; ++k) {
+    f.hist_sigma[k] = m.hist_sigma[k];
+    f.hist_iter[k] = m.hist_iter[k];
+  }
   *F->host_ctl = f;
   HIP_OK(hipMemcpyAsync(fs + F->ctl_offset, F->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));

@@ -51,6 +51,8 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
 
 // Device-resident control block: penalty, counters, stop flag and the last
 // residuals. Kernels read sigma and stop at entry; the finalize kernel writes.
+constexpr int kSigmaHist = 32;  // sigma changes kept in the control block
+
 struct Ctl {
   double sigma;
   double tau;
@@ -68,6 +70,10 @@ struct Ctl {
   int32_t cadence;       // residual-check cadence
   int32_t iter_limit;    // stop (2) at the first check with iter >= iter_limit
   double growth;         // growth factor of the sigma schedule gaps
+  // the last kSigmaHist sigma changes (a ring: change j sits at j % kSigmaHist):
+  // the new sigma and the iteration count of the check that made it
+  double hist_sigma[kSigmaHist];
+  int32_t hist_iter[kSigmaHist];
 };
 
 }  // namespace dot

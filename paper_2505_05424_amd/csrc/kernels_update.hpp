@@ -763,12 +763,17 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
     } else {
       if (c.adapt && c.iter >= c.next_update) {
         const double ratio = eds > 0.0 ? eps / eds : INFINITY;
+        const int changes = c.sigma_changes;
         if (ratio > 2.0) {
           c.sigma *= 1.25;
           c.sigma_changes += 1;
         } else if (ratio < 0.5) {
           c.sigma /= 1.25;
           c.sigma_changes += 1;
+        }
+        if (c.sigma_changes != changes) {
+          c.hist_sigma[changes % kSigmaHist] = c.sigma;
+          c.hist_iter[changes % kSigmaHist] = c.iter;
         }
         while (c.next_update <= c.iter) {
           const int nxt = (int)floor(c.growth * (double)c.gap) + c.cadence;

@@ -153,3 +153,38 @@ def test_invalid_time_budget_is_rejected():
     for bad in (-1.0, float("inf"), float("nan")):
         with pytest.raises(B.DotError):
             _plan(inst, time_limit_s=bad)
+
+
+@pytest.mark.parametrize("name,D,n", [("1d-16x32", 1, (16, 32)), ("2d-8x20x24-masked", 2, (8, 20, 24))],
+                         ids=["1d-16x32", "2d-8x20x24-masked"])
+def test_sigma_history_matches_the_oracle_decisions(name, D, n):
+    """Every change of the sigma rule (Sec. 5.3) on the device: the same
+    iterations and values as the oracle's decisions, in order; the batch
+    keeps each instance's own history."""
+    inst = (dotgen.config1_instance() if D == 1 else
+            dotgen.tiny_instance(D, n, seed=97, floor=0.0, masked=True))
+    iters = 1500
+    P = O.make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask)
+    ref = O.run_fixed(P, iters)
+    expect = [(rec["k"], rec["sigma"] * 1.25 ** rec["decision"]) for rec in ref.history if rec["decision"] != 0]
+    plan = _plan(inst)
+    s = G.GpuState(plan)
+    s.reset()
+    r = s.run(iters)
+    hist, count = B.dot_sigma_history(plan, s.ptr, 32, G.stream_handle())
+    print(f"[case] {name}: {count} sigma changes", flush=True)
+    assert count == r.sigma_changes == len(expect) > 0
+    tail = expect[-min(count, 32):]
+    assert [k for k, _ in hist] == [k for k, _ in tail]
+    for (_, a), (_, b) in zip(hist, tail):
+        assert abs(a - b) <= 1e-12 * b
+    # the same instance inside a batch, next to another one
+    other = dotgen.tiny_instance(2 if D == 2 else 1, (6, 10, 12) if D == 2 else (6, 20), seed=98, floor=0.02)
+    batch = B.dot_batch_create([other, inst], tol=-1.0, max_iter=10 ** 6)
+    torch = G.torch_mod()
+    ws = torch.zeros(int(batch.workspace_bytes), dtype=torch.uint8, device="cuda")
+    st = G.stream_handle()
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    B.dot_batch_run(batch, ws.data_ptr(), iters, st)
+    hb, cb = B.dot_batch_sigma_history(batch, ws.data_ptr(), 1, 32, st)
+    assert cb == count and hb == hist
