@@ -53,7 +53,8 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
 // residuals. Kernels read sigma and stop at entry; the finalize kernel writes.
 constexpr int kSigmaHist = 32;  // sigma changes kept in the control block
 
-struct Ctl {
+// The scalar part, which the finalize step keeps in registers.
+struct CtlState {
   double sigma;
   double tau;
   double tol;
@@ -70,6 +71,9 @@ struct Ctl {
   int32_t cadence;       // residual-check cadence
   int32_t iter_limit;    // stop (2) at the first check with iter >= iter_limit
   double growth;         // growth factor of the sigma schedule gaps
+};
+
+struct Ctl : CtlState {
   // the last kSigmaHist sigma changes (a ring: change j sits at j % kSigmaHist):
   // the new sigma and the iteration count of the check that made it
   double hist_sigma[kSigmaHist];

@@ -705,8 +705,8 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
   // thread 0 requests the control block first, so that its latency overlaps
   // the partial sums
-  Ctl c;
-  if (threadIdx.x == 0) c = *ctl;
+  CtlState c;
+  if (threadIdx.x == 0) c = *static_cast<const CtlState*>(ctl);
   // one pass over the workgroup partials: each thread sums every slot of its
   // workgroups (slot-major rows, read coalesced), then the slots are reduced
   // across the block; waves past the last workgroup hold zeros and skip the
@@ -772,8 +772,8 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
           c.sigma_changes += 1;
         }
         if (c.sigma_changes != changes) {
-          c.hist_sigma[changes % kSigmaHist] = c.sigma;
-          c.hist_iter[changes % kSigmaHist] = c.iter;
+          ctl->hist_sigma[changes % kSigmaHist] = c.sigma;
+          ctl->hist_iter[changes % kSigmaHist] = c.iter;
         }
         while (c.next_update <= c.iter) {
           const int nxt = (int)floor(c.growth * (double)c.gap) + c.cadence;
@@ -784,7 +784,7 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
       if (c.iter >= c.iter_limit) c.stop = 2;
     }
   }
-  *ctl = c;
+  *static_cast<CtlState*>(ctl) = c;
 }
 
 // ---- standalone step kernels (step-level entry points) --------------------
