@@ -90,10 +90,12 @@ typedef struct {
   int32_t sigma_gap0;     /* first sigma decision after this many iterations; 0 selects 10 */
   double sigma_growth;    /* gap growth g' = floor(growth*g) + check_every, rounded down
                              to a multiple of check_every; 0 selects 1.2 */
-  double time_limit_s;    /* wall-clock budget of one dot_run / dot_batch_run call in seconds
-                             (0: none). When it runs out the call returns at its next poll
-                             of the control blocks (every 40 iterations) with term
-                             DOT_TIMEOUT; the state is left resumable (a later call goes on) */
+  double time_limit_s;    /* wall-clock budget in seconds (0: none). dot_run / dot_batch_run:
+                             per call; when it runs out the call returns at its next poll of
+                             the control blocks (every 40 iterations) with term DOT_TIMEOUT
+                             and the state resumable. Serving: from the request's admission
+                             (on its target level); the request is retired at the next step
+                             with DOT_TIMEOUT and its iterate so far */
 } dot_problem;
 
 typedef struct {

@@ -2237,6 +2237,7 @@ struct Request {
   size_t off = 0;               // arena offset of the current level's state
   std::vector<double> rho, m;
   dot_result res{};
+  std::chrono::steady_clock::time_point admitted;  // start of the time budget
   ~Request() {
     for (auto* P : plans) dot_plan_destroy(P);
   }
@@ -2417,6 +2418,7 @@ int ctx_admit(dot_ctx* C, hipStream_t st) {
     r->off = off + r->lvl_off[0];
     off = r->off;
     r->status = kRunning;
+    r->admitted = std::chrono::steady_clock::now();
     C->slots[sl] = r;
     dot_plan* P = r->plan;
     HIP_OK(hipMemsetAsync(static_cast<char*>(C->arena_mem) + off, 0, P->ctl_offset, st));
@@ -2440,8 +2442,15 @@ int ctx_retire(dot_ctx* C, hipStream_t st) {
     Request* r = C->slots[sl];
     if (!r) continue;
     Ctl c = *reinterpret_cast<Ctl*>(reinterpret_cast<char*>(C->h_ctl) + (size_t)sl * C->ctl_stride);
-    if (!c.stop && c.iter < r->plan->max_iter) continue;
-    if (r->level + 1 < (int)r->plans.size()) {
+    // a request's time budget runs from its admission and applies on its
+    // target level (a multilevel request always finishes its coarse levels)
+    const bool last = r->level + 1 == (int)r->plans.size();
+    const double limit = r->plans.back()->time_limit;
+    const bool out_of_time =
+        last && limit > 0.0 &&
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - r->admitted).count() >= limit;
+    if (!c.stop && c.iter < r->plan->max_iter && !out_of_time) continue;
+    if (!last) {
       // multilevel: the next finer level starts from the interpolated
       // iterate, whatever the coarse level's stop reason (as solved alone)
       dot_plan* Pc = r->plans[r->level];
@@ -2471,6 +2480,7 @@ int ctx_retire(dot_ctx* C, hipStream_t st) {
     int rc = extract_impl(P, state, r->rho.data(), r->m.data(), st);
     if (rc) return rc;
     fill_result(c, &r->res);
+    if (!c.stop && c.iter < r->plan->max_iter) r->res.term = DOT_TIMEOUT;
     r->status = kDone;
     C->arena.release(r->block, r->bytes);
     C->slots[sl] = nullptr;

@@ -98,6 +98,33 @@ def test_iteration_limit_retires_like_a_capped_solve():
             assert np.array_equal(a, b)
 
 
+def test_time_budget_retires_a_request_with_timeout():
+    """A request whose time budget (from admission) runs out is retired at the
+    next step with DOT_TIMEOUT and its iterate so far (bitwise that of a solve
+    alone stopped after as many iterations); the request beside it is not
+    affected."""
+    insts = [dotgen.tiny_instance(2, (6, 10, 12), seed=73, floor=0.05),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=74, floor=0.0, masked=True)]
+    ctx = B.dot_ctx_create(2, B.DOT_FP64, 1 << 24, 4)
+    st = G.stream_handle()
+    t_timed = B.dot_ctx_submit(ctx, insts[0], tol=-1.0, max_iter=100000, time_limit_s=1e-6)
+    t_other = B.dot_ctx_submit(ctx, insts[1], tol=-1.0, max_iter=60)
+    for _ in range(5):
+        B.dot_ctx_step(ctx, 20, st)
+    assert B.dot_ctx_poll(ctx, t_timed) == B.CTX_DONE
+    r, rho, m = B.dot_ctx_fetch(ctx, t_timed)
+    assert B.TERM_NAMES[r.term] == "timeout" and r.iters == 20
+    ra, rhoa, ma = _alone(insts[0], B.DOT_FP64, -1.0, 20)
+    assert r.objective == ra.objective and r.eta_dot == ra.eta_dot
+    assert np.array_equal(rho, rhoa)
+    assert B.dot_ctx_poll(ctx, t_other) == B.CTX_DONE
+    r2, rho2, _ = B.dot_ctx_fetch(ctx, t_other)
+    rb, rhob, _ = _alone(insts[1], B.DOT_FP64, -1.0, 60)
+    assert r2.iters == 60 and B.TERM_NAMES[r2.term] == "maxiter"
+    _same(r2, rb)
+    assert np.array_equal(rho2, rhob)
+
+
 def test_footprint_is_the_plan_state_size():
     for D, n in ((1, (5, 40)), (2, (12, 33, 21)), (3, (6, 9, 10, 7))):
         inst = dotgen.tiny_instance(D, n, seed=80 + D)
