@@ -186,6 +186,27 @@ int dot_step_update(dot_plan* plan, const void* phi, const void* q, void* alpha,
 int dot_step_residuals(dot_plan* plan, const void* phi, const void* z, const void* q,
                        const void* alpha, const void* beta, dot_result* res, void* stream);
 
+/* ---- residuals without device allocation --------------------------------- */
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Computes what
+ * dot_step_residuals computes (the relative KKT residuals of Sec. 5.3, the
+ * objective and the dual objective at (phi, z, q, alpha, beta); same kernels,
+ * same summation order, so bitwise the same result) and calls no hipMalloc,
+ * hipFree or other allocating routine: the control block and the
+ * per-workgroup partial sums go to a fixed device array of
+ * DOT_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of the plan's buffers. A plan needs 768
+ * bytes for the control block plus 160 bytes per workgroup of its residual
+ * sweep (about 9,700 workgroups for 3D 32x64^3, 37,000 for 2D 32x1024^2);
+ * beyond the array's size the call returns DOT_EINVAL before any device work.
+ * The current device must be the plan's (DOT_EINVAL otherwise). Every call on
+ * one GPU shares that GPU's array and leaves the last call's contents in it;
+ * calls that overlap on one GPU (other streams or host threads) race. Blocks
+ * and fills *res (iters and term are left 0 / DOT_RUNNING). */
+#define DOT_NOALLOC_SCRATCH_BYTES (8u << 20)
+int dot_step_residuals_noalloc(dot_plan* plan, const void* phi, const void* z, const void* q,
+                               const void* alpha, const void* beta, dot_result* res, void* stream);
+
 /* ---- measurement hook ---------------------------------------------------- */
 /* Kernel classes of one iteration, for dot_profile_select. */
 typedef enum {

@@ -34,7 +34,9 @@ EXPORTED = [
     "dot_sigma_history", "dot_batch_sigma_history",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
+    "dot_step_residuals_noalloc",
 ]
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 CTX_QUEUED, CTX_RUNNING, CTX_DONE = 0, 1, 2
 
@@ -148,6 +150,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_step_cone.argtypes = [vp, vp, vp, dbl, vp, vp]
     lib.dot_step_update.argtypes = [vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp]
     lib.dot_step_residuals.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dot_result), vp]
+    lib.dot_step_residuals_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.POINTER(dot_result), vp]
     lib.dot_profile_select.argtypes = [vp, i32]
     lib.dot_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.dot_solve.argtypes = [ctypes.POINTER(dot_problem), ctypes.POINTER(ctypes.c_double),
@@ -349,6 +352,14 @@ def dot_step_residuals(plan, phi_ptr, z_ptr, q_ptr, alpha_ptr, beta_ptr, stream=
     _check(load().dot_step_residuals(plan.handle, ctypes.c_void_p(phi_ptr), ctypes.c_void_p(z_ptr),
                                      ctypes.c_void_p(q_ptr), ctypes.c_void_p(alpha_ptr), ctypes.c_void_p(beta_ptr),
                                      ctypes.byref(r), ctypes.c_void_p(stream)))
+    return r
+
+
+def dot_step_residuals_noalloc(plan, phi_ptr, z_ptr, q_ptr, alpha_ptr, beta_ptr, stream=0) -> dot_result:
+    r = dot_result()
+    _check(load().dot_step_residuals_noalloc(plan.handle, ctypes.c_void_p(phi_ptr), ctypes.c_void_p(z_ptr),
+                                             ctypes.c_void_p(q_ptr), ctypes.c_void_p(alpha_ptr),
+                                             ctypes.c_void_p(beta_ptr), ctypes.byref(r), ctypes.c_void_p(stream)))
     return r
 
 

@@ -148,6 +148,11 @@ kb_tri_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map) {
 
 // ---- step-level kernels (single instance, caller pointers) ----------------
 
+// Zero n 32-bit words (one workgroup).
+__global__ void __launch_bounds__(256) kb_clear_words(uint32_t* __restrict__ p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0u;
+}
+
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
 kb_cone_out(const Inst<T>* __restrict__ I, double inv_sigma, T* __restrict__ z) {

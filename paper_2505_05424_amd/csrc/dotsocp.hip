@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -963,6 +964,68 @@ struct ResidF {
   }
 };
 
+// ---- residuals without allocation -------------------------------------------
+// dot_step_residuals_noalloc keeps the control block that the finalize step
+// writes and the per-workgroup partial sums of the residual sweep in this
+// file-scope array instead of the plan's buffers. Each GPU the library runs on
+// holds its own copy until the process ends. In host code the array's name is
+// a host-side stand-in, not a device address: host code uses only the address
+// that hipGetSymbolAddress returns for the current device, taken once per
+// device and kept in noalloc_ptr.
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[DOT_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (device current).
+int noalloc_ptr(int device, unsigned char** out) {
+  if (device < 0 || device >= kNoAllocMaxDevices) return fail(DOT_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(DOT_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_noalloc_ptr[device] = p;
+  }
+  *out = static_cast<unsigned char*>(g_noalloc_ptr[device]);
+  return DOT_OK;
+}
+
+// Bytes of the scratch array one residual evaluation of P takes: the control
+// block, then kNumSums partial rows of one entry per workgroup.
+size_t noalloc_bytes(const dot_plan* P) {
+  return align256(sizeof(Ctl)) + (size_t)kNumSums * (size_t)P->nblocks * sizeof(double);
+}
+
+template <typename T, int D>
+struct ResidNoAllocF {
+  static int run(dot_plan* P, const void* phi, const void* z, const void* q, const void* alpha, const void* beta,
+                 unsigned char* scr, hipStream_t st) {
+    Ctl* ctl = reinterpret_cast<Ctl*>(scr);
+    double* partials = reinterpret_cast<double*>(scr + align256(sizeof(Ctl)));
+    Exec E = plan_exec(P, 1);
+    E.prof = nullptr;
+    // the control block starts zeroed (the finalize step reads it and, with
+    // update_ctl = 0, only fills the residuals); a fill kernel rather than a
+    // memset keeps the call capturable. Every partial slot of every workgroup
+    // is written by the two sweeps below, so the partial rows need no clearing.
+    hipLaunchKernelGGL(kb_clear_words, dim3(1), dim3(256), 0, st, reinterpret_cast<uint32_t*>(ctl),
+                       (int)(sizeof(Ctl) / sizeof(uint32_t)));
+    HIP_OK(hipGetLastError());
+    int rc = upload_inst(E, inst_of<T>(P, (double*)phi, (T*)nullptr, (T*)q, (T*)nullptr, (double*)alpha, (T*)beta,
+                                       (T*)nullptr, ctl, partials),
+                         st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((kb_zres<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+                       (const T*)z);
+    HIP_OK(hipGetLastError());
+    if ((rc = check_iter<T, D>(E, 0, 0, st))) return rc;
+    HIP_OK(hipMemcpyAsync(P->host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    return DOT_OK;
+  }
+};
+
 int validate(const dot_problem* p) {
   if (!p) return fail(DOT_EINVAL, "null problem");
   if (p->D < 1 || p->D > 3) return fail(DOT_EINVAL, "D must be 1, 2 or 3");
@@ -1544,6 +1607,31 @@ int dot_step_residuals(dot_plan* P, const void* phi, const void* z, const void* 
   int rc = dispatch<ResidF>(P->precision, P->D, P, phi, z, q, alpha, beta, st);
   if (rc) return rc;
   HIP_OK(hipMemcpyAsync(P->host_ctl, P->step_ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  std::memset(res, 0, sizeof(*res));
+  fill_result(*P->host_ctl, res);
+  res->iters = 0;
+  res->checks = 0;
+  res->term = DOT_RUNNING;
+  return DOT_OK;
+}
+
+int dot_step_residuals_noalloc(dot_plan* P, const void* phi, const void* z, const void* q, const void* alpha,
+                               const void* beta, dot_result* res, void* stream) {
+  if (!P || !phi || !z || !q || !alpha || !beta || !res) return fail(DOT_EINVAL, "bad argument");
+  if (noalloc_bytes(P) > (size_t)DOT_NOALLOC_SCRATCH_BYTES)
+    return fail(DOT_EINVAL, "the residual sweep of this grid needs " + std::to_string(noalloc_bytes(P)) +
+                                " bytes of scratch, more than the " + std::to_string((size_t)DOT_NOALLOC_SCRATCH_BYTES) +
+                                " of dot_step_residuals_noalloc");
+  int cur = -1;
+  HIP_OK(hipGetDevice(&cur));
+  if (cur != P->device) return fail(DOT_EINVAL, "the plan's device must be the current device");
+  unsigned char* scr = nullptr;
+  int rc = noalloc_ptr(cur, &scr);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  rc = dispatch<ResidNoAllocF>(P->precision, P->D, P, phi, z, q, alpha, beta, scr, st);
+  if (rc) return rc;
   HIP_OK(hipStreamSynchronize(st));
   std::memset(res, 0, sizeof(*res));
   fill_result(*P->host_ctl, res);
