@@ -249,7 +249,13 @@ int32_t dot_batch_size(const dot_batch* batch);
 /* zero state, sigma0 and counters for every instance */
 int dot_batch_reset(dot_batch* batch, void* workspace, void* stream);
 /* up to max_iters iterations of all instances in lockstep (stopped instances
- * do no work); blocks; fills results[count] (may be NULL) */
+ * do no work); blocks; fills results[count] (may be NULL). Time budgets
+ * (dot_problem.time_limit_s): the call returns at the first poll after the
+ * smallest nonzero budget among the instances has run out, unless it has done
+ * max_iters iterations by then. On such an early return an unfinished
+ * instance whose own budget has run out reports DOT_TIMEOUT; the other
+ * unfinished instances (no budget, or one not yet spent) report DOT_RUNNING.
+ * Every state is resumable by another dot_batch_run. */
 int dot_batch_run(dot_batch* batch, void* workspace, int32_t max_iters, void* stream, dot_result* results);
 /* rho / m of instance `index`, as dot_extract */
 int dot_batch_extract(dot_batch* batch, const void* workspace, int32_t index, double* rho_out, double* m_out,
@@ -398,16 +404,26 @@ int dot_solve_multilevel(const dot_problem* p, int32_t levels, double* rho_out, 
  * at multiples of 10 iterations of the context's counter, so each request
  * follows exactly the iterates of a solve of that problem alone (dot_run with
  * the same settings): same result fields, bitwise. Requests need the default
- * check cadence (5) and a max_iter that is a multiple of 5. Not thread-safe:
- * one context per host thread. */
+ * check cadence (5) and a max_iter that is a multiple of 5. Every dot_ctx_*
+ * call takes the context's lock and makes the context's device current for
+ * its duration (the caller's current device is restored), so several host
+ * threads may share one context; a dot_ctx_step holds the lock until its
+ * iterations are done. dot_last_error() keeps the calling thread's last
+ * failure, dot_ctx_last_error() the context's. */
 typedef struct dot_ctx dot_ctx;
 typedef enum { DOT_REQ_QUEUED = 0, DOT_REQ_RUNNING = 1, DOT_REQ_DONE = 2 } dot_req_status;
 /* Device bytes one instance of p's D, n and precision takes in the arena
  * (state, control block and reduction partials); 0 for an invalid D. Pure host
  * arithmetic; the rho/mask pointers of p are not read. */
 size_t dot_footprint_bytes(const dot_problem* p);
-/* Reserves the arena (DOT_ENOMEM if the device cannot hold it). */
-int dot_ctx_create(int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_t max_slots, dot_ctx** out);
+/* Reserves the arena on HIP device `device` (-1: the current device) for
+ * requests of D spatial dimensions and one precision, with at most max_slots
+ * running at a time (1..4096). DOT_EINVAL for a device index outside the
+ * devices present or bad arguments; DOT_ENOMEM if the device cannot hold the
+ * budget. Later calls on the context run on that device whatever the caller's
+ * current device, on the stream they are given. */
+int dot_ctx_create(int32_t device, int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_t max_slots,
+                   dot_ctx** out);
 /* Frees the arena and every request, finished or not. */
 void dot_ctx_destroy(dot_ctx* ctx);
 /* Validates p (as dot_plan_create), builds its constant tables and queues it;
@@ -436,6 +452,30 @@ int dot_ctx_poll(dot_ctx* ctx, uint64_t ticket, int32_t* status);
 int dot_ctx_fetch(dot_ctx* ctx, uint64_t ticket, double* rho_out, double* m_out, dot_result* res);
 /* Free arena bytes and the counts of admitted and retired requests. */
 int dot_ctx_stats(const dot_ctx* ctx, size_t* free_bytes, int64_t* admitted, int64_t* retired);
+/* Checkpoint of a running request (restart from the latest iterate, Sec. 5.3,
+ * here without losing any state): between two dot_ctx_step calls, copies the
+ * whole device state of the request's current level -- every plane (phi, q,
+ * q_new, alpha, beta and the workspaces) and its control block (sigma,
+ * counters, sigma schedule, last residuals, iteration cap) -- with a header
+ * naming D, precision, grids and level into the host buffer `buf` of `cap`
+ * bytes. *bytes receives the size needed; with buf NULL only the size is
+ * reported. The request keeps running in this context. DOT_EINVAL for an
+ * unknown ticket, a queued or finished request, or cap too small. Blocks on
+ * `stream`. */
+int dot_ctx_export(dot_ctx* ctx, uint64_t ticket, void* buf, size_t cap, size_t* bytes, void* stream);
+/* Queues a request that resumes from a checkpoint of dot_ctx_export (made by
+ * this or another context with the same D and precision): p and levels must
+ * be those of the exported request (grids and layout are checked against the
+ * header); the host arrays of p are copied before return. At admission its
+ * state and control block are those of the checkpoint, so it continues the
+ * exported iterate exactly: it finishes with bitwise the result the exported
+ * request would have reached without interruption. The time budget of p
+ * restarts at the new admission. DOT_EINVAL on any mismatch, as
+ * dot_ctx_submit otherwise. */
+int dot_ctx_import(dot_ctx* ctx, const dot_problem* p, int32_t levels, const void* buf, size_t bytes,
+                   uint64_t* ticket);
+/* Message of the last failed call on this context ("" if none). */
+const char* dot_ctx_last_error(const dot_ctx* ctx);
 
 #ifdef __cplusplus
 }

@@ -34,7 +34,7 @@ EXPORTED = [
     "dot_sigma_history", "dot_batch_sigma_history",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
-    "dot_step_residuals_noalloc",
+    "dot_step_residuals_noalloc", "dot_ctx_export", "dot_ctx_import", "dot_ctx_last_error",
 ]
 NOALLOC_SCRATCH_BYTES = 8 << 20
 
@@ -177,7 +177,12 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_batch_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.dot_footprint_bytes.argtypes = [ctypes.POINTER(dot_problem)]
     lib.dot_footprint_bytes.restype = ctypes.c_size_t
-    lib.dot_ctx_create.argtypes = [i32, i32, ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+    lib.dot_ctx_create.argtypes = [i32, i32, i32, ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+    lib.dot_ctx_export.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), vp]
+    lib.dot_ctx_import.argtypes = [vp, ctypes.POINTER(dot_problem), i32, vp, ctypes.c_size_t,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    lib.dot_ctx_last_error.argtypes = [vp]
+    lib.dot_ctx_last_error.restype = ctypes.c_char_p
     lib.dot_ctx_destroy.argtypes = [vp]
     lib.dot_ctx_destroy.restype = None
     lib.dot_ctx_submit.argtypes = [vp, ctypes.POINTER(dot_problem), ctypes.POINTER(ctypes.c_uint64)]
@@ -205,7 +210,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                          ctypes.POINTER(dot_result)]
     for name in EXPORTED:
         if name not in ("dot_last_error", "dot_plan_destroy", "dot_batch_destroy", "dot_batch_workspace_bytes",
-                        "dot_batch_size", "dot_footprint_bytes", "dot_ctx_destroy"):
+                        "dot_batch_size", "dot_footprint_bytes", "dot_ctx_destroy", "dot_ctx_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -480,12 +485,16 @@ class Batch:
             pass
 
 
-def dot_batch_create(insts, **kw) -> Batch:
-    """Batch of problems (objects with D, n, rho0, rho1, mask); kw as make_problem."""
+def dot_batch_create(insts, per_instance=None, **kw) -> Batch:
+    """Batch of problems (objects with D, n, rho0, rho1, mask); kw as make_problem,
+    per_instance: optional list of dicts of further make_problem settings, one per instance."""
     lib = load()
     structs, keep = [], []
-    for inst in insts:
-        p, k = make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, **kw)
+    for i, inst in enumerate(insts):
+        kwi = dict(kw)
+        if per_instance is not None:
+            kwi.update(per_instance[i])
+        p, k = make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, **kwi)
         structs.append(p)
         keep.append(k)
     arr = (dot_problem * len(structs))(*structs)
@@ -682,9 +691,11 @@ class Ctx:
             pass
 
 
-def dot_ctx_create(D, precision, hbm_budget_bytes, max_slots) -> Ctx:
+def dot_ctx_create(D, precision, hbm_budget_bytes, max_slots, device: int = -1) -> Ctx:
+    """Serving context on HIP device `device` (-1: the current one)."""
     h = ctypes.c_void_p()
-    _check(load().dot_ctx_create(int(D), int(precision), int(hbm_budget_bytes), int(max_slots), ctypes.byref(h)))
+    _check(load().dot_ctx_create(int(device), int(D), int(precision), int(hbm_budget_bytes), int(max_slots),
+                                 ctypes.byref(h)))
     return Ctx(h, D, precision)
 
 
@@ -741,6 +752,33 @@ def dot_ctx_stats(ctx: Ctx):
     r = ctypes.c_int64()
     _check(load().dot_ctx_stats(ctx.handle, ctypes.byref(f), ctypes.byref(a), ctypes.byref(r)))
     return f.value, a.value, r.value
+
+
+def dot_ctx_export(ctx: Ctx, ticket: int, stream: int = 0) -> bytes:
+    """Checkpoint of a running request (opaque bytes, see dotsocp.h)."""
+    lib = load()
+    need = ctypes.c_size_t()
+    _check(lib.dot_ctx_export(ctx.handle, ctypes.c_uint64(ticket), None, 0, ctypes.byref(need),
+                              ctypes.c_void_p(stream)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib.dot_ctx_export(ctx.handle, ctypes.c_uint64(ticket), buf, need.value, ctypes.byref(need),
+                              ctypes.c_void_p(stream)))
+    return buf.raw[:need.value]
+
+
+def dot_ctx_import(ctx: Ctx, inst, checkpoint: bytes, levels: int = 0, **kw) -> int:
+    """Queue a request that resumes from a checkpoint of dot_ctx_export; returns its ticket."""
+    p, keep = make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=ctx.precision, **kw)
+    t = ctypes.c_uint64()
+    buf = ctypes.create_string_buffer(bytes(checkpoint), len(checkpoint))
+    _check(load().dot_ctx_import(ctx.handle, ctypes.byref(p), int(levels), buf, len(checkpoint),
+                                 ctypes.byref(t)))
+    ctx.shapes[t.value] = (inst.D, tuple(int(k) for k in inst.n))
+    return t.value
+
+
+def dot_ctx_last_error(ctx: Ctx) -> str:
+    return load().dot_ctx_last_error(ctx.handle).decode(errors="replace")
 
 
 # ---- padded-box marshalling (host side, numpy) -----------------------------

@@ -765,8 +765,9 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
       HIP_OK(hipStreamSynchronize(st));
       if (E.prof) E.prof->collect();
       if (all_stopped()) break;
-      // wall-clock budget: return with the state as it is (resumable)
-      if (time_limit > 0.0 &&
+      // wall-clock budget: return with the state as it is (resumable); a
+      // call that has also done all its iterations is not cut short by it
+      if (time_limit > 0.0 && j < max_iters &&
           std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count() >= time_limit) {
         if (timed_out) *timed_out = true;
         break;
@@ -1766,14 +1767,22 @@ int dot_batch_run(dot_batch* B, void* ws, int32_t max_iters, void* stream, dot_r
   hipStream_t st = (hipStream_t)stream;
   int done = 0;
   bool timed_out = false;
+  const auto t0 = std::chrono::steady_clock::now();
   int rc = dispatch<BatchRunF>(B->precision, B->D, B, ws, (int)max_iters, st, &done, &timed_out);
   if (rc) return rc;
+  const double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   B->it += done;
   if (results)
     for (size_t i = 0; i < B->plans.size(); ++i) {
       const Ctl& c = *reinterpret_cast<const Ctl*>(reinterpret_cast<char*>(B->host_ctl) + i * B->ctl_stride);
       fill_result(c, &results[i]);
-      if (timed_out && !c.stop) results[i].term = DOT_TIMEOUT;
+      // the call ended early at the smallest budget: instances whose own
+      // budget ran out report DOT_TIMEOUT, the other unfinished ones
+      // DOT_RUNNING (their state is resumable as well)
+      if (timed_out && !c.stop) {
+        const double own = B->plans[i]->time_limit;
+        results[i].term = own > 0.0 && elapsed >= own ? DOT_TIMEOUT : DOT_RUNNING;
+      }
     }
   return DOT_OK;
 }
@@ -2326,6 +2335,11 @@ struct Request {
   std::vector<double> rho, m;
   dot_result res{};
   std::chrono::steady_clock::time_point admitted;  // start of the time budget
+  // imported checkpoint (dot_ctx_import): installed at admission instead of
+  // the initial point; empty for a plain submission
+  int ck_level = 0;
+  std::vector<unsigned char> ck_planes;  // the level's state up to its control block
+  Ctl ck_ctl{};
   ~Request() {
     for (auto* P : plans) dot_plan_destroy(P);
   }
@@ -2357,6 +2371,8 @@ struct dot_ctx {
   Prof prof;
   int device = 0;
   int64_t admitted = 0, retired = 0;
+  mutable std::mutex mu;                // every dot_ctx_* call holds it
+  mutable std::string err;              // message of the last failed call on this context
   ~dot_ctx() { delete graphs; }
 };
 
@@ -2501,20 +2517,28 @@ int ctx_admit(dot_ctx* C, hipStream_t st) {
     C->queue.erase(C->queue.begin());
     r->slot = sl;
     r->block = off;
-    r->level = 0;
-    r->plan = r->plans[0];
-    r->off = off + r->lvl_off[0];
+    r->level = r->ck_planes.empty() ? 0 : r->ck_level;
+    r->plan = r->plans[r->level];
+    r->off = off + r->lvl_off[r->level];
     off = r->off;
     r->status = kRunning;
     r->admitted = std::chrono::steady_clock::now();
     C->slots[sl] = r;
     dot_plan* P = r->plan;
-    HIP_OK(hipMemsetAsync(static_cast<char*>(C->arena_mem) + off, 0, P->ctl_offset, st));
-    Ctl h = initial_ctl(P);
-    h.iter_limit = P->max_iter;
-    HIP_OK(hipMemcpyAsync(reinterpret_cast<char*>(C->d_ctl) + (size_t)sl * C->ctl_stride, &h, sizeof(Ctl),
-                          hipMemcpyHostToDevice, st));
+    char* slot_ctl = reinterpret_cast<char*>(C->d_ctl) + (size_t)sl * C->ctl_stride;
+    if (r->ck_planes.empty()) {
+      HIP_OK(hipMemsetAsync(static_cast<char*>(C->arena_mem) + off, 0, P->ctl_offset, st));
+      Ctl h = initial_ctl(P);
+      h.iter_limit = P->max_iter;
+      HIP_OK(hipMemcpyAsync(slot_ctl, &h, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    } else {
+      // the checkpointed iterate continues exactly where it was exported
+      HIP_OK(hipMemcpyAsync(static_cast<char*>(C->arena_mem) + off, r->ck_planes.data(), r->ck_planes.size(),
+                            hipMemcpyHostToDevice, st));
+      HIP_OK(hipMemcpyAsync(slot_ctl, &r->ck_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    }
     HIP_OK(hipStreamSynchronize(st));
+    if (!r->ck_planes.empty()) std::vector<unsigned char>().swap(r->ck_planes);
     C->dirty = true;
     C->admitted += 1;
   }
@@ -2608,6 +2632,8 @@ size_t dot_footprint_bytes(const dot_problem* p) {
 
 void dot_ctx_destroy(dot_ctx* C) {
   if (!C) return;
+  int prev = -1;
+  const bool other = hipGetDevice(&prev) == hipSuccess && prev != C->device && hipSetDevice(C->device) == hipSuccess;
   C->all.clear();  // requests destroy their plans
   (void)hipFree(C->arena_mem);
   (void)hipFree(C->d_ctl);
@@ -2615,9 +2641,15 @@ void dot_ctx_destroy(dot_ctx* C) {
   (void)hipFree(C->d_inst);
   (void)hipFree(C->d_maps);
   delete C;
+  if (other) (void)hipSetDevice(prev);
 }
 
-int dot_ctx_create(int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_t max_slots, dot_ctx** out) {
+}  // extern "C"
+
+namespace {
+
+int ctx_create_impl(int32_t device, int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_t max_slots,
+                    dot_ctx** out) {
   if (!out || D < 1 || D > 3 || (precision != DOT_FP64 && precision != DOT_MIXED) || max_slots < 1 ||
       max_slots > 4096 || hbm_budget_bytes < 4096)
     return fail(DOT_EINVAL, "bad serving context arguments");
@@ -2628,7 +2660,7 @@ int dot_ctx_create(int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_
   C->precision = precision;
   C->max_slots = max_slots;
   C->budget = hbm_budget_bytes;
-  HIP_OK(hipGetDevice(&C->device));
+  C->device = device;
   if (hipMalloc(&C->arena_mem, hbm_budget_bytes) != hipSuccess)
     return fail(DOT_ENOMEM, "cannot reserve the HBM budget");
   C->arena.init(hbm_budget_bytes);
@@ -2646,7 +2678,7 @@ int dot_ctx_create(int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_
   return DOT_OK;
 }
 
-int dot_ctx_submit_ml(dot_ctx* C, const dot_problem* p, int32_t levels, uint64_t* ticket) {
+int ctx_submit_impl(dot_ctx* C, const dot_problem* p, int32_t levels, uint64_t* ticket, Request** made = nullptr) {
   if (!C || !p || !ticket) return fail(DOT_EINVAL, "null argument");
   if (levels < 0 || levels > 8) return fail(DOT_EINVAL, "levels must be in 0..8");
   if (p->D != C->D || p->precision != C->precision) return fail(DOT_EINVAL, "problem D / precision differ from the context");
@@ -2699,16 +2731,13 @@ int dot_ctx_submit_ml(dot_ctx* C, const dot_problem* p, int32_t levels, uint64_t
   r->plan = r->plans[0];
   r->ticket = C->next_ticket++;
   *ticket = r->ticket;
+  if (made) *made = r.get();
   C->queue.push_back(r.get());
   C->all.push_back(std::move(r));
   return DOT_OK;
 }
 
-int dot_ctx_submit(dot_ctx* C, const dot_problem* p, uint64_t* ticket) {
-  return dot_ctx_submit_ml(C, p, 0, ticket);
-}
-
-int dot_ctx_step(dot_ctx* C, int32_t iters, void* stream, int32_t* n_active, int32_t* n_queued) {
+int ctx_step_impl(dot_ctx* C, int32_t iters, void* stream, int32_t* n_active, int32_t* n_queued) {
   if (!C || iters < 0 || iters % kGraphIters != 0) return fail(DOT_EINVAL, "iters must be a multiple of 10");
   hipStream_t st = (hipStream_t)stream;
   int rc = ctx_admit(C, st);
@@ -2728,7 +2757,7 @@ int dot_ctx_step(dot_ctx* C, int32_t iters, void* stream, int32_t* n_active, int
   return DOT_OK;
 }
 
-int dot_ctx_poll(dot_ctx* C, uint64_t ticket, int32_t* status) {
+int ctx_poll_impl(dot_ctx* C, uint64_t ticket, int32_t* status) {
   if (!C || !status) return fail(DOT_EINVAL, "null argument");
   Request* r = find_req(C, ticket);
   if (!r) return fail(DOT_EINVAL, "unknown ticket");
@@ -2736,7 +2765,7 @@ int dot_ctx_poll(dot_ctx* C, uint64_t ticket, int32_t* status) {
   return DOT_OK;
 }
 
-int dot_ctx_fetch(dot_ctx* C, uint64_t ticket, double* rho_out, double* m_out, dot_result* res) {
+int ctx_fetch_impl(dot_ctx* C, uint64_t ticket, double* rho_out, double* m_out, dot_result* res) {
   if (!C) return fail(DOT_EINVAL, "null argument");
   for (auto it = C->all.begin(); it != C->all.end(); ++it) {
     Request* r = it->get();
@@ -2751,12 +2780,192 @@ int dot_ctx_fetch(dot_ctx* C, uint64_t ticket, double* rho_out, double* m_out, d
   return fail(DOT_EINVAL, "unknown ticket");
 }
 
-int dot_ctx_stats(const dot_ctx* C, size_t* free_bytes, int64_t* admitted, int64_t* retired) {
+int ctx_stats_impl(const dot_ctx* C, size_t* free_bytes, int64_t* admitted, int64_t* retired) {
   if (!C) return fail(DOT_EINVAL, "null context");
   if (free_bytes) *free_bytes = C->arena.free_bytes();
   if (admitted) *admitted = C->admitted;
   if (retired) *retired = C->retired;
   return DOT_OK;
 }
+
+
+// ---- checkpoint of a running request --------------------------------------
+// Layout of a checkpoint (host bytes): CkHeader, the state of the request's
+// current level up to its control block (every plane: phi, transform
+// scratch, q, q_new, alpha, beta, W), then the control block.
+constexpr uint64_t kCkMagic = 0x31544B4354534F44ull;  // "DOSTCKT1"
+struct CkHeader {
+  uint64_t magic;
+  int32_t D, precision, levels, level;
+  int32_t n[4];           // target grid of the request
+  int32_t level_n[4];     // grid of the exported level
+  uint64_t plane_bytes;   // state bytes before the control block
+  uint64_t ctl_bytes;
+};
+
+int ctx_export_impl(dot_ctx* C, uint64_t ticket, void* buf, size_t cap, size_t* bytes, hipStream_t st) {
+  Request* r = find_req(C, ticket);
+  if (!r) return fail(DOT_EINVAL, "unknown ticket");
+  if (r->status != kRunning) return fail(DOT_EINVAL, "only a running request can be exported");
+  dot_plan* P = r->plan;
+  const size_t need = sizeof(CkHeader) + P->ctl_offset + sizeof(Ctl);
+  if (bytes) *bytes = need;
+  if (!buf) return DOT_OK;
+  if (cap < need) return fail(DOT_EINVAL, "checkpoint buffer too small");
+  CkHeader h{};
+  h.magic = kCkMagic;
+  h.D = C->D;
+  h.precision = C->precision;
+  h.levels = (int32_t)r->plans.size() - 1;
+  h.level = r->level;
+  for (int d = 0; d < 4; ++d) {
+    h.n[d] = r->plans.back()->n[d];
+    h.level_n[d] = P->n[d];
+  }
+  h.plane_bytes = P->ctl_offset;
+  h.ctl_bytes = sizeof(Ctl);
+  unsigned char* out = static_cast<unsigned char*>(buf);
+  std::memcpy(out, &h, sizeof(h));
+  HIP_OK(hipMemcpyAsync(out + sizeof(h), static_cast<char*>(C->arena_mem) + r->off, P->ctl_offset,
+                        hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(out + sizeof(h) + P->ctl_offset,
+                        reinterpret_cast<char*>(C->d_ctl) + (size_t)r->slot * C->ctl_stride, sizeof(Ctl),
+                        hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  return DOT_OK;
+}
+
+int ctx_import_impl(dot_ctx* C, const dot_problem* p, int32_t levels, const void* buf, size_t bytes,
+                    uint64_t* ticket) {
+  if (!buf || bytes < sizeof(CkHeader)) return fail(DOT_EINVAL, "checkpoint too short");
+  CkHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (h.magic != kCkMagic) return fail(DOT_EINVAL, "not a serving checkpoint");
+  if (h.D != C->D || h.precision != C->precision) return fail(DOT_EINVAL, "checkpoint D / precision differ from the context");
+  if (h.levels != levels || h.level < 0 || h.level > levels)
+    return fail(DOT_EINVAL, "checkpoint levels differ from the request's");
+  for (int d = 0; d <= p->D && d < 4; ++d)
+    if (p->n[d] != h.n[d]) return fail(DOT_EINVAL, "checkpoint grid differs from the problem's");
+  if (h.ctl_bytes != sizeof(Ctl) || bytes != sizeof(CkHeader) + h.plane_bytes + h.ctl_bytes)
+    return fail(DOT_EINVAL, "checkpoint size does not match its header");
+  Request* r = nullptr;
+  uint64_t t = 0;
+  int rc = ctx_submit_impl(C, p, levels, &t, &r);
+  if (rc) return rc;
+  dot_plan* P = r->plans[h.level];
+  bool same = P->ctl_offset == h.plane_bytes;
+  for (int d = 0; d < 4; ++d) same = same && P->n[d] == h.level_n[d];
+  if (!same) {
+    // undo the submission: the request was queued last
+    C->queue.pop_back();
+    C->all.pop_back();
+    return fail(DOT_EINVAL, "checkpoint state layout differs from the problem's");
+  }
+  const unsigned char* in = static_cast<const unsigned char*>(buf) + sizeof(CkHeader);
+  r->ck_level = h.level;
+  r->ck_planes.assign(in, in + h.plane_bytes);
+  std::memcpy(&r->ck_ctl, in + h.plane_bytes, sizeof(Ctl));
+  *ticket = t;
+  return DOT_OK;
+}
+
+// Makes the context's device current for one call and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  int dev = -1;
+  int rc = DOT_OK;
+  explicit DeviceGuard(int device) : dev(device) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      rc = fail(DOT_EDEVICE, "hipGetDevice failed");
+      prev = -1;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) rc = fail(DOT_EDEVICE, "cannot select the context's device");
+  }
+  ~DeviceGuard() {
+    if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+  }
+};
+
+// Keeps the message of a failed call in the context.
+int ctx_ret(const dot_ctx* C, int rc) {
+  if (rc) C->err = g_err;
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dot_ctx_create(int32_t device, int32_t D, int32_t precision, size_t hbm_budget_bytes, int32_t max_slots,
+                   dot_ctx** out) {
+  if (!out) return fail(DOT_EINVAL, "null output pointer");
+  *out = nullptr;
+  // host-side checks first (no device call before the arguments are valid)
+  if (D < 1 || D > 3 || (precision != DOT_FP64 && precision != DOT_MIXED) || max_slots < 1 || max_slots > 4096 ||
+      hbm_budget_bytes < 4096)
+    return fail(DOT_EINVAL, "bad serving context arguments");
+  int count = 0;
+  if (device < -1) return fail(DOT_EINVAL, "device must be >= -1");
+  if (device == -1) {
+    HIP_OK(hipGetDevice(&device));
+  } else {
+    HIP_OK(hipGetDeviceCount(&count));
+    if (device >= count) return fail(DOT_EINVAL, "no such device: " + std::to_string(device));
+  }
+  DeviceGuard g(device);
+  if (g.rc) return g.rc;
+  return ctx_create_impl(device, D, precision, hbm_budget_bytes, max_slots, out);
+}
+
+#define CTX_ENTER(C)                            \
+  if (!(C)) return fail(DOT_EINVAL, "null context"); \
+  std::lock_guard<std::mutex> lk_((C)->mu);     \
+  DeviceGuard dg_((C)->device);                 \
+  if (dg_.rc) return ctx_ret((C), dg_.rc)
+
+int dot_ctx_submit_ml(dot_ctx* C, const dot_problem* p, int32_t levels, uint64_t* ticket) {
+  CTX_ENTER(C);
+  return ctx_ret(C, ctx_submit_impl(C, p, levels, ticket));
+}
+
+int dot_ctx_submit(dot_ctx* C, const dot_problem* p, uint64_t* ticket) {
+  CTX_ENTER(C);
+  return ctx_ret(C, ctx_submit_impl(C, p, 0, ticket));
+}
+
+int dot_ctx_step(dot_ctx* C, int32_t iters, void* stream, int32_t* n_active, int32_t* n_queued) {
+  CTX_ENTER(C);
+  return ctx_ret(C, ctx_step_impl(C, iters, stream, n_active, n_queued));
+}
+
+int dot_ctx_poll(dot_ctx* C, uint64_t ticket, int32_t* status) {
+  CTX_ENTER(C);
+  return ctx_ret(C, ctx_poll_impl(C, ticket, status));
+}
+
+int dot_ctx_fetch(dot_ctx* C, uint64_t ticket, double* rho_out, double* m_out, dot_result* res) {
+  CTX_ENTER(C);
+  return ctx_ret(C, ctx_fetch_impl(C, ticket, rho_out, m_out, res));
+}
+
+int dot_ctx_stats(const dot_ctx* C, size_t* free_bytes, int64_t* admitted, int64_t* retired) {
+  CTX_ENTER(C);
+  return ctx_ret(C, ctx_stats_impl(C, free_bytes, admitted, retired));
+}
+
+int dot_ctx_export(dot_ctx* C, uint64_t ticket, void* buf, size_t cap, size_t* bytes, void* stream) {
+  CTX_ENTER(C);
+  return ctx_ret(C, ctx_export_impl(C, ticket, buf, cap, bytes, (hipStream_t)stream));
+}
+
+int dot_ctx_import(dot_ctx* C, const dot_problem* p, int32_t levels, const void* buf, size_t bytes,
+                   uint64_t* ticket) {
+  CTX_ENTER(C);
+  if (!p || !ticket) return ctx_ret(C, fail(DOT_EINVAL, "null argument"));
+  return ctx_ret(C, ctx_import_impl(C, p, levels, buf, bytes, ticket));
+}
+
+const char* dot_ctx_last_error(const dot_ctx* C) { return C ? C->err.c_str() : ""; }
 
 }  // extern "C"

@@ -34,10 +34,10 @@ class Request:
 class _Lane:
     """One context, its stream and the thread that steps it."""
 
-    def __init__(self, D, precision, budget, slots, step_iters, tol, max_iter, keep_solution):
+    def __init__(self, D, precision, budget, slots, step_iters, tol, max_iter, keep_solution, device):
         import torch
         self.D = D
-        self.ctx = B.dot_ctx_create(D, precision, budget, slots)
+        self.ctx = B.dot_ctx_create(D, precision, budget, slots, device=device)
         self.stream = torch.cuda.Stream()  # default priority
         self.step_iters = step_iters
         self.tol = tol
@@ -101,13 +101,14 @@ class Server:
     budgets / slots: per spatial dimension D, the device bytes reserved for
     iterate state and the number of concurrently running instances.
     step_iters: iterations per context step (a multiple of 10); requests are
-    admitted and retired between steps."""
+    admitted and retired between steps. device: HIP device of the contexts
+    (-1: the current one)."""
 
     def __init__(self, precision=B.DOT_MIXED, budgets=None, slots=None, step_iters=40, tol=1e-6,
-                 max_iter=40000, keep_solution=False):
+                 max_iter=40000, keep_solution=False, device=-1):
         budgets = budgets or {2: 64 << 30, 3: 24 << 30}
         slots = slots or {2: 128, 3: 16}
-        self.lanes = {D: _Lane(D, precision, budgets[D], slots[D], step_iters, tol, max_iter, keep_solution)
+        self.lanes = {D: _Lane(D, precision, budgets[D], slots[D], step_iters, tol, max_iter, keep_solution, device)
                       for D in budgets}
         for ln in self.lanes.values():
             ln.thread.start()

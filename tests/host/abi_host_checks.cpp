@@ -167,7 +167,7 @@ static void check_footprint_and_null_handles() {
   dot_problem pair[2] = {a, base_problem(f, 1, small, false)};
   expect(dot_batch_create(pair, 2, &B) == DOT_EINVAL && B == nullptr, "batch of different D");
   dot_ctx* C = nullptr;
-  expect(dot_ctx_create(5, DOT_FP64, 1 << 20, 4, &C) == DOT_EINVAL, "context with D = 5");
+  expect(dot_ctx_create(-1, 5, DOT_FP64, 1 << 20, 4, &C) == DOT_EINVAL, "context with D = 5");
 }
 
 int main() {

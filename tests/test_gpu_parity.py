@@ -247,3 +247,33 @@ def test_graph_replay_equals_plain_launches(name, iters):
         s.run(iters - 33)
         states.append(s.raw().copy())
     assert np.array_equal(states[0], states[1])
+
+
+def test_headline_solve_matches_the_converged_oracle():
+    """The headline workload (2D 32x64^2, three-component mixtures, FP64, default
+    settings) solved to eta_dot <= 1e-6 on the device against the oracle's
+    converged solve of the same instance (tests/golden/config2_converged.json,
+    written by make_config2_golden.py from oracle/ only): the same iteration
+    and check counts and sigma sequence, objective and dual objective within
+    1e-8 relative, rho and m within 1e-6 at the 4096 stored positions each."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "config2_converged.json")))
+    inst = dotgen.config2_instance()
+    assert inst.label == gold["instance"] and list(inst.n) == gold["n"]
+    print("[case] headline solve 2D 32x64x64 FP64 to 1e-6 vs the converged oracle", flush=True)
+    plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=1e-6, max_iter=100000)
+    s = G.GpuState(plan)
+    s.reset()
+    r = s.run(100000)
+    assert B.TERM_NAMES[r.term] == "converged"
+    assert r.iters == gold["iters"] and r.checks == gold["checks"]
+    assert r.sigma_changes == gold["sigma_changes"]
+    assert abs(r.sigma - gold["sigma_final"]) <= 1e-12 * gold["sigma_final"]
+    assert abs(r.objective - gold["objective"]) <= 1e-8 * abs(gold["objective"])
+    assert abs(r.dual_objective - gold["dual_objective"]) <= 1e-8 * abs(gold["dual_objective"])
+    assert abs(r.eta_dot - gold["residuals"]["eta_dot"]) <= 1e-6 * gold["residuals"]["eta_dot"]
+    rho, m = s.extract()
+    mflat = np.concatenate([a.ravel() for a in m])
+    assert np.max(np.abs(rho.ravel()[gold["rho_index"]] - np.array(gold["rho_value"]))) <= 1e-6
+    assert np.max(np.abs(mflat[gold["m_index"]] - np.array(gold["m_value"]))) <= 1e-6

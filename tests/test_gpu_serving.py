@@ -229,3 +229,98 @@ def test_multilevel_request_rejects_odd_grids():
     with pytest.raises(B.DotError):
         B.dot_ctx_submit_ml(ctx, dotgen.tiny_instance(2, (8, 16, 16), seed=116), 9)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(B.DOT_FP64, 1e-7), (B.DOT_MIXED, 1e-6)])
+def test_served_results_match_the_oracle(prec, tol):
+    """Requests served with staggered arrivals against the FP64 oracle's
+    solve of the same problem with the same settings (O.solve). FP64: the
+    same iteration count and check count, objective within 1e-8 relative,
+    rho and m within 1e-6 in max norm. Mixed precision: converged to the same
+    tolerance, objective within 1e-5 relative of the oracle's."""
+    from oracle import dot_oracle as O
+    insts = _requests()[:4]
+    print(f"[case] serving vs oracle {len(insts)} requests precision={prec} tol={tol}", flush=True)
+    ctx = B.dot_ctx_create(2, prec, 1 << 26, 3)
+    done, _ = _serve(ctx, insts, [0, 0, 5, 11], tol, 40000)
+    for i, inst in enumerate(insts):
+        r, rho, m = done[i]
+        P = O.make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask)
+        ref = O.solve(P, tol=tol, max_iter=40000)
+        assert ref.converged and B.TERM_NAMES[r.term] == "converged", i
+        assert r.eta_dot <= tol
+        if prec == B.DOT_FP64:
+            assert r.iters == ref.iters and r.checks == len(ref.history), (i, r.iters, ref.iters)
+            assert abs(r.objective - ref.objective) <= 1e-8 * abs(ref.objective), i
+            assert np.max(np.abs(rho - ref.state.alpha[0])) <= 1e-6, i
+            for a, b in zip(m, ref.state.alpha[1:]):
+                assert np.max(np.abs(a - b)) <= 1e-6, i
+        else:
+            assert abs(r.objective - ref.objective) <= 1e-5 * abs(ref.objective), (i, r.objective, ref.objective)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
+def test_checkpoint_of_a_running_request_resumes_bitwise(prec):
+    """dot_ctx_export mid-run, dot_ctx_import into a fresh context: the resumed
+    request finishes with bitwise the result of an uninterrupted one (plain
+    and multilevel requests; the exporting context keeps running too)."""
+    insts = [dotgen.tiny_instance(2, (8, 20, 24), seed=111, floor=0.0, masked=True),
+             dotgen.tiny_instance(2, (12, 32, 16), seed=112, floor=0.0, n_comp=3)]
+    levels = [0, 1]
+    tol = 1e-7 if prec == B.DOT_FP64 else 1e-5
+    st = G.stream_handle()
+    print(f"[case] checkpoint export/import precision={prec}", flush=True)
+    ctx = B.dot_ctx_create(2, prec, 1 << 26, 4)
+    tickets = [B.dot_ctx_submit_ml(ctx, inst, lv, tol=tol, max_iter=40000) for inst, lv in zip(insts, levels)]
+    for _ in range(7):
+        B.dot_ctx_step(ctx, 20, st)
+    assert all(B.dot_ctx_poll(ctx, t) == B.CTX_RUNNING for t in tickets)
+    cks = [B.dot_ctx_export(ctx, t, st) for t in tickets]
+    # a fresh context resumes both; the first context runs them to the end uninterrupted
+    ctx2 = B.dot_ctx_create(2, prec, 1 << 26, 4, device=0)
+    tickets2 = [B.dot_ctx_import(ctx2, inst, ck, levels=lv, tol=tol, max_iter=40000)
+                for inst, ck, lv in zip(insts, cks, levels)]
+    for c, ts in ((ctx, tickets), (ctx2, tickets2)):
+        for _ in range(4000):
+            B.dot_ctx_step(c, 20, st)
+            if all(B.dot_ctx_poll(c, t) == B.CTX_DONE for t in ts):
+                break
+    for t, t2 in zip(tickets, tickets2):
+        r, rho, m = B.dot_ctx_fetch(ctx, t)
+        r2, rho2, m2 = B.dot_ctx_fetch(ctx2, t2)
+        assert B.TERM_NAMES[r.term] == "converged"
+        _same(r2, r)
+        assert np.array_equal(rho2, rho)
+        for a, b in zip(m2, m):
+            assert np.array_equal(a, b)
+    ctx.close()
+    ctx2.close()
+
+
+def test_checkpoint_errors_and_context_messages():
+    st = G.stream_handle()
+    ctx = B.dot_ctx_create(2, B.DOT_FP64, 1 << 24, 2)
+    inst = dotgen.tiny_instance(2, (6, 10, 12), seed=113, floor=0.05)
+    t = B.dot_ctx_submit(ctx, inst, tol=-1.0, max_iter=200)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_export(ctx, t, st)  # still queued
+    assert "running" in B.dot_ctx_last_error(ctx)
+    B.dot_ctx_step(ctx, 20, st)
+    ck = B.dot_ctx_export(ctx, t, st)
+    other = dotgen.tiny_instance(2, (6, 10, 14), seed=114, floor=0.05)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_import(ctx, other, ck)  # other grid
+    assert "grid" in B.dot_ctx_last_error(ctx)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_import(ctx, inst, ck[:-8])  # truncated
+    with pytest.raises(B.DotError):
+        B.dot_ctx_import(ctx, inst, ck, levels=1)
+    ctx3 = B.dot_ctx_create(2, B.DOT_MIXED, 1 << 24, 2)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_import(ctx3, inst, ck)  # other precision
+    assert "precision" in B.dot_ctx_last_error(ctx3)
+    with pytest.raises(B.DotError):
+        B.dot_ctx_create(2, B.DOT_FP64, 1 << 24, 2, device=4096)
+    ctx.close()
+    ctx3.close()

@@ -188,3 +188,24 @@ def test_sigma_history_matches_the_oracle_decisions(name, D, n):
     B.dot_batch_run(batch, ws.data_ptr(), iters, st)
     hb, cb = B.dot_batch_sigma_history(batch, ws.data_ptr(), 1, 32, st)
     assert cb == count and hb == hist
+
+
+def test_batch_with_mixed_time_budgets_reports_each_instance():
+    """One batch with budgets 0 (none) and 1e-6 s: the call ends at the first
+    poll (40 iterations); the instance whose budget ran out reports DOT_TIMEOUT,
+    the one without a budget DOT_RUNNING; a further run continues both, and a
+    run whose iteration count ends at the same poll as the budget reports the
+    iteration cap of the call, not a timeout."""
+    insts = [dotgen.config2_instance(), dotgen.tiny_instance(2, (8, 20, 24), seed=97, floor=0.02)]
+    batch = B.dot_batch_create(insts, per_instance=[{"time_limit_s": 0.0}, {"time_limit_s": 1e-6}],
+                               tol=1e-6, max_iter=100000)
+    torch = G.torch_mod()
+    ws = torch.zeros(int(batch.workspace_bytes), dtype=torch.uint8, device="cuda")
+    st = G.stream_handle()
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    res = B.dot_batch_run(batch, ws.data_ptr(), 100000, st)
+    assert [x.iters for x in res] == [40, 40]
+    assert [B.TERM_NAMES[x.term] for x in res] == ["running", "timeout"]
+    res = B.dot_batch_run(batch, ws.data_ptr(), 40, st)
+    assert [x.iters for x in res] == [80, 80]
+    assert [B.TERM_NAMES[x.term] for x in res] == ["maxiter", "maxiter"]
