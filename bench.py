@@ -32,7 +32,8 @@ from paper_2505_05424_amd import perfmodel as PM  # noqa: E402
 
 TOL = 1e-6
 MAX_ITER = 100000
-BATCH_MAX_ITER = 40000  # cap per instance in the batched section
+BATCH_MAX_ITER = 60000   # mixed-precision batch iterations before the FP64 finish
+FINISH_MAX_ITER = 100000  # cap per instance in all (batch + FP64 finish; plain FP64 solves)
 
 
 def log(msg):
@@ -49,37 +50,108 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(inst, iters_per_solve, budget_s=15.0):
-    """The FP64 oracle as it stands, timed on this host on a bounded sample:
-    consecutive PALM iterations of the same instance from the zero start for
-    about `budget_s` seconds; solves/s = iterations/s / iterations per solve."""
+# The paper's own CPU figures (MATLAB with a C++ projection on an Intel Core
+# i9-9900KF, 8 cores, 3.6 GHz; Table 4, single-level inpALM, tolerance 1e-4),
+# as seconds per iteration = total time / iterations over its rows. Context only.
+PAPER_CPU_S_PER_ITER = {"(32,128,128)": [0.105, 0.120], "(64,256,256)": [0.829, 0.921]}
+
+
+def cpu_baseline(iters_per_solve_cfg2, cfg3_iters=3):
+    """The FP64 oracle as it stands, timed on this host: the cosine transforms
+    (scipy.fft) on all cores (workers = os.cpu_count()) and on one core (the
+    rest of the oracle is single-threaded numpy either way). Per leg: ms per
+    iteration over a 50-iteration block on the headline 2D 32x64^2 instance
+    (after one warm-up iteration; residuals every 5 as in a solve) and over a
+    `cfg3_iters`-iteration block on 2D 64x256^2 (a full 50-iteration block
+    would take minutes); a full solve of the 1D 16x32 instance to
+    eta_dot <= 1e-8. value = headline solves/s with all cores = 1 / (ms per
+    iteration x the iterations a solve takes)."""
+    import scipy.fft as sfft
     from oracle import dot_oracle as O
-    P = O.make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask)
-    S = O.zero_state(P)
-    S = O.iterate(P, S)  # first call warms numpy/scipy
-    n = 0
-    t0 = time.perf_counter()
-    while True:
-        S = O.iterate(P, S)
-        n += 1
-        if S.k % 5 == 0:
-            O.residuals(P, S.phi, S.z, S.q, S.alpha, S.beta)
-        el = time.perf_counter() - t0
-        if el >= budget_s and n >= 10:
-            break
-    its = n / el
+    ncpu = os.cpu_count() or 1
+
+    def ms_per_iter(inst, n_iter, workers):
+        P = O.make_problem(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask)
+        S = O.zero_state(P)
+        with sfft.set_workers(workers):
+            S = O.iterate(P, S)
+            t0 = time.perf_counter()
+            for _ in range(n_iter):
+                S = O.iterate(P, S)
+                if S.k % 5 == 0:
+                    O.residuals(P, S.phi, S.z, S.q, S.alpha, S.beta)
+            return 1e3 * (time.perf_counter() - t0) / n_iter
+
+    c2, c3 = dotgen.config2_instance(), dotgen.config3_instance()
+    legs = {}
+    for workers, name in ((ncpu, "all_cores"), (1, "one_core")):
+        log(f"cpu baseline: {name}")
+        legs[name] = {"threads": workers,
+                      "2d_32x64x64_ms_per_iter_50": ms_per_iter(c2, 50, workers),
+                      f"2d_64x256x256_ms_per_iter_{cfg3_iters}": ms_per_iter(c3, cfg3_iters, workers)}
+    c1 = dotgen.config1_instance()
+    P1 = O.make_problem(c1.D, c1.n, c1.rho0, c1.rho1, c1.mask)
+    with sfft.set_workers(1):
+        r1 = O.solve(P1, tol=1e-8, max_iter=200000)
+    ms_all = legs["all_cores"]["2d_32x64x64_ms_per_iter_50"]
     return {
-        "value": its / iters_per_solve,
+        "value": 1e3 / ms_all / iters_per_solve_cfg2,
         "unit": "solves/s",
-        "cores": 1,
+        "cores": ncpu,
         "kind": "oracle",
-        "sample": (f"{n} consecutive oracle iterations (numpy/scipy FP64, one thread) of the "
-                   f"{inst.n[0]}x{inst.n[1]}x{inst.n[2]} instance in {el:.1f} s = {its:.2f} it/s, "
-                   f"divided by the {iters_per_solve} iterations one solve takes"),
-        "iters_per_s": its,
+        "sample": (f"50 consecutive oracle iterations (numpy/scipy FP64) of the 32x64x64 headline instance with "
+                   f"the transforms on {ncpu} threads: {ms_all:.1f} ms per iteration, times the "
+                   f"{iters_per_solve_cfg2} iterations one solve takes"),
+        "legs": legs,
+        "config1_full_solve": {"workload": "1d-16x32, tol 1e-8", "iters": r1.iters, "converged": r1.converged,
+                               "seconds": r1.seconds, "objective": r1.objective},
+        "paper_table4_s_per_iter_i9_9900kf_8_cores": PAPER_CPU_S_PER_ITER,
         "cpu_model": cpu_model(),
-        "host_cpus": os.cpu_count(),
+        "host_cpus": ncpu,
     }
+
+
+def headline_error(rho, m, r):
+    """The headline solve against the oracle's converged solve of the same
+    instance (tests/golden/config2_converged.json, written from the oracle):
+    iteration counts, relative objective error, max |rho|, |m| errors at the
+    stored positions."""
+    path = os.path.join(ROOT, "tests", "golden", "config2_converged.json")
+    try:
+        gold = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    mflat = np.concatenate([a.ravel() for a in m])
+    return {"reference": "tests/golden/config2_converged.json (FP64 oracle, same settings)",
+            "iters": r.iters, "oracle_iters": gold["iters"],
+            "objective_rel_err": abs(r.objective - gold["objective"]) / abs(gold["objective"]),
+            "dual_objective_rel_err": abs(r.dual_objective - gold["dual_objective"]) / abs(gold["dual_objective"]),
+            "rho_max_abs_err_sampled": float(np.max(np.abs(rho.ravel()[gold["rho_index"]] - np.array(gold["rho_value"])))),
+            "m_max_abs_err_sampled": float(np.max(np.abs(mflat[gold["m_index"]] - np.array(gold["m_value"])))),
+            "samples": len(gold["rho_index"]) + len(gold["m_index"])}
+
+
+def mixed_vs_fp64_config3(torch, st):
+    """2D 64x256^2 (5-component mixtures) solved to eta_dot <= 1e-6 in FP64 and
+    in mixed precision: iterations, seconds, relative objective difference."""
+    inst = dotgen.config3_instance()
+    out = {"workload": "2d-64x256x256-gaussmix5, tol 1e-6"}
+    for prec, name in ((B.DOT_FP64, "fp64"), (B.DOT_MIXED, "mixed")):
+        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=TOL, max_iter=MAX_ITER,
+                                 precision=prec)
+        buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+        el, r = time_solves(plan, buf.data_ptr(), st, 1, torch)
+        rho, _ = B.dot_extract(plan, buf.data_ptr(), st)
+        mass = rho.reshape(rho.shape[0], -1).sum(1) / (inst.n[1] * inst.n[2])
+        out[name] = {"iters": r[0].iters, "term": B.TERM_NAMES[r[0].term], "seconds": el,
+                     "eta_dot": r[0].eta_dot, "objective": r[0].objective,
+                     "ms_per_iter": 1e3 * el / r[0].iters, "slice_mass_max_err": float(np.max(np.abs(mass - 1)))}
+        del buf
+        plan.close()
+    out["objective_rel_diff_mixed_vs_fp64"] = (abs(out["mixed"]["objective"] - out["fp64"]["objective"])
+                                               / abs(out["fp64"]["objective"]))
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
 
 
 def solve_plain(plan, ptr, st, cap=MAX_ITER):
@@ -87,10 +159,10 @@ def solve_plain(plan, ptr, st, cap=MAX_ITER):
     return B.dot_run(plan, ptr, cap, st)
 
 
-def time_solves(plan, ptr, st, k, torch):
+def time_solves(plan, ptr, st, k, torch, cap=MAX_ITER):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [solve_plain(plan, ptr, st) for _ in range(k)]
+    res = [solve_plain(plan, ptr, st, cap) for _ in range(k)]
     torch.cuda.synchronize()
     return time.perf_counter() - t0, res
 
@@ -256,13 +328,22 @@ def large_section(torch, st, iters=40, max_solve_s=60.0):
     return out
 
 
-def batched_section(torch, st, count, sample, seed=4000):
-    """Config-4-like batch: `count` instances (grid sides from {32..128}, n0
-    from {16, 32, 64}, half masked), mixed precision, one launch per kernel
-    for all instances, to eta_dot <= 1e-6; plus `sample` of the same
-    instances solved one at a time in FP64 and in mixed precision."""
+def _converged(r):
+    return B.TERM_NAMES[r.term] == "converged" and r.eta_dot <= TOL
+
+
+def batched_section(torch, st, count, seed=4000):
+    """Config-4 batch: `count` instances (grid sides from {32..128}, n0 from
+    {16, 32, 64}, half masked), mixed precision, one launch per kernel for all
+    instances, to eta_dot <= 1e-6 with a cap of BATCH_MAX_ITER iterations;
+    members still above the tolerance at the cap (masked instances that need
+    more iterations, or that level off at their FP32 storage floor) are then
+    promoted to FP64 (dot_batch_promote) and finished alone up to
+    FINISH_MAX_ITER iterations in all. Against it: the same `count` instances
+    solved one at a time in plain FP64 (cap FINISH_MAX_ITER). Only results
+    with eta_dot <= 1e-6 count as solves."""
     insts = dotgen.config4_instances(count, seed=seed)
-    batch = B.dot_batch_create(insts, tol=TOL, max_iter=BATCH_MAX_ITER, precision=B.DOT_MIXED)
+    batch = B.dot_batch_create(insts, tol=TOL, max_iter=FINISH_MAX_ITER, precision=B.DOT_MIXED)
     ws = torch.zeros(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
     # transform schedule of this batch's launches, measured before the timed run
     t0 = time.perf_counter()
@@ -276,13 +357,35 @@ def batched_section(torch, st, count, sample, seed=4000):
     while done < BATCH_MAX_ITER:
         res = B.dot_batch_run(batch, ws.data_ptr(), 5000, st)
         done += 5000
-        conv = sum(1 for r in res if B.TERM_NAMES[r.term] == "converged")
+        conv = sum(1 for r in res if _converged(r))
         log(f"batched: {done} iterations, {conv}/{count} converged, {time.perf_counter() - t0:.1f} s")
         if conv == count:
             break
     torch.cuda.synchronize()
+    el_batch = time.perf_counter() - t0
+    conv_batch = sum(1 for r in res if _converged(r))
+    # FP64 finish of the members still running (inside the timed region)
+    finished = {}
+    for i, r in enumerate(res):
+        if _converged(r):
+            continue
+        inst = insts[i]
+        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=TOL,
+                                 max_iter=FINISH_MAX_ITER)
+        buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+        B.dot_batch_promote(batch, ws.data_ptr(), i, plan, buf.data_ptr(), st)
+        rf = B.dot_run(plan, buf.data_ptr(), FINISH_MAX_ITER - r.iters, st)
+        finished[inst.label] = {"mixed_iters": r.iters, "mixed_eta_dot": r.eta_dot, "fp64_iters_after": rf.iters - r.iters,
+                                "eta_dot": rf.eta_dot, "term": B.TERM_NAMES[rf.term],
+                                "objective_change_rel": abs(rf.objective - r.objective) / abs(rf.objective)}
+        res[i] = rf
+        log(f"batched: fp64 finish {inst.label}: {r.iters} mixed + {rf.iters - r.iters} fp64 iterations, "
+            f"eta {rf.eta_dot:.2e}")
+        del buf
+        plan.close()
+    torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    conv = sum(1 for r in res if B.TERM_NAMES[r.term] == "converged")
+    conv = sum(1 for r in res if _converged(r))
     inst_iters = sum(r.iters for r in res)
     nodes = sum(int(np.prod([k + 1 for k in i.n])) for i in insts)
     # dominant kernel of the batch, timed with events in a second run
@@ -292,17 +395,23 @@ def batched_section(torch, st, count, sample, seed=4000):
     B.dot_batch_run(batch, ws.data_ptr(), 400, st)
     ms, cnt = B.dot_batch_profile_read(batch)
     B.dot_batch_profile_select(batch, -1)
+    del ws
+    batch.close()
     kb = sum(PM.kernel_bytes(i.D, i.n, 4)["beta"] for i in insts)
     avg_us = 1e3 * ms / max(cnt, 1)
     out = {
         "workload": f"{count} 2D instances, sides {{32,48,64,96,128}}, n0 {{16,32,64}}, half masked, mixed precision",
         "instances": count,
         "converged": conv,
+        "converged_in_batch": conv_batch,
+        "batch_iteration_cap": BATCH_MAX_ITER,
+        "finished_in_fp64": finished,
+        "total_iteration_cap": FINISH_MAX_ITER,
         "seconds": el,
+        "seconds_batch_part": el_batch,
         "solves_per_s": conv / el,
         "instance_iters_per_s": inst_iters / el,
         "max_iters": max(r.iters for r in res),
-        "iteration_cap": BATCH_MAX_ITER,
         "mean_iters": inst_iters / count,
         "nodes_total": nodes,
         "transform_schedule": sched,
@@ -311,34 +420,23 @@ def batched_section(torch, st, count, sample, seed=4000):
                         "achieved_GBs": kb / (avg_us * 1e-6) / 1e9,
                         "frac_of_hbm_peak": kb / (avg_us * 1e-6) / 1e9 / PM.HBM_PEAK_GBS},
     }
-    plain = {}
-    for prec, label in ((B.DOT_FP64, "fp64"), (B.DOT_MIXED, "mixed")):
-        t_tot, its = 0.0, 0
-        for inst in insts[:sample]:
-            log(f"plain {label}: {inst.label}")
-            plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=TOL,
-                                     max_iter=BATCH_MAX_ITER, precision=prec)
-            buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
-            el1, r = time_solves(plan, buf.data_ptr(), st, 1, torch)
-            t_tot += el1
-            its += r[0].iters
-            plan.close()
-        plain[label] = {"instances": sample, "seconds": t_tot, "solves_per_s": sample / t_tot,
-                        "iters_per_s": its / t_tot}
-    out["plain_one_at_a_time_sample"] = plain
-    # the same sample inside a batch of its own, for a like-for-like ratio
-    log("batched sample")
-    sub = B.dot_batch_create(insts[:sample], tol=TOL, max_iter=BATCH_MAX_ITER, precision=B.DOT_MIXED)
-    ws2 = torch.zeros(sub.workspace_bytes, dtype=torch.uint8, device="cuda")
-    B.dot_batch_autotune(sub, ws2.data_ptr(), st)
-    B.dot_batch_reset(sub, ws2.data_ptr(), st)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r2 = B.dot_batch_run(sub, ws2.data_ptr(), BATCH_MAX_ITER, st)
-    torch.cuda.synchronize()
-    el2 = time.perf_counter() - t0
-    out["batched_sample"] = {"instances": sample, "seconds": el2, "solves_per_s": sample / el2}
-    out["speedup_batched_mixed_vs_plain_fp64_same_sample"] = (sample / el2) / plain["fp64"]["solves_per_s"]
+    # the same instances one at a time in plain FP64
+    t_tot, its, conv_p = 0.0, 0, 0
+    for k, inst in enumerate(insts):
+        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=TOL,
+                                 max_iter=FINISH_MAX_ITER)
+        buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
+        el1, r = time_solves(plan, buf.data_ptr(), st, 1, torch, cap=FINISH_MAX_ITER)
+        t_tot += el1
+        its += r[0].iters
+        conv_p += int(_converged(r[0]))
+        if k % 8 == 7:
+            log(f"plain fp64: {k + 1}/{count} solved, {t_tot:.1f} s")
+        del buf
+        plan.close()
+    out["plain_fp64_one_at_a_time"] = {"instances": count, "converged": conv_p, "seconds": t_tot,
+                                       "solves_per_s": conv_p / t_tot, "iters_per_s": its / t_tot}
+    out["speedup_batched_mixed_vs_plain_fp64"] = (conv / el) / (conv_p / t_tot)
     return out
 
 
@@ -436,9 +534,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-cfg3-iters", type=int, default=3,
+                    help="oracle iterations timed on 2D 64x256^2 per leg of the CPU baseline")
     ap.add_argument("--batch", type=int, default=64, help="instances of the batched section (0: skip)")
-    ap.add_argument("--plain-sample", type=int, default=4)
     ap.add_argument("--serve-seconds", type=float, default=50.0, help="serving arrival window (0: skip)")
     ap.add_argument("--serve-drain", type=float, default=90.0)
     # about 80% of the serving mix's capacity on one MI355X: a 3D request
@@ -473,13 +571,16 @@ def main():
     iters = [r.iters for r in results]
     assert all(B.TERM_NAMES[r.term] == "converged" for r in results), [r.term for r in results]
     last = results[-1]
+    rho_h, m_h = B.dot_extract(plan, ptr, st)
+    err = headline_error(rho_h, m_h, last)
 
     # roofline: the same solves again with events around the dominant kernel
     log("kernel breakdown")
     breakdown = kernel_breakdown(plan, ptr, st)
     dominant = max(breakdown, key=lambda k: breakdown[k]["ms_total"])
     B.dot_profile_select(plan, B.KERNEL_CLASSES[dominant])
-    el_ev, _ = time_solves(plan, ptr, st, args.steps, torch)
+    n_ev = min(args.steps, 5)
+    el_ev, _ = time_solves(plan, ptr, st, n_ev, torch)
     dom_ms, dom_cnt = B.dot_profile_read(plan)
     B.dot_profile_select(plan, -1)
     kb = PM.kernel_bytes(D, n, w)
@@ -513,6 +614,7 @@ def main():
         "eta_dot": last.eta_dot,
         "objective": last.objective,
         "dual_objective": last.dual_objective,
+        "error_vs_oracle": err,
         "roofline": {
             "bound": "hbm",
             "kernel": dominant,
@@ -525,7 +627,7 @@ def main():
             "algorithmic_bytes_per_launch": kb[dominant],
             "avg_launch_us": avg_us,
             "launches": dom_cnt,
-            "timed_region": f"{args.steps} further solves of the same instance with HIP events around every "
+            "timed_region": f"{n_ev} further solves of the same instance with HIP events around every "
                             f"launch of this kernel on the solver's stream (graphs off), {el_ev:.2f} s",
         },
         "iteration": {
@@ -534,21 +636,26 @@ def main():
             "min_bytes_frac_of_hbm_peak": it_min / (el / sum(iters)) / 1e9 / PM.HBM_PEAK_GBS,
         },
         "kernel_breakdown_one_solve": breakdown,
+        "kernel_breakdown_note": ("one solve per class with HIP events around every launch of that class: "
+                                  "graphs off and the beta + next right-hand-side fusion off, so the classes sum "
+                                  "to more than the timed solve (which runs graphs and the fused launch)"),
         "roofline_bandwidth_bound_size": large,
     }
     log("large instance 32x1024x1024")
     out["large_instance"] = large_section(torch, st)
     log("multilevel")
     out["multilevel"] = multilevel_section(torch, inst)
+    log("mixed vs fp64 at 2D 64x256x256")
+    out["mixed_vs_fp64_2d_64x256x256"] = mixed_vs_fp64_config3(torch, st)
     log("variants (tau)")
     out["variants_tau"] = variants_section(torch, st, inst)
     if args.batch > 0:
-        out["batched"] = batched_section(torch, st, args.batch, args.plain_sample)
+        out["batched"] = batched_section(torch, st, args.batch)
     if args.serve_seconds > 0:
         out["serving"] = serving_section(torch, args.serve_rate, args.serve_seconds, args.serve_drain)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(inst, iters[0], args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(iters[0], args.cpu_cfg3_iters)
     print(json.dumps(out))
 
 

@@ -383,6 +383,11 @@ int dot_batch_sigma_history(const dot_batch* batch, const void* workspace, int32
  * floor. mixed_state is not modified. Blocks. */
 int dot_state_promote(const dot_plan* mixed_plan, const void* mixed_state, dot_plan* fp64_plan, void* fp64_state,
                       void* stream);
+/* The same for instance `index` of a DOT_MIXED batch (its state and control
+ * block in the batch workspace `workspace`): fp64_plan must be made from that
+ * instance's problem in DOT_FP64. The batch is not modified. */
+int dot_batch_promote(const dot_batch* batch, const void* workspace, int32_t index, dot_plan* fp64_plan,
+                      void* fp64_state, void* stream);
 /* One-shot multilevel solve with `levels` coarser grids (0 = plain solve):
  * allocates, solves level by level on the default stream, copies rho / m of
  * the target grid (as dot_solve) and frees. res: the target level;

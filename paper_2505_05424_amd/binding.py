@@ -34,7 +34,7 @@ EXPORTED = [
     "dot_sigma_history", "dot_batch_sigma_history",
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
-    "dot_step_residuals_noalloc", "dot_ctx_export", "dot_ctx_import", "dot_ctx_last_error",
+    "dot_step_residuals_noalloc", "dot_ctx_export", "dot_ctx_import", "dot_ctx_last_error", "dot_batch_promote",
 ]
 NOALLOC_SCRATCH_BYTES = 8 << 20
 
@@ -199,6 +199,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                      ctypes.POINTER(ctypes.c_uint8)]
     lib.dot_prolong.argtypes = [vp, vp, vp, vp, vp]
     lib.dot_state_promote.argtypes = [vp, vp, vp, vp, vp]
+    lib.dot_batch_promote.argtypes = [vp, vp, i32, vp, vp, vp]
     pd = ctypes.POINTER(ctypes.c_double)
     lib.dot_state_export.argtypes = [vp, vp, pd, pd, pd, pd, vp]
     lib.dot_state_import.argtypes = [vp, vp, pd, pd, pd, dbl, vp]
@@ -641,6 +642,11 @@ def dot_batch_sigma_history(batch, ws_ptr: int, index: int, cap: int = 32, strea
 
 def dot_state_promote(mixed_plan, mixed_state_ptr: int, fp64_plan, fp64_state_ptr: int, stream: int = 0):
     _check(load().dot_state_promote(mixed_plan.handle, ctypes.c_void_p(mixed_state_ptr), fp64_plan.handle,
+                                    ctypes.c_void_p(fp64_state_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_batch_promote(batch, ws_ptr: int, index: int, fp64_plan, fp64_state_ptr: int, stream: int = 0):
+    _check(load().dot_batch_promote(batch.handle, ctypes.c_void_p(ws_ptr), int(index), fp64_plan.handle,
                                     ctypes.c_void_p(fp64_state_ptr), ctypes.c_void_p(stream)))
 
 

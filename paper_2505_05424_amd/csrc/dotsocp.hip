@@ -2130,14 +2130,19 @@ int dot_state_import(dot_plan* P, void* state, const double* q, const double* al
   return DOT_OK;
 }
 
-int dot_state_promote(const dot_plan* M, const void* mixed_state, dot_plan* F, void* fp64_state, void* stream) {
-  if (!M || !mixed_state || !F || !fp64_state) return fail(DOT_EINVAL, "null argument");
+}  // extern "C"
+
+namespace {
+
+// Promotion of the mixed iterate in `mixed_state` (layout of M) whose control
+// block is at `mctl` (the state's own, or a batch member's) into fp64_state.
+int promote_impl(const dot_plan* M, const void* mixed_state, const Ctl* mctl, dot_plan* F, void* fp64_state,
+                 hipStream_t st) {
   if (M->precision != DOT_MIXED || F->precision != DOT_FP64)
     return fail(DOT_EINVAL, "promotion goes from a mixed-precision plan to an FP64 plan");
   bool same = M->D == F->D && M->cadence == F->cadence;
   for (int a = 0; a <= M->D; ++a) same = same && M->n[a] == F->n[a];
   if (!same) return fail(DOT_EINVAL, "the two plans differ in grid or check cadence");
-  hipStream_t st = (hipStream_t)stream;
   const int D = M->D;
   const int64_t nb = M->g.nb;
   const char* ms = static_cast<const char*>(mixed_state);
@@ -2159,7 +2164,7 @@ int dot_state_promote(const dot_plan* M, const void* mixed_state, dot_plan* F, v
   HIP_OK(hipMemsetAsync(fs + F->off_w, 0, (size_t)(4 * D) * nb * 8, st));
   // control block: the FP64 plan's parameters, the iterate's sigma, counters
   // and sigma schedule
-  HIP_OK(hipMemcpyAsync(M->host_ctl, ms + M->ctl_offset, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIP_OK(hipMemcpyAsync(M->host_ctl, mctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
   const Ctl m = *M->host_ctl;
   Ctl f = initial_ctl(F);
@@ -2180,6 +2185,26 @@ int dot_state_promote(const dot_plan* M, const void* mixed_state, dot_plan* F, v
   HIP_OK(hipMemcpyAsync(fs + F->ctl_offset, F->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
   return DOT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dot_state_promote(const dot_plan* M, const void* mixed_state, dot_plan* F, void* fp64_state, void* stream) {
+  if (!M || !mixed_state || !F || !fp64_state) return fail(DOT_EINVAL, "null argument");
+  return promote_impl(M, mixed_state, at<const Ctl>(const_cast<void*>(mixed_state), M->ctl_offset), F, fp64_state,
+                      (hipStream_t)stream);
+}
+
+int dot_batch_promote(const dot_batch* B, const void* ws, int32_t index, dot_plan* F, void* fp64_state,
+                      void* stream) {
+  if (!B || !ws || !F || !fp64_state) return fail(DOT_EINVAL, "null argument");
+  if (index < 0 || index >= (int)B->plans.size()) return fail(DOT_EINVAL, "instance index out of range");
+  const char* base = static_cast<const char*>(ws);
+  return promote_impl(B->plans[index], base + B->state_off[index],
+                      reinterpret_cast<const Ctl*>(base + (size_t)index * B->ctl_stride), F, fp64_state,
+                      (hipStream_t)stream);
 }
 
 int dot_prolong(const dot_plan* C, const void* coarse_state, dot_plan* F, void* fine_state, void* stream) {

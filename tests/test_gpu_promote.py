@@ -93,3 +93,34 @@ def test_promotion_rejects_mismatched_plans():
         B.dot_state_promote(mp, ms.ptr, mp, ms.ptr, st)  # target not FP64
     with pytest.raises(B.DotError):
         B.dot_state_promote(mp, ms.ptr, fp_other, fs2.ptr, st)  # other grid
+
+
+def test_batch_member_promotion_equals_promoting_its_solve_alone():
+    """dot_batch_promote of member 1 of a mixed batch after 200 iterations gives
+    bitwise the FP64 state that dot_state_promote gives for the same problem
+    solved alone in mixed precision (a batch member equals its solve alone);
+    50 FP64 iterations from either are bitwise equal."""
+    insts = [dotgen.tiny_instance(2, (12, 30, 26), seed=84, floor=0.0),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=85, floor=0.0, masked=True)]
+    st = G.stream_handle()
+    torch = G.torch_mod()
+    batch = B.dot_batch_create(insts, tol=-1.0, max_iter=10 ** 6, precision=B.DOT_MIXED)
+    ws = torch.zeros(int(batch.workspace_bytes), dtype=torch.uint8, device="cuda")
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    B.dot_batch_run(batch, ws.data_ptr(), 200, st)
+    fp_b = _plan(insts[1], B.DOT_FP64)
+    fs_b = G.GpuState(fp_b)
+    B.dot_batch_promote(batch, ws.data_ptr(), 1, fp_b, fs_b.ptr, st)
+    mp, fp = _plan(insts[1], B.DOT_MIXED), _plan(insts[1], B.DOT_FP64)
+    ms, fs = G.GpuState(mp), G.GpuState(fp)
+    ms.reset()
+    ms.run(200)
+    B.dot_state_promote(mp, ms.ptr, fp, fs.ptr, st)
+    assert np.array_equal(G.host(fs_b.buf), G.host(fs.buf))
+    r_b, r = fs_b.run(50), fs.run(50)
+    assert r_b.iters == r.iters == 250
+    assert r_b.objective == r.objective and r_b.eta_dot == r.eta_dot and r_b.sigma == r.sigma
+    with pytest.raises(B.DotError):
+        B.dot_batch_promote(batch, ws.data_ptr(), 2, fp_b, fs_b.ptr, st)  # no such member
+    with pytest.raises(B.DotError):
+        B.dot_batch_promote(batch, ws.data_ptr(), 0, fp_b, fs_b.ptr, st)  # other grid
