@@ -160,9 +160,13 @@ int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double
  * rge A^*), inverse transform. A last axis of 257 or more nodes is not
  * transformed: after the other axes' transforms each of its lines is a
  * tridiagonal system (eigenvalue sum of the other axes + path-graph Laplacian
- * / h^2), solved by elimination in FP64; same linear system, same phi up to
- * rounding (forward error within the condition number of the line systems
- * times the FP64 unit, which grows with the square of the axis length). Such
+ * / h^2), solved by elimination with the recurrences in FP64 registers; same
+ * linear system, same phi up to rounding (forward error within the condition
+ * number of the line systems times the FP64 unit, which grows with the square
+ * of the axis length). In DOT_MIXED the transforms work on an FP32 plane, and
+ * so does the elimination's intermediate d' between its forward and backward
+ * sweep (stored in the plane's type; the c' checkpoints are FP64), i.e. the
+ * FP32 rounding of the other transform passes. Such
  * an axis has no transform-tile limit (every axis stays within the 4096
  * segments dot_plan_create accepts); the other axes must fit a tile. */
 int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
