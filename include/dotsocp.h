@@ -281,10 +281,14 @@ int dot_batch_set_graphs(dot_batch* batch, int32_t enable);
  * products run in one wavefront in a fixed order, so results are bitwise
  * those of any other schedule (and a batch member still equals its solve
  * alone). On a last axis that every instance of the launch solves by
- * tridiagonal elimination (>= 257 nodes) cw is the number of lines (one per
- * thread) of each 256-thread workgroup, 64 by default; waves do not apply. */
+ * tridiagonal elimination (>= 257 nodes) cw is the number of lines of each
+ * 256-thread workgroup: 4, 8, 16, 32 or 64 (4 and 8 only when no line is
+ * longer than 576 nodes), by default the lines one round of the partitioned
+ * solve takes (8 for lines of up to 288 nodes, 4 up to 576; 64 when some
+ * line is longer); waves do not apply. */
 typedef struct {
-  int32_t cw[4];       /* lines per tile, axes 0..D: 16, 32 or 64 (set calls: 0 keeps the rule's) */
+  int32_t cw[4];       /* lines per tile, axes 0..D: 16, 32 or 64, also 4 or 8 on an eliminated last
+                          axis (set calls: 0 keeps the rule's) */
   int32_t waves[4];    /* wavefronts per workgroup, 1..16, enough for the axis's work items
                           (set calls: 0 keeps the rule's for that tile width) */
   int32_t tuned;       /* out: 1 when the schedule was chosen by an autotune call */

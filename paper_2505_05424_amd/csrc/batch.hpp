@@ -142,8 +142,19 @@ __global__ void __launch_bounds__(kTriThreads)
 kb_tri_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[inst_of_block(map, L)];
-  if (stopped(s) || !s.tri) return;
+  if (stopped(s) || !s.tri || s.g.N[D] <= kTriPartMaxNodes) return;  // shorter lines: kb_tri_part
   tri_pass_body<T, CW>(s.g, s.work, s.W, s.lam_other, (int64_t)(L - s.tile0[D]));
+}
+
+// Partitioned last-axis solve (lines of up to kTriPartMaxNodes nodes) over the
+// same tile grid: tile t of an instance holds its lines [t cw, (t + 1) cw).
+template <typename T, int D>
+__global__ void __launch_bounds__(kTriThreads, 2)
+kb_tri_part(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int cw) {
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[inst_of_block(map, L)];
+  if (stopped(s) || !s.tri || s.g.N[D] > kTriPartMaxNodes) return;
+  tri_part_body<T>(s.g, s.work, s.lam_other, (int64_t)(L - s.tile0[D]), cw);
 }
 
 // ---- step-level kernels (single instance, caller pointers) ----------------

@@ -303,12 +303,34 @@ int choose_cw(int64_t lines, bool wide_ok, bool mid_ok) {
   if (mid_ok && (lines + kCWMid - 1) / kCWMid >= kMidTiles) return kCWMid;
   return kCWNarrow;
 }
+
+// Lines per workgroup on a last axis that every instance solves by
+// elimination: one round of the partitioned solve (256 / lanes per line: 8
+// for lines of up to 288 nodes, 4 up to 576), so that each workgroup loads,
+// solves and stores once; 64 when some line is longer (the one-lane-per-line
+// solve takes tiles of 16, 32 or 64 lines).
+int tri_default_cw(dot_plan* const* plans, int count) {
+  int L = 0;
+  for (int i = 0; i < count; ++i) L = std::max(L, plans[i]->g.N[plans[i]->D]);
+  if (L > kTriPartMaxNodes) return kCW;
+  return kTriThreads / tri_lanes(L);
+}
+
+// Tile widths a last axis solved by elimination in every instance may take.
+bool tri_cw_ok(dot_plan* const* plans, int count, int cw) {
+  if (cw == kCW || cw == kCWMid || cw == kCWNarrow) return true;
+  if (cw != 4 && cw != 8) return false;
+  for (int i = 0; i < count; ++i)
+    if (plans[i]->g.N[plans[i]->D] > kTriPartMaxNodes) return false;
+  return true;
+}
 int64_t tiles_for(int64_t lines, int cw) { return (lines + cw - 1) / cw; }
 
 // Launch geometry of the passes over axis a of one launch covering the
 // instances plans[0..count): tile width and waves from s where it sets them,
-// else from the rules above (the tridiagonal-only last axis keeps the wide
-// tile: its pass takes a full wave of lines), and the LDS bytes.
+// else from the rules above (a last axis that every instance solves by
+// elimination takes one round of the partitioned solve: 8 lines of up to 288
+// nodes, 4 of up to 576 per 256 lanes; 64 for longer lines), and the LDS bytes.
 struct AxisGeom {
   int cw = kCW, waves = 4;
   int64_t tiles = 0;
@@ -325,7 +347,8 @@ AxisGeom axis_geom(dot_plan* const* plans, int count, int a, const Sched& s) {
     all_tri = all_tri && plans[i]->tri;
   }
   AxisGeom ag;
-  ag.cw = s.cw[a] ? s.cw[a] : ((a == plans[0]->D && all_tri) ? kCW : choose_cw(all_lines, wide_ok, mid_ok));
+  ag.cw = s.cw[a] ? s.cw[a]
+                  : ((a == plans[0]->D && all_tri) ? tri_default_cw(plans, count) : choose_cw(all_lines, wide_ok, mid_ok));
   for (int i = 0; i < count; ++i) ag.tiles += tiles_for(plans[i]->lines[a], ag.cw);
   int waves = 1;
   for (int i = 0; i < count; ++i) {
@@ -355,7 +378,10 @@ std::vector<std::pair<int, int>> axis_candidates(dot_plan* const* plans, int cou
   if (a == plans[0]->D && all_tri) {
     // only the tridiagonal solve runs on this axis: 256 threads whatever the
     // waves; the width sets the lines per workgroup (and its LDS)
-    for (int cw : {kCWNarrow, kCWMid, kCW}) {
+    std::vector<int> cws = {tri_default_cw(plans, count), kCWNarrow, kCWMid, kCW};
+    std::sort(cws.begin(), cws.end());
+    cws.erase(std::unique(cws.begin(), cws.end()), cws.end());
+    for (int cw : cws) {
       Sched s;
       s.cw[a] = cw;
       out.push_back({cw, axis_geom<T>(plans, count, a, s).waves});
@@ -527,7 +553,8 @@ struct Exec {
   size_t smem_axis[kMaxAxes] = {0, 0, 0, 0};
   int waves_axis[kMaxAxes] = {0, 0, 0, 0};
   int cw_axis[kMaxAxes] = {kCW, kCW, kCW, kCW};  // transform tile width per axis
-  int ntri = 0;  // instances whose last axis takes the tridiagonal solve
+  int ntri = 0;       // instances whose last axis takes the tridiagonal solve
+  int ntri_long = 0;  // of those, lines longer than the partitioned solve takes
   Prof* prof = nullptr;
   int device = 0;
   struct GraphCache* graphs = nullptr;  // captured 10-iteration blocks (nullptr: plain launches)
@@ -579,8 +606,17 @@ int launch_tri_cw(const Exec& E, hipStream_t st) {
   return DOT_OK;
 }
 
+// Last-axis elimination: the partitioned solve for lines of up to
+// kTriPartMaxNodes nodes, the one-lane-per-line solve for longer ones.
 template <typename T, int D>
 int launch_tri(const Exec& E, hipStream_t st) {
+  if (E.ntri > E.ntri_long) {
+    ProfScope ps(E.prof, DOT_K_DCT_LAST, st);
+    hipLaunchKernelGGL((kb_tri_part<T, D>), dim3(E.grid_axis[D]), dim3(kTriThreads), 0, st, (const Inst<T>*)E.d_inst,
+                       E.map_axis[D], E.cw_axis[D]);
+    HIP_OK(hipGetLastError());
+  }
+  if (E.ntri_long == 0) return DOT_OK;
   switch (E.cw_axis[D]) {
     case kCW: return launch_tri_cw<T, D, kCW>(E, st);
     case kCWMid: return launch_tri_cw<T, D, kCWMid>(E, st);
@@ -830,6 +866,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.map_nodes = nullptr;  // one instance: blocks need no map
   E.grid_nodes = (unsigned)P->nblocks;
   E.ntri = P->tri ? 1 : 0;
+  E.ntri_long = P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = nullptr;
     const AxisGeom ag = P->precision == DOT_FP64 ? axis_geom<double>(&P, 1, a, P->sched)
@@ -903,7 +940,9 @@ struct PoissonF {
   static int run(dot_plan* P, void* phi, const void* q, const void* al, double sigma, hipStream_t st) {
     Exec E = plan_exec(P, 1);
     E.prof = nullptr;
-    if (P->tri && !P->step_cbuf) HIP_OK(hipMalloc(&P->step_cbuf, (size_t)P->g.nb * sizeof(T)));
+    // c' checkpoints of the one-lane-per-line elimination (lines longer than the partitioned solve takes)
+    if (P->tri && P->g.N[D] > kTriPartMaxNodes && !P->step_cbuf)
+      HIP_OK(hipMalloc(&P->step_cbuf, (size_t)P->g.nb * sizeof(T)));
     int rc = upload_inst(E, step_inst<T>(P, phi, q, al, nullptr, nullptr, P->step_cbuf, nullptr), st);
     if (rc) return rc;
     if (q && (rc = launch_rhs<T, D, false>(E, 0, sigma, st))) return rc;
@@ -1139,7 +1178,11 @@ int batch_layout(dot_batch* B, const Sched& s) {
   Exec& E = B->E;
   E.grid_nodes = (unsigned)map_off[0];
   E.ntri = 0;
-  for (int i = 0; i < count; ++i) E.ntri += plans[i]->tri ? 1 : 0;
+  E.ntri_long = 0;
+  for (int i = 0; i < count; ++i) {
+    E.ntri += plans[i]->tri ? 1 : 0;
+    E.ntri_long += plans[i]->tri && plans[i]->g.N[plans[i]->D] > kTriPartMaxNodes ? 1 : 0;
+  }
   E.map_nodes = B->d_maps;
   for (int a = 0; a <= B->D; ++a) {
     E.map_axis[a] = B->d_maps + map_off[a];
@@ -1195,7 +1238,7 @@ bool schedule_ok(dot_plan* const* plans, int count, int a, int cw, int waves, in
   bool all_tri = true;
   for (int i = 0; i < count; ++i) all_tri = all_tri && plans[i]->tri;
   if (waves < 1 || waves > kMaxWaves) return false;
-  if (a == plans[0]->D && all_tri) return cw == kCW || cw == kCWMid || cw == kCWNarrow;
+  if (a == plans[0]->D && all_tri) return tri_cw_ok(plans, count, cw);
   if (cw != kCWNarrow && cw != kCWMid && cw != kCW) return false;
   for (int i = 0; i < count; ++i) {
     if (a == plans[i]->D && plans[i]->tri) continue;  // only the tridiagonal solve runs there
@@ -2442,7 +2485,8 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
       mid_ok = mid_ok && P->mid_ok[a];
       all_tri = all_tri && P->tri;
     }
-    E.cw_axis[a] = (a == C->D && all_tri) ? kCW : choose_cw(all_lines, wide_ok, mid_ok);
+    E.cw_axis[a] = (a == C->D && all_tri) ? tri_default_cw(act.data(), (int)act.size())
+                                           : choose_cw(all_lines, wide_ok, mid_ok);
   }
   // descriptors of the active instances, in slot order
   uint32_t blk = 0;
@@ -2466,7 +2510,10 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
   }
   E.ninst = idx;
   E.grid_nodes = blk;
-  for (dot_plan* P : act) E.ntri += P->tri ? 1 : 0;
+  for (dot_plan* P : act) {
+    E.ntri += P->tri ? 1 : 0;
+    E.ntri_long += P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
+  }
   size_t map_off[kMaxAxes] = {0, 0, 0, 0};
   for (int a = 0; a <= C->D; ++a) {
     map_off[a] = maps.size();

@@ -607,4 +607,242 @@ __device__ __forceinline__ void tri_pass_body(const Geo& g, T* __restrict__ plan
   }
 }
 
+// ---- partitioned elimination of the last-axis line systems -------------------
+// The same line systems as tri_pass_body, (lam + n^2 L_path) x = b along each
+// line of the last axis, solved with P lanes per line instead of one. Lane k
+// of a line's group owns the consecutive rows [lo, hi) (segment sizes differ
+// by at most one); u = x_{lo-1} and z = x_{hi-1} denote the row before its
+// segment and its own last row.
+//   1. Forward elimination of the segment with u kept as an unknown gives its
+//      last row as z = d + g u - c x_{hi} (c = -n^2 r, r the pivot reciprocals,
+//      which are kept).
+//   2. Elimination of rows hi-2 .. lo from the bottom, with z kept as an
+//      unknown, gives its first row as x_lo = al + be u + ga z.
+//   3. Putting the next segment's first-row relation into the first gives one
+//      equation per segment in the last rows z_k:
+//        -g z_{k-1} + (1 + c be') z_k + c ga' z_{k+1} = d - c al',
+//      a tridiagonal system of order P (the primes: the next segment's
+//      values), solved by the P lanes together by parallel cyclic reduction
+//      through cross-lane shuffles (log2 P steps; the reduced system of a
+//      diagonally dominant one is diagonally dominant).
+//   4. With u = z_{k-1} known, the segment's rows follow from a forward pass
+//      with the kept pivots and a backward pass from z_k.
+// All arithmetic is FP64 (the plane's type only for load and store). The lines
+// of a round are staged in LDS as FP64 (padded by one element per 16, so that
+// lanes reading rows about 16 apart fall on different banks), so the plane is
+// read once and written once, coalesced, and the passes read their rows from
+// LDS. The line with lam = 0 (mode 0 on every other axis) is the singular
+// Neumann problem: its fluxes f_i = -(b_0 + ... + b_i) and values x_i =
+// (f_0 + ... + f_{i-1}) / n^2 are prefix sums, taken per segment and across
+// the lanes by shuffle scans, and the line mean is removed (the constant mode
+// of phi is zero), as in the one-lane solve.
+// The rows per lane are bounded by kTriSeg, a compile-time constant (the size
+// of the register arrays); lines of up to 64 kTriSeg nodes take this solve,
+// longer ones the one-lane-per-line solve (measured at 1025 nodes: with 17
+// rows per lane the arrays no longer fit the registers of two waves per SIMD,
+// and the partitioned solve was slower than the one-lane solve, 230-260 us
+// against 208 us per pass at 2D 32x1024^2 mixed).
+constexpr int kTriSeg = 9;
+constexpr int kTriPartMaxNodes = 64 * kTriSeg;  // longest line (64 lanes of 9 rows)
+
+// Lanes per line: 16, 32 or 64, the fewest that keep segments within kTriSeg rows.
+__device__ __host__ __forceinline__ int tri_lanes(int L) {
+  return L <= 16 * kTriSeg ? 16 : (L <= 32 * kTriSeg ? 32 : 64);
+}
+
+__device__ __forceinline__ int tri_pad(int i) { return i + (i >> 4); }
+
+// Inclusive prefix sum of v over the P lanes of a group (Hillis-Steele).
+__device__ __forceinline__ double group_scan(double v, int k, int P) {
+  for (int s = 1; s < P; s <<= 1) {
+    const double o = __shfl_up(v, s, P);
+    if (k >= s) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ double group_sum(double v, int P) {
+  for (int s = P >> 1; s >= 1; s >>= 1) v += __shfl_xor(v, s, P);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ void tri_part_body(const Geo& g, T* __restrict__ plane, const T* __restrict__ lam_other,
+                                              int64_t tile, int cw) {
+  constexpr int kTriSegMax = kTriSeg;
+  constexpr int kTriLoadPer = kTriSeg;  // elements per thread of one round's copy (lpr L <= 16 kTriSeg * 16)
+  constexpr int kTriPartElems = 16 * (16 * kTriSeg + kTriSeg + 1);  // LDS doubles of one round (padded lines)
+  __shared__ double buf[kTriPartElems];
+  const int D = g.D;
+  const int L = g.N[D];
+  const double s2 = (double)g.n[D] * (double)g.n[D];
+  const double inv_s2 = 1.0 / s2;
+  const int P = tri_lanes(L);
+  const int lpr = kTriThreads / P;  // lines per round
+  const int64_t ncols = g.nb / L;
+  const int64_t ct = tile * cw;
+  const int nlt = (int)((ncols - ct) < cw ? (ncols - ct) : cw);
+  const int k = threadIdx.x & (P - 1);  // segment of this lane
+  const int grp = threadIdx.x / P;      // line of this lane within the round
+  const int lo = (k * L) / P, hi = ((k + 1) * L) / P, len = hi - lo;
+  const int Lp = tri_pad(L) + 1;  // padded line length in LDS
+  gp<T> pl = glob(plane);
+  auto diag_at = [&](double lam, int i) { return lam + s2 * ((i == 0 || i == L - 1) ? 1.0 : 2.0); };
+  for (int r0 = 0; r0 < nlt; r0 += lpr) {
+    const int nl = nlt - r0 < lpr ? nlt - r0 : lpr;
+    const uint32_t base = (uint32_t)(ct + r0) * (uint32_t)L;
+    const int tot = nl * L;
+    {
+      // coalesced copy of the round's lines into LDS; every thread issues its
+      // loads before the first LDS write (L > kTriThreads: element e + 256 is
+      // on the same line or the next)
+      T v[kTriLoadPer];
+      int i = threadIdx.x, ln = 0;
+#pragma unroll
+      for (int r = 0; r < kTriLoadPer; ++r) {
+        const int e = threadIdx.x + r * kTriThreads;
+        v[r] = e < tot ? pl[base + e] : T(0);
+      }
+#pragma unroll
+      for (int r = 0; r < kTriLoadPer; ++r) {
+        const int e = threadIdx.x + r * kTriThreads;
+        if (e < tot) buf[ln * Lp + tri_pad(i)] = (double)v[r];
+        i += kTriThreads;
+        if (i >= L) {
+          i -= L;
+          ++ln;
+        }
+      }
+    }
+    __syncthreads();
+    const bool active = grp < nl;
+    const double lam = active ? (double)glob(lam_other)[ct + r0 + grp] : 1.0;
+    double* row = buf + (active ? grp : 0) * Lp;  // this lane's line
+    auto rd = [&](int j) { return active ? row[tri_pad(lo + j)] : 0.0; };
+    if (lam == 0.0) {
+      // singular line: prefix sums of b, then of the fluxes
+      double sb = 0.0;
+      for (int j = 0; j < len; ++j) sb += rd(j);
+      const double pb = group_scan(sb, k, P) - sb;  // b_0 + ... + b_{lo-1}
+      double cb = pb, sf = 0.0;
+      for (int j = 0; j < len; ++j) {
+        cb += rd(j);
+        sf -= cb;  // f_{lo+j} = -(b_0 + ... + b_{lo+j})
+      }
+      double x = group_scan(sf, k, P) - sf;  // f_0 + ... + f_{lo-1}
+      double sx = 0.0;
+      cb = pb;
+      for (int j = 0; j < len; ++j) {
+        const double bj = rd(j);
+        const double xj = x * inv_s2;
+        if (active) row[tri_pad(lo + j)] = xj;
+        sx += xj;
+        cb += bj;
+        x -= cb;
+      }
+      const double mean = group_sum(sx, P) / (double)L;
+      if (active)
+        for (int j = 0; j < len; ++j) row[tri_pad(lo + j)] -= mean;
+    } else {
+      // the segment's right-hand side in registers (rows past its end read
+      // its last row; every loop below runs the full length and keeps the
+      // values of valid rows only, without branches)
+      double bv[kTriSegMax];
+#pragma unroll
+      for (int j = 0; j < kTriSegMax; ++j) bv[j] = row[tri_pad(lo + (j < len ? j : len - 1))];
+      if (!active) {
+#pragma unroll
+        for (int j = 0; j < kTriSegMax; ++j) bv[j] = 0.0;
+      }
+      // 1: forward elimination with u unknown; pivots kept
+      double rv[kTriSegMax];
+      double cp = 0.0, dp = 0.0, gq = lo > 0 ? 1.0 : 0.0;
+#pragma unroll
+      for (int j = 0; j < kTriSegMax; ++j) {
+        const int i = lo + j;
+        const double r = tri_recip(diag_at(lam, i) + s2 * cp);
+        const bool ok = j < len;
+        rv[j] = r;
+        dp = ok ? (bv[j] + s2 * dp) * r : dp;
+        gq = ok ? s2 * gq * r : gq;
+        cp = ok ? (i < L - 1 ? -s2 * r : 0.0) : cp;
+      }
+      // 2: first row in terms of u and z, by elimination from the bottom
+      double al = 0.0, ga = 1.0, f = 0.0;
+#pragma unroll
+      for (int j = kTriSegMax - 2; j >= 0; --j) {
+        const bool ok = j < len - 1;
+        const double q = tri_recip(diag_at(lam, lo + j) + s2 * f);
+        al = ok ? (bv[j] + s2 * al) * q : al;
+        ga = ok ? s2 * ga * q : ga;
+        f = ok ? -s2 * q : f;
+      }
+      const double be = lo > 0 ? -f : 0.0;
+      // 3: reduced system of the segments' last rows, cyclic reduction across lanes
+      const double al1 = __shfl_down(al, 1, P), be1 = __shfl_down(be, 1, P), ga1 = __shfl_down(ga, 1, P);
+      const bool last = k == P - 1;
+      double A = -gq;
+      double Bq = last ? 1.0 : 1.0 + cp * be1;
+      double C = last ? 0.0 : cp * ga1;
+      double R = last ? dp : dp - cp * al1;
+      for (int s = 1; s < P; s <<= 1) {
+        const double Am = __shfl_up(A, s, P), Bm = __shfl_up(Bq, s, P), Cm = __shfl_up(C, s, P),
+                     Rm = __shfl_up(R, s, P);
+        const double Ap = __shfl_down(A, s, P), Bp = __shfl_down(Bq, s, P), Cp = __shfl_down(C, s, P),
+                     Rp = __shfl_down(R, s, P);
+        const bool hm = k >= s, hp = k + s < P;
+        const double a = hm ? -A * tri_recip(Bm) : 0.0;
+        const double c = hp ? -C * tri_recip(Bp) : 0.0;
+        const double An = hm ? a * Am : 0.0;
+        const double Cn = hp ? c * Cp : 0.0;
+        Bq = Bq + (hm ? a * Cm : 0.0) + (hp ? c * Ap : 0.0);
+        R = R + (hm ? a * Rm : 0.0) + (hp ? c * Rp : 0.0);
+        A = An;
+        C = Cn;
+      }
+      const double z = R * tri_recip(Bq);
+      // every lane takes part in the shuffle: a lane outside the active set
+      // of a cross-lane read supplies nothing
+      const double zm = __shfl_up(z, 1, P);
+      const double u = k > 0 ? zm : 0.0;
+      // 4: the segment's rows from u and z (bv holds the forward values, then x)
+      double d = u;
+#pragma unroll
+      for (int j = 0; j < kTriSegMax - 1; ++j) {
+        bv[j] = (bv[j] + s2 * d) * rv[j];
+        d = j < len - 1 ? bv[j] : d;
+      }
+      double x = z;
+#pragma unroll
+      for (int j = kTriSegMax - 2; j >= 0; --j) {
+        x = j < len - 1 ? bv[j] + s2 * rv[j] * x : x;
+        bv[j] = x;
+      }
+      if (active) {
+        double* seg = row + tri_pad(lo);
+#pragma unroll
+        for (int j = 0; j < kTriSegMax; ++j) {
+          if (j < len - 1) seg[tri_pad(lo + j) - tri_pad(lo)] = bv[j];
+        }
+        row[tri_pad(hi - 1)] = z;
+      }
+    }
+    __syncthreads();
+    {
+      int i = threadIdx.x, ln = 0;
+#pragma unroll
+      for (int r = 0; r < kTriLoadPer; ++r) {
+        const int e = threadIdx.x + r * kTriThreads;
+        if (e < tot) pl[base + e] = (T)buf[ln * Lp + tri_pad(i)];
+        i += kTriThreads;
+        if (i >= L) {
+          i -= L;
+          ++ln;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace dot

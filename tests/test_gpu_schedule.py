@@ -81,13 +81,15 @@ def test_every_schedule_gives_the_rule_bits(name, D, n, prec):
 @pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
 @pytest.mark.parametrize("n", [(4, 7, 300), (3, 5, 1200)], ids=["last-301", "last-1201"])
 def test_tridiagonal_last_axis_widths_give_the_same_bits(n, prec):
-    # the elimination runs one line per thread: the lines per workgroup
-    # change no value (1201 nodes: longer than a transform tile holds)
+    # each line is solved by its own lanes in a fixed order: the lines per
+    # workgroup change no value. 301 nodes: the partitioned solve with 64
+    # lanes per line (4 lines per round); 1201 nodes (longer than a transform
+    # tile holds): one lane per line, which takes 16, 32 or 64 lines
     inst = dotgen.tiny_instance(2, n, seed=62, floor=0.0)
     plan = _plan(inst, prec)
     ref = _run(plan, 20)
-    assert B.dot_plan_get_schedule(plan)["cw"][2] == 64
-    for cw in (16, 32):
+    assert B.dot_plan_get_schedule(plan)["cw"][2] == (4 if n[2] < 576 else 64)
+    for cw in ((4, 8, 16, 32, 64) if n[2] < 576 else (16, 32, 64)):
         B.dot_plan_set_schedule(plan, cw=[16, 32, cw], waves=[8, 16, 0])
         _same(_run(plan, 20), ref)
 
