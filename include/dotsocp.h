@@ -117,7 +117,8 @@ typedef struct {
   int32_t n_planes;       /* bulk-type planes in the state buffer (q, q_new, beta, W) */
   size_t state_bytes;     /* bytes the caller must provide for a state buffer */
   /* byte offsets inside a state buffer: phi (FP64 plane), transform scratch
-   * (mixed precision only), q, q_new (bulk type), alpha (double), beta, W (bulk type) */
+   * (mixed precision only), q, q_new (bulk type), alpha (double), beta, W (4D planes of the
+   * bulk type, then one double plane of z-step workspace) */
   uint64_t off_phi, off_scratch, off_q, off_qn, off_alpha, off_beta, off_w;
 } dot_plan_info;
 
@@ -181,7 +182,8 @@ int dot_step_cone(dot_plan* plan, const void* q, const void* beta, double sigma,
 /* a5: q_new, alpha, beta updates of Algorithm 2 (q-step and both
  * multiplier steps) from phi and the old
  * (q, alpha, beta); alpha and beta are updated in place, q_new written to
- * q_out; w_scratch holds 4D planes of workspace. */
+ * q_out; w_scratch is workspace for the z-step: 4D planes of the bulk type
+ * followed by one double plane (nb * (4D * scalar_bytes + 8) bytes). */
 int dot_step_update(dot_plan* plan, const void* phi, const void* q, void* alpha, void* beta,
                     double sigma, double tau, void* q_out, void* w_scratch, void* stream);
 /* a6: the relative KKT residuals of Sec. 5.3 at (phi, z, q, alpha, beta),
@@ -218,8 +220,8 @@ typedef enum {
   DOT_K_DCT_MID = 1,   /* forward passes on the middle spatial axes */
   DOT_K_DCT_LAST = 2,  /* last axis: forward, 1/Lambda, inverse */
   DOT_K_DCT_INV = 3,   /* inverse passes on the other axes */
-  DOT_K_CONE = 4,      /* cone gather + projection + q0/alpha0 update */
-  DOT_K_QD = 5,        /* q_d / alpha_d update */
+  DOT_K_CONE = 4,      /* cone gather + projection (z-step) into the weighted w planes */
+  DOT_K_QD = 5,        /* q-step and alpha update (q0 and q_d) */
   DOT_K_BETA = 6,      /* beta update */
   DOT_K_RESID = 7,     /* residual partial sums (checks only) */
   DOT_K_FINAL = 8,     /* residual finalize + sigma rule (checks only) */

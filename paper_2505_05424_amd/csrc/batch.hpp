@@ -21,7 +21,8 @@ struct Inst {
   T* q[2];          // q and q_new, swapped every iteration (parity argument)
   double* alpha;    // multipliers alpha (FP64 in both modes: they accumulate updates)
   T* beta;
-  T* W;
+  T* W;             // 4D weighted w planes of the z-step
+  double* dw;       // w_{K-1} - w_0 of the z-step (FP64)
   Ctl* ctl;         // nullptr for step-level calls (sigma from the argument)
   double* partials;
   const double* sw;
@@ -48,22 +49,25 @@ __device__ __forceinline__ bool stopped(const Inst<T>& s) {
   return s.ctl && glob(s.ctl)->stop;
 }
 
+// z-step of iteration par's parity: cone gather and projection from q[par]
+// and beta into the W planes.
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
-kb_cone_q0(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+kb_cone(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
-  cone_q0_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.sw, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
+  cone_body<T, D>(s.g, s.q[par], s.beta, s.sw, s.W, s.dw, s.ctl, L - s.blk0);
 }
 
+// q-step and alpha update: q[par ^ 1] from phi, alpha and the W planes.
 template <typename T, int D>
 __global__ void __launch_bounds__(256)
-kb_qd(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+kb_q(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
   const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
   const Inst<T>& s = I[inst_of_block(map, L)];
   if (stopped(s)) return;
-  qd_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.ctl, L - s.blk0);
+  q_body<T, D>(s.g, s.phi, s.alpha, s.om, s.q[par ^ 1], s.W, s.dw, s.ctl, L - s.blk0);
 }
 
 template <typename T, int D>
@@ -136,7 +140,8 @@ kb_axis_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, in
 }
 
 // Last-axis tridiagonal solve over the tiles of the last-axis grid (CW lines
-// each); the c' coefficients go to W plane 0, free between the cone steps.
+// each); the c' checkpoints go to W plane 0 (an executor with such an
+// instance runs the cone step after the phi-step, not beside it).
 template <typename T, int D, int CW>
 __global__ void __launch_bounds__(kTriThreads)
 kb_tri_pass(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map) {

@@ -111,12 +111,19 @@ struct ProfScope {
 constexpr int kGraphIters = 10;
 struct GraphCache {
   hipGraphExec_t exec = nullptr;
-  hipStream_t cap = nullptr;  // private capture stream (default priority)
+  hipStream_t cap = nullptr;       // private capture stream (default priority)
+  hipStream_t cap_side = nullptr;  // second branch of the captured iterations
+  hipStream_t side = nullptr;      // second branch of plain launches
+  hipEvent_t fork = nullptr, join = nullptr;  // branch points (no timing)
   bool enabled = true;
   bool warm = false;
   ~GraphCache() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (cap) (void)hipStreamDestroy(cap);
+    if (cap_side) (void)hipStreamDestroy(cap_side);
+    if (side) (void)hipStreamDestroy(side);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
   }
 };
 
@@ -173,7 +180,7 @@ struct dot_plan {
   // state layout (byte offsets): phi (FP64) | transform scratch (mixed only) |
   // q | q_new | alpha | beta | W (bulk scalar type) | control block | partials
   int n_planes = 0;  // bulk-type planes
-  size_t off_phi = 0, off_scr = 0, off_q = 0, off_qn = 0, off_alpha = 0, off_beta = 0, off_w = 0;
+  size_t off_phi = 0, off_scr = 0, off_q = 0, off_qn = 0, off_alpha = 0, off_beta = 0, off_w = 0, off_dw = 0;
   size_t ctl_offset = 0, partials_offset = 0, state_bytes = 0;
   int device = 0;
   Prof prof;
@@ -493,8 +500,8 @@ FinArgs fin_args(const dot_plan* P) {
 // Descriptor of one instance with caller planes: phi / b and alpha (FP64), q,
 // q_new, beta, W (bulk type), transform work plane, control block, partials.
 template <typename T>
-Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, double* alpha, T* beta, T* W, Ctl* ctl,
-                double* partials) {
+Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, double* alpha, T* beta, T* W, double* dw,
+                Ctl* ctl, double* partials) {
   Inst<T> s{};
   s.g = P->g;
   s.phi = phi;
@@ -504,6 +511,7 @@ Inst<T> inst_of(const dot_plan* P, double* phi, T* scr, T* q, T* qn, double* alp
   s.alpha = alpha;
   s.beta = beta;
   s.W = W;
+  s.dw = dw;
   s.ctl = ctl;
   s.partials = partials;
   s.sw = P->sw_sp;
@@ -524,7 +532,7 @@ template <typename T>
 Inst<T> state_inst(const dot_plan* P, void* state, Ctl* ctl) {
   return inst_of<T>(P, at<double>(state, P->off_phi), at<T>(state, P->off_scr), at<T>(state, P->off_q),
                     at<T>(state, P->off_qn), at<double>(state, P->off_alpha), at<T>(state, P->off_beta),
-                    at<T>(state, P->off_w), ctl, at<double>(state, P->partials_offset));
+                    at<T>(state, P->off_w), at<double>(state, P->off_dw), ctl, at<double>(state, P->partials_offset));
 }
 
 Ctl initial_ctl(const dot_plan* P) {
@@ -555,6 +563,7 @@ struct Exec {
   int cw_axis[kMaxAxes] = {kCW, kCW, kCW, kCW};  // transform tile width per axis
   int ntri = 0;       // instances whose last axis takes the tridiagonal solve
   int ntri_long = 0;  // of those, lines longer than the partitioned solve takes
+  int64_t nodes = 0;  // grid nodes over all instances
   Prof* prof = nullptr;
   int device = 0;
   struct GraphCache* graphs = nullptr;  // captured 10-iteration blocks (nullptr: plain launches)
@@ -669,28 +678,45 @@ int poisson_iter(const Exec& E, int par, hipStream_t st, bool rhs_ready = false)
 }
 
 template <typename T, int D>
-int update_iter(const Exec& E, int par, int check, hipStream_t st, bool rhs_next = false) {
+int launch_cone(const Exec& E, int par, hipStream_t st) {
+  ProfScope ps(E.prof, DOT_K_CONE, st);
+  hipLaunchKernelGGL((kb_cone<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+                     E.map_nodes, par);
+  HIP_OK(hipGetLastError());
+  return DOT_OK;
+}
+
+template <typename T, int D>
+int launch_q(const Exec& E, int par, hipStream_t st) {
+  ProfScope ps(E.prof, DOT_K_QD, st);
+  hipLaunchKernelGGL((kb_q<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst, E.map_nodes,
+                     par);
+  HIP_OK(hipGetLastError());
+  return DOT_OK;
+}
+
+// beta update of the iteration with parity par (q[par] the old q, q[par ^ 1]
+// the new one); with rhs_next also the right-hand side of the next iteration.
+template <typename T, int D>
+int launch_beta(const Exec& E, int par, int check, hipStream_t st, bool rhs_next) {
   const Inst<T>* I = (const Inst<T>*)E.d_inst;
-  {
-    ProfScope ps(E.prof, DOT_K_CONE, st);
-    hipLaunchKernelGGL((kb_cone_q0<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
-  }
-  HIP_OK(hipGetLastError());
-  {
-    ProfScope ps(E.prof, DOT_K_QD, st);
-    hipLaunchKernelGGL((kb_qd<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
-  }
-  HIP_OK(hipGetLastError());
+  ProfScope ps(E.prof, DOT_K_BETA, st);
   if (rhs_next) {
     constexpr bool kMixed = !std::is_same<T, double>::value;
-    ProfScope ps(E.prof, DOT_K_BETA, st);
     hipLaunchKernelGGL((kb_beta_rhs<T, D, kMixed>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
   } else {
-    ProfScope ps(E.prof, DOT_K_BETA, st);
     hipLaunchKernelGGL((kb_beta<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par, check);
   }
   HIP_OK(hipGetLastError());
   return DOT_OK;
+}
+
+// z-step, q-step and multiplier steps of one iteration, one after the other.
+template <typename T, int D>
+int update_iter(const Exec& E, int par, int check, hipStream_t st, bool rhs_next = false) {
+  int rc;
+  if ((rc = launch_cone<T, D>(E, par, st)) || (rc = launch_q<T, D>(E, par, st))) return rc;
+  return launch_beta<T, D>(E, par, check, st, rhs_next);
 }
 
 // Residual partials at the iterate in q[qpar], then one finalize block per
@@ -717,17 +743,78 @@ int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
 // iteration's right-hand side. Returns through *rhs_next whether this one
 // computed the next iteration's (it does when it has no residual check and
 // `more` says another iteration follows in the same launch sequence).
+// What one iteration hands to the next inside a launch sequence: its
+// right-hand side already computed (sequential order), or its beta update
+// still to run (overlapped order).
+struct Carry {
+  bool rhs_ready = false;
+  bool beta_pending = false;
+};
+
+// Whether the executor runs the z-step beside the phi-step: needs the branch
+// streams, no kernel class being timed, no instance whose last axis takes the
+// one-lane elimination (it keeps its checkpoints in W plane 0, which the
+// z-step writes), and at least kOverlapMinNodes grid nodes in all. The fork
+// and the join cost about 10 us per iteration; below that size the kernels
+// they would overlap are shorter (measured per iteration: 2D 32x64^2 FP64
+// 55 -> 66 us overlapped; 2D 64x256^2 mixed 492 -> 474 us, FP64 789 -> 732 us,
+// the 64-instance 2D batch 1225 -> 1161 us).
+constexpr int64_t kOverlapMinNodes = int64_t(1) << 20;
+bool overlapped(const Exec& E) {
+  return E.graphs && !(E.prof && E.prof->cls >= 0) && E.ntri_long == 0 && E.nodes >= kOverlapMinNodes;
+}
+
+int branch_streams(GraphCache* g) {
+  if (!g->side) HIP_OK(hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking));
+  if (!g->cap_side) HIP_OK(hipStreamCreateWithFlags(&g->cap_side, hipStreamNonBlocking));
+  if (!g->fork) HIP_OK(hipEventCreateWithFlags(&g->fork, hipEventDisableTiming));
+  if (!g->join) HIP_OK(hipEventCreateWithFlags(&g->join, hipEventDisableTiming));
+  return DOT_OK;
+}
+
+// One iteration of every instance of E: Poisson solve, cone and updates, and
+// on check iterations the residual reductions and the control update.
+//
+// Sequential order (one stream): [rhs] passes | cone | q | beta (+ next rhs).
+// Overlapped order: the z-step reads only q and beta, so it runs on a second
+// stream (`side`, a parallel branch inside a captured graph) while the main
+// stream computes the right-hand side and the transforms; the beta update of
+// an iteration without a check is deferred to the side branch of the next
+// iteration, ahead of its z-step, beside the next right-hand side (the two
+// read q and alpha and write disjoint planes):
+//   main: rhs -> passes ------------\
+//   side: [beta of it-1] -> cone ----+-> q [-> beta -> resid -> finalize]
+// An iteration with a check, or the last one of a sequence (`more` false),
+// runs its beta update on the main stream, so that every sequence ends with a
+// complete iterate. Both orders compute the same values.
 template <typename T, int D>
-int one_iter(const Exec& E, int it, hipStream_t st, bool rhs_ready, bool more, bool* rhs_next) {
+int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more, Carry* cy) {
   const int par = it & 1;
-  int rc;
-  if ((rc = poisson_iter<T, D>(E, par, st, rhs_ready))) return rc;
   const int check = ((it + 1) % E.cadence) == 0;
+  int rc;
+  if (side) {
+    GraphCache* g = E.graphs;
+    HIP_OK(hipEventRecord(g->fork, st));
+    HIP_OK(hipStreamWaitEvent(side, g->fork, 0));
+    if (cy->beta_pending && (rc = launch_beta<T, D>(E, par ^ 1, 0, side, false))) return rc;
+    if ((rc = launch_cone<T, D>(E, par, side))) return rc;
+    HIP_OK(hipEventRecord(g->join, side));
+    if ((rc = poisson_iter<T, D>(E, par, st, false))) return rc;
+    HIP_OK(hipStreamWaitEvent(st, g->join, 0));
+    if ((rc = launch_q<T, D>(E, par, st))) return rc;
+    cy->beta_pending = !check && more;
+    if (!cy->beta_pending && (rc = launch_beta<T, D>(E, par, check, st, false))) return rc;
+    if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
+    cy->rhs_ready = false;
+    return DOT_OK;
+  }
+  if ((rc = poisson_iter<T, D>(E, par, st, cy->rhs_ready))) return rc;
   // kernel classes timed one by one run unfused
   const bool fuse = !check && more && !(E.prof && E.prof->cls >= 0);
   if ((rc = update_iter<T, D>(E, par, check, st, fuse))) return rc;
   if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
-  *rhs_next = fuse;
+  cy->rhs_ready = fuse;
+  cy->beta_pending = false;
   return DOT_OK;
 }
 
@@ -741,11 +828,17 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
   Ec.prof = nullptr;  // no events inside a captured graph
   if (!E.graphs->cap) HIP_OK(hipStreamCreateWithFlags(&E.graphs->cap, hipStreamNonBlocking));
   hipStream_t st = E.graphs->cap;
+  hipStream_t side = nullptr;
+  if (overlapped(Ec)) {
+    int rc0 = branch_streams(E.graphs);
+    if (rc0) return rc0;
+    side = E.graphs->cap_side;
+  }
   hipGraph_t graph = nullptr;
   HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   int rc = DOT_OK;
-  bool ready = false;
-  for (int k = 0; k < kGraphIters && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st, ready, k + 1 < kGraphIters, &ready);
+  Carry cy;
+  for (int k = 0; k < kGraphIters && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st, side, k + 1 < kGraphIters, &cy);
   hipError_t e = hipStreamEndCapture(st, &graph);
   if (rc) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -776,21 +869,30 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
     return true;
   };
   const bool graphs = E.graphs && E.graphs->enabled && !(E.prof && E.prof->cls >= 0) && E.cadence == 5;
+  hipStream_t side = nullptr;
+  if (overlapped(E)) {
+    int rc0 = branch_streams(E.graphs);
+    if (rc0) return rc0;
+    side = E.graphs->side;
+  }
   int j = 0;
   int since_poll = 0;
-  bool ready = false;  // this iteration's right-hand side was computed by the previous beta launch
+  Carry cy;  // what the previous iteration left to this one
   while (j < max_iters) {
     const int it = it0 + j;
     int rc;
-    if (graphs && E.graphs->warm && it % kGraphIters == 0 && max_iters - j >= kGraphIters) {
+    if (graphs && E.graphs->warm && it % kGraphIters == 0 && max_iters - j >= kGraphIters && !cy.rhs_ready &&
+        !cy.beta_pending) {
       hipGraphExec_t& ex = E.graphs->exec;
       if (!ex && (rc = capture_block<T, D>(E, it, &ex))) return rc;
       HIP_OK(hipGraphLaunch(ex, st));
-      ready = false;  // a block starts with its own right-hand side and ends with a check
+      // a block starts with its own right-hand side and ends with a check
       j += kGraphIters;
       since_poll += kGraphIters;
     } else {
-      if ((rc = one_iter<T, D>(E, it, st, ready, j + 1 < max_iters, &ready))) return rc;
+      // an iteration before a poll completes its iterate (nothing deferred)
+      const bool more = j + 1 < max_iters && since_poll + 1 < poll;
+      if ((rc = one_iter<T, D>(E, it, st, side, more, &cy))) return rc;
       if (E.graphs) E.graphs->warm = true;
       ++j;
       ++since_poll;
@@ -867,6 +969,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.grid_nodes = (unsigned)P->nblocks;
   E.ntri = P->tri ? 1 : 0;
   E.ntri_long = P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
+  E.nodes = P->g.nb;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = nullptr;
     const AxisGeom ag = P->precision == DOT_FP64 ? axis_geom<double>(&P, 1, a, P->sched)
@@ -916,7 +1019,10 @@ struct RunF {
 template <typename T>
 Inst<T> step_inst(dot_plan* P, const void* phi, const void* q, const void* alpha, const void* beta, void* q_out,
                   void* W, Ctl* ctl) {
-  return inst_of<T>(P, (double*)phi, (T*)P->step_scratch, (T*)q, (T*)q_out, (double*)alpha, (T*)beta, (T*)W, ctl,
+  // a caller's z-step workspace: 4D planes of the bulk type, then one FP64 plane
+  double* dw = W ? reinterpret_cast<double*>(static_cast<char*>(W) + (size_t)(4 * P->D) * P->g.nb * sizeof(T))
+                 : nullptr;
+  return inst_of<T>(P, (double*)phi, (T*)P->step_scratch, (T*)q, (T*)q_out, (double*)alpha, (T*)beta, (T*)W, dw, ctl,
                     P->step_partials);
 }
 
@@ -1054,7 +1160,7 @@ struct ResidNoAllocF {
                        (int)(sizeof(Ctl) / sizeof(uint32_t)));
     HIP_OK(hipGetLastError());
     int rc = upload_inst(E, inst_of<T>(P, (double*)phi, (T*)nullptr, (T*)q, (T*)nullptr, (double*)alpha, (T*)beta,
-                                       (T*)nullptr, ctl, partials),
+                                       (T*)nullptr, (double*)nullptr, ctl, partials),
                          st);
     if (rc) return rc;
     hipLaunchKernelGGL((kb_zres<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
@@ -1179,9 +1285,11 @@ int batch_layout(dot_batch* B, const Sched& s) {
   E.grid_nodes = (unsigned)map_off[0];
   E.ntri = 0;
   E.ntri_long = 0;
+  E.nodes = 0;
   for (int i = 0; i < count; ++i) {
     E.ntri += plans[i]->tri ? 1 : 0;
     E.ntri_long += plans[i]->tri && plans[i]->g.N[plans[i]->D] > kTriPartMaxNodes ? 1 : 0;
+    E.nodes += plans[i]->g.nb;
   }
   E.map_nodes = B->d_maps;
   for (int a = 0; a <= B->D; ++a) {
@@ -1550,7 +1658,7 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   rc = P->precision == DOT_FP64 ? build_eigs<double>(P.get()) : build_eigs<float>(P.get());
   if (rc) return rc;
   // state layout: phi (FP64) | scratch (mixed) | q (D+1) | q_new (D+1) | alpha (D+1, FP64) | beta (K) |
-  // W (4D) | control block | partials (the same arithmetic as dot_footprint_bytes)
+  // W (4D) | dw (FP64) | control block | partials (the same arithmetic as dot_footprint_bytes)
   const size_t pb = (size_t)g.nb * P->scalar_bytes;
   P->off_phi = 0;
   P->off_scr = align256((size_t)g.nb * sizeof(double));
@@ -1563,7 +1671,8 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   set_sweep(g, default_tc(g.nx, g.N[0]));
   P->nblocks = g.nsweep;
   P->partial_rows = (int64_t)g.nxb * g.N[0];
-  P->ctl_offset = align256(P->off_w + (size_t)(4 * D) * pb);
+  P->off_dw = align256(P->off_w + (size_t)(4 * D) * pb);
+  P->ctl_offset = align256(P->off_dw + (size_t)g.nb * sizeof(double));
   P->partials_offset = P->ctl_offset + align256(sizeof(Ctl));
   P->state_bytes = P->partials_offset + align256((size_t)P->partial_rows * kNumSums * sizeof(double));
   if (P->precision == DOT_MIXED) HIP_OK(hipMalloc(&P->step_scratch, pb));
@@ -2204,7 +2313,7 @@ int promote_impl(const dot_plan* M, const void* mixed_state, const Ctl* mctl, do
   int rc = widen(M->off_q, F->off_q, (int64_t)(2 * (D + 1)) * nb);
   if (rc || (rc = widen(M->off_beta, F->off_beta, (int64_t)M->K * nb))) return rc;
   // the W planes only carry values inside an iteration
-  HIP_OK(hipMemsetAsync(fs + F->off_w, 0, (size_t)(4 * D) * nb * 8, st));
+  HIP_OK(hipMemsetAsync(fs + F->off_w, 0, F->ctl_offset - F->off_w, st));
   // control block: the FP64 plan's parameters, the iterate's sigma, counters
   // and sigma schedule
   HIP_OK(hipMemcpyAsync(M->host_ctl, mctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -2513,6 +2622,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
   for (dot_plan* P : act) {
     E.ntri += P->tri ? 1 : 0;
     E.ntri_long += P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
+    E.nodes += P->g.nb;
   }
   size_t map_off[kMaxAxes] = {0, 0, 0, 0};
   for (int a = 0; a <= C->D; ++a) {
@@ -2696,6 +2806,7 @@ size_t dot_footprint_bytes(const dot_problem* p) {
   s = align256(s + (size_t)(2 * (D + 1)) * pb);              // q, q_new
   s += (size_t)(D + 1) * nb * 8;                             // alpha (FP64)
   s += (size_t)(4 * D + 2 + 4 * D) * pb;                     // beta, W
+  s = align256(s) + nb * 8;                                  // w_{K-1} - w_0 (FP64)
   s = align256(s) + align256(sizeof(Ctl));
   s += align256((nb / ((size_t)p->n[0] + 1) + kBlock - 1) / kBlock * ((size_t)p->n[0] + 1) * kNumSums *
                 sizeof(double));

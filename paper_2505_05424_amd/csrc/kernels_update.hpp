@@ -155,74 +155,72 @@ __device__ __forceinline__ void cone_arg(const T (&bt)[4 * D + 2], double q0, co
   }
 }
 
-// a1 + a2 + q0 part of a5 per cell: z = Pi(u); w = z - d + beta/sigma;
-// q0_new = (A_0 phi + alpha0/sigma + w_{K-1} - w_0) / 3 and the alpha0
-// update; the weighted components sqrt(omega/2) w_{d,v} go to W for the q_d
-// update.
+// a1 + a2 per cell (the z-step of Algorithm 2): z = Pi(u), w = z - d + beta/sigma;
+// the weighted components sqrt(omega/2) w_{d,v} go to the W planes (for the
+// q_d update) and w_{K-1} - w_0 to the FP64 plane DW (for the q0 update: in
+// the storage type its rounding would enter every alpha0 increment, which
+// near convergence are smaller than that rounding). Reads only q and beta, so
+// it may run while the phi-step is being solved.
 template <typename T, int D>
-__device__ __forceinline__ void cone_q0_body(const Geo& g, const double* __restrict__ phi_, const T* __restrict__ q_,
-                                             double* __restrict__ alpha_, const T* __restrict__ beta_,
-                                             const double* __restrict__ sw_sp, T* __restrict__ qn_, T* __restrict__ W_,
-                                             const Ctl* __restrict__ ctl, uint32_t blk) {
+__device__ __forceinline__ void cone_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ beta_,
+                                          const double* __restrict__ sw_sp, T* __restrict__ W_,
+                                          double* __restrict__ DW_, const Ctl* __restrict__ ctl, uint32_t blk) {
   constexpr int K = 4 * D + 2;
   const Column c = column_of<D>(g, blk);
   const int tend = min(c.t1, g.n[0]);
   if (!c.live || c.t0 >= tend) return;
-  gp<const double> phi = glob(phi_);
   gp<const T> q = glob(q_);
-  gp<double> alpha = glob(alpha_);
   gp<const T> beta = glob(beta_);
-  gp<T> qn = glob(qn_);
   gp<T> W = glob(W_);
+  gp<double> DW = glob(DW_);
   const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
-  const double sigma = glob(ctl)->sigma, tau = glob(ctl)->tau, inv_sigma = 1.0 / sigma;
+  const double inv_sigma = 1.0 / glob(ctl)->sigma;
   const double sw = glob(sw_sp)[c.xs];
   uint32_t i = (uint32_t)c.t0 * nx + c.xs;
   T fa[kMaxAxes][2], fb[kMaxAxes][2];
   load_fq<T, D>(g, q, i, c, fa);
-  double ph = phi[i];
   for (int t = c.t0; t < tend; ++t, i += nx) {
     load_fq<T, D>(g, q, i + nx, c, fb);
-    const double ph1 = phi[i + nx];
     T bt[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) bt[k] = beta[(size_t)k * nb + i];
     const double q0 = (double)q[i];
-    const double a0 = alpha[i];
     double u[K];
     cone_arg<T, D>(bt, q0, fa, fb, sw, inv_sigma, u);
     soc_project<K>(u);
     const double w0 = u[0] - 1.0 + (double)bt[0] * inv_sigma;
     const double wl = u[K - 1] - 1.0 + (double)bt[K - 1] * inv_sigma;
-    const double g0 = (ph1 - ph) * g.inv_h[0];
-    const double q0n = (g0 + a0 * inv_sigma + wl - w0) * (1.0 / 3.0);
-    qn[i] = (T)q0n;
-    alpha[i] = a0 + tau * sigma * (g0 - q0n);
 #pragma unroll
     for (int k = 1; k < K - 1; ++k) W[(size_t)(k - 1) * nb + i] = (T)(sw * (u[k] + (double)bt[k] * inv_sigma));
+    DW[i] = wl - w0;
     shift_fq<T, D>(fa, fb);
-    ph = ph1;
   }
 }
 
 // q_d update (d >= 1) of a5 per node: rhs = A_d phi + alpha_d/sigma + the four
 // adjacent cells' weighted w components; diagonal 1 + 1/2 sum of omega over
-// the adjacent cells (Prop. 3.2 with weights); alpha_d update. The loads of
-// slice t+1 are issued before slice t is computed (two slices in flight).
+// the adjacent cells (Prop. 3.2 with weights); alpha_d update; q0 as in the
+// paper's diagonal 3. The loads of slice t+1 are issued before slice t is
+// computed (two slices in flight).
 template <typename T, int D>
 struct QdSlice {
   double ph;
   double phd[kMaxAxes];  // phi[i + e_d]
   T w[kMaxAxes][4];      // W_{d,v} of the adjacent cells (0 where absent)
   double ad[kMaxAxes];   // alpha_d
+  double a0;             // alpha0 of the cell (t < n0)
+  double dw;             // w_{K-1} - w_0 of the cell (t < n0)
 };
 
 template <typename T, int D>
 __device__ __forceinline__ void qd_load(const Geo& g, const Column& c, int t, uint32_t i, gp<const double> phi,
-                                        gp<const double> alpha, gp<const T> W, QdSlice<T, D>& s) {
+                                        gp<const double> alpha, gp<const T> W, gp<const double> DW,
+                                        QdSlice<T, D>& s) {
   const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
   const bool has_now = t < g.n[0], has_prev = t >= 1;
   s.ph = phi[i];
+  s.a0 = has_now ? alpha[i] : 0.0;
+  s.dw = has_now ? DW[i] : 0.0;
 #pragma unroll
   for (int d = 1; d <= D; ++d) {
     const bool in = c.x[d] < g.n[d];
@@ -237,16 +235,22 @@ __device__ __forceinline__ void qd_load(const Geo& g, const Column& c, int t, ui
   }
 }
 
+// q update of a5 per node (the q-step of Algorithm 2 with the diagonal of
+// Prop. 3.2) and the alpha update: q0 and alpha0 at the cell (t < n0) from
+// A_0 phi, alpha0 and w_{K-1} - w_0; q_d and alpha_d (d >= 1) from A_d phi,
+// alpha_d and the adjacent cells' weighted w components.
 template <typename T, int D>
-__device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__ phi_, double* __restrict__ alpha_,
-                                        const double* __restrict__ om_sp, T* __restrict__ qn_,
-                                        const T* __restrict__ W_, const Ctl* __restrict__ ctl, uint32_t blk) {
+__device__ __forceinline__ void q_body(const Geo& g, const double* __restrict__ phi_, double* __restrict__ alpha_,
+                                       const double* __restrict__ om_sp, T* __restrict__ qn_,
+                                       const T* __restrict__ W_, const double* __restrict__ DW_,
+                                       const Ctl* __restrict__ ctl, uint32_t blk) {
   const Column c = column_of<D>(g, blk);
   if (!c.live) return;
   gp<const double> phi = glob(phi_);
   gp<double> alpha = glob(alpha_);
   gp<T> qn = glob(qn_);
   gp<const T> W = glob(W_);
+  gp<const double> DW = glob(DW_);
   gp<const double> om = glob(om_sp);
   const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
   const double sigma = glob(ctl)->sigma, tau = glob(ctl)->tau, inv_sigma = 1.0 / sigma;
@@ -255,12 +259,20 @@ __device__ __forceinline__ void qd_body(const Geo& g, const double* __restrict__
   for (int d = 1; d <= D; ++d) om_b[d] = c.x[d] < g.n[d] ? om[c.xs + (uint32_t)g.stride[d]] : 0.0;
   uint32_t i = (uint32_t)c.t0 * nx + c.xs;
   QdSlice<T, D> cur, nxt;
-  qd_load<T, D>(g, c, c.t0, i, phi, alpha, W, cur);
+  qd_load<T, D>(g, c, c.t0, i, phi, alpha, W, DW, cur);
   for (int t = c.t0; t < c.t1; ++t, i += nx) {
-    if (t + 1 < c.t1) qd_load<T, D>(g, c, t + 1, i + nx, phi, alpha, W, nxt);
+    const bool more = t + 1 < c.t1;
+    if (more) qd_load<T, D>(g, c, t + 1, i + nx, phi, alpha, W, DW, nxt);
     const bool has_now = t < g.n[0];
     const bool has_prev = t >= 1;
     const double ct = (double)has_now + (double)has_prev;
+    if (has_now) {
+      const double ph1 = more ? nxt.ph : phi[i + nx];
+      const double g0 = (ph1 - cur.ph) * g.inv_h[0];
+      const double q0n = (g0 + cur.a0 * inv_sigma + cur.dw) * (1.0 / 3.0);
+      qn[i] = (T)q0n;
+      alpha[i] = cur.a0 + tau * sigma * (g0 - q0n);
+    }
 #pragma unroll
     for (int d = 1; d <= D; ++d) {
       if (c.x[d] >= g.n[d]) continue;

@@ -35,10 +35,10 @@ def kernel_bytes(D: int, n: Sequence[int], w: int) -> Dict[str, float]:
         "dct_last": 2 * w * Nc,
         # D launches: D-1 plain inverse passes and the time-axis one
         "dct_inv": ((D - 1) * 2 * w * Nc + last_inv) / D,
-        # cone: read q, beta, phi, alpha0; write q0_new, alpha0, 4D weighted w planes
-        "cone": w * (Q + K * S + S + 4 * D * S) + 2 * a * S + 8 * Nc,
-        # q_d: read phi, alpha_d, w planes; write q_d, alpha_d
-        "qd": w * (Qb + 4 * D * S) + 2 * a * Qb + 8 * Nc,
+        # cone (z-step): read q, beta; write 4D weighted w planes and w_{K-1} - w_0
+        "cone": w * (Q + K * S + (4 * D + 1) * S),
+        # q-step: read phi, alpha, the 4D + 1 w planes; write q, alpha
+        "qd": w * (Q + (4 * D + 1) * S) + 2 * a * Q + 8 * Nc,
         # beta: read q_old, q_new, beta; write beta
         "beta": w * (2 * Q + 2 * K * S),
         # residual partials: read phi, q, alpha, beta

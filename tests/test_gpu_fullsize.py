@@ -85,7 +85,7 @@ def test_3d_32x64x64x64_steps(serving3d):
     # a5
     phd = G.dev(B.to_box(phi, g.n))
     qo = G.dev(np.zeros((g.D + 1,) + g.node_shape))
-    wd = G.dev(np.zeros((4 * g.D,) + g.node_shape))
+    wd = G.dev(np.zeros((4 * g.D + 1,) + g.node_shape))
     B.dot_step_update(plan, phd.data_ptr(), qd.data_ptr(), ad.data_ptr(), bed.data_ptr(), sigma, tau,
                       qo.data_ptr(), wd.data_ptr(), st)
     qn = O.step_q(P, phi, z_ref, al, be, sigma)

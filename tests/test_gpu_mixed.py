@@ -75,7 +75,7 @@ def test_mixed_steps(name):
     # a5 with an FP64 phi
     pd = G.dev(B.to_box(phi, g.n))
     qo = G.dev(np.zeros((g.D + 1,) + g.node_shape, dtype=f32))
-    wd = G.dev(np.zeros((4 * g.D,) + g.node_shape, dtype=f32))
+    wd = G.dev(np.zeros((4 * g.D + 2,) + g.node_shape, dtype=f32))  # 4D FP32 planes, then one FP64
     B.dot_step_update(plan, pd.data_ptr(), qd.data_ptr(), ad.data_ptr(), bed.data_ptr(), sigma, tau,
                       qo.data_ptr(), wd.data_ptr(), st)
     qn = O.step_q(P, phi, z_ref, al, be, sigma)

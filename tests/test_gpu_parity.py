@@ -118,7 +118,7 @@ def test_step_update(name):
     ad = G.dev(G.planes_of(al, g.n))
     bed = G.dev(G.planes_of(list(be), g.n))
     qo = G.dev(np.zeros((g.D + 1,) + g.node_shape))
-    wd = G.dev(np.zeros((4 * g.D,) + g.node_shape))
+    wd = G.dev(np.zeros((4 * g.D + 1,) + g.node_shape))
     B.dot_step_update(plan, pd.data_ptr(), qd.data_ptr(), ad.data_ptr(), bed.data_ptr(), sigma, tau,
                       qo.data_ptr(), wd.data_ptr(), st)
     S = O.State(phi, np.zeros_like(be), q, al, be, sigma)
