@@ -420,7 +420,11 @@ std::vector<std::pair<int, int>> axis_candidates(dot_plan* const* plans, int cou
 // Last axes of at least this many nodes are solved by tridiagonal elimination
 // (its cost per point does not grow with the axis length; measured per
 // iteration: 2D 32x1024^2 mixed 6.15 -> 5.13 ms, 2D 64x256^2 FP64 844 -> 823 us,
-// mixed 534 -> 531 us; slower than the folded transform at 129 nodes and below).
+// mixed 534 -> 531 us). With the partitioned elimination also taking the
+// shorter last axes (threshold 33 instead of 257), per iteration: 2D 32x64^2
+// FP64 55.6 us either way, 2D 64x128^2 mixed 145.6 -> 133.7 us, but 3D 32x64^3
+// mixed 1227 -> 1291 us and the 64-instance 2D batch 1181 -> 1264 us; the
+// transform keeps the short axes.
 constexpr int kTriMinNodes = 257;
 
 double axis_eig(int N, int nseg, int k) {

@@ -694,10 +694,13 @@ __device__ __forceinline__ void tri_part_body(const Geo& g, T* __restrict__ plan
     const int tot = nl * L;
     {
       // coalesced copy of the round's lines into LDS; every thread issues its
-      // loads before the first LDS write (L > kTriThreads: element e + 256 is
-      // on the same line or the next)
+      // loads before the first LDS write
       T v[kTriLoadPer];
-      int i = threadIdx.x, ln = 0;
+      int i = threadIdx.x, ln = 0;  // line ln, node i of element threadIdx.x
+      while (i >= L) {
+        i -= L;
+        ++ln;
+      }
 #pragma unroll
       for (int r = 0; r < kTriLoadPer; ++r) {
         const int e = threadIdx.x + r * kTriThreads;
@@ -708,7 +711,7 @@ __device__ __forceinline__ void tri_part_body(const Geo& g, T* __restrict__ plan
         const int e = threadIdx.x + r * kTriThreads;
         if (e < tot) buf[ln * Lp + tri_pad(i)] = (double)v[r];
         i += kTriThreads;
-        if (i >= L) {
+        while (i >= L) {
           i -= L;
           ++ln;
         }
@@ -830,12 +833,16 @@ __device__ __forceinline__ void tri_part_body(const Geo& g, T* __restrict__ plan
     __syncthreads();
     {
       int i = threadIdx.x, ln = 0;
+      while (i >= L) {
+        i -= L;
+        ++ln;
+      }
 #pragma unroll
       for (int r = 0; r < kTriLoadPer; ++r) {
         const int e = threadIdx.x + r * kTriThreads;
         if (e < tot) pl[base + e] = (T)buf[ln * Lp + tri_pad(i)];
         i += kTriThreads;
-        if (i >= L) {
+        while (i >= L) {
           i -= L;
           ++ln;
         }
