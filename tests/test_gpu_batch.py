@@ -107,3 +107,46 @@ def test_batch_mixing_tridiagonal_and_transform_last_axes(prec):
         assert np.array_equal(rb, rho), i
         for a, b in zip(mb, m):
             assert np.array_equal(a, b), i
+
+
+@pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
+def test_overlapped_order_gives_the_sequential_bits(prec):
+    """From 2^20 grid nodes an executor runs the z-step on a second graph
+    branch beside the phi-step and defers beta updates; the same kernels in the
+    one-stream order (a kernel class being timed switches to it) give bitwise
+    the same iterates. Also a batch large enough to overlap against each member
+    solved alone below the threshold (one stream)."""
+    big = dotgen.tiny_instance(2, (16, 256, 256), seed=41, floor=0.0, n_comp=3)  # 1.12 M nodes
+    small = dotgen.tiny_instance(2, (8, 20, 24), seed=42, floor=0.0, masked=True)
+    iters = 60
+    st = G.stream_handle()
+    print(f"[case] overlapped vs sequential precision={prec}", flush=True)
+    plan = B.dot_plan_create(big.D, big.n, big.rho0, big.rho1, big.mask, tol=-1.0, max_iter=10 ** 6, precision=prec)
+    a, b = G.GpuState(plan), G.GpuState(plan)
+    a.reset()
+    ra = a.run(iters)                                    # overlapped (graphs)
+    B.dot_profile_select(plan, B.KERNEL_CLASSES["cone"])  # one stream, every class its own launch
+    b.reset()
+    rb = b.run(iters)
+    B.dot_profile_select(plan, -1)
+    for k in ("objective", "eta_dot", "sigma", "iters", "checks"):
+        assert getattr(ra, k) == getattr(rb, k), k
+    assert np.array_equal(G.host(a.buf)[:plan.info.off_w], G.host(b.buf)[:plan.info.off_w])
+    # a batch of both (over the threshold) against each alone
+    torch = G.torch_mod()
+    batch = B.dot_batch_create([big, small], tol=-1.0, max_iter=10 ** 6, precision=prec)
+    ws = torch.zeros(int(batch.workspace_bytes), dtype=torch.uint8, device="cuda")
+    B.dot_batch_reset(batch, ws.data_ptr(), st)
+    res = B.dot_batch_run(batch, ws.data_ptr(), iters, st)
+    for i, inst in enumerate((big, small)):
+        p = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=-1.0, max_iter=10 ** 6,
+                              precision=prec)
+        s = G.GpuState(p)
+        s.reset()
+        r = s.run(iters)
+        assert res[i].objective == r.objective and res[i].eta_dot == r.eta_dot and res[i].sigma == r.sigma, i
+        rho_b, m_b = B.dot_batch_extract(batch, ws.data_ptr(), i, st)
+        rho, m = s.extract()
+        assert np.array_equal(rho_b, rho), i
+        for x, y in zip(m_b, m):
+            assert np.array_equal(x, y), i
