@@ -95,6 +95,31 @@ kb_beta_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int
   rhs_body<T, D, DEFECT>(s.g, s.q[par ^ 1], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
 }
 
+// beta update of iteration it (parity par, no residual check) and the z-step
+// of iteration it + 1 (parity par ^ 1) in one sweep.
+template <typename T, int D>
+__global__ void __launch_bounds__(256)
+kb_beta_cone(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[inst_of_block(map, L)];
+  if (stopped(s)) return;
+  beta_cone_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.W, s.dw, s.ctl, L - s.blk0);
+}
+
+// kb_beta_cone and the right-hand side of iteration it + 1 in one launch (the
+// right-hand side reads the new q, alpha and phi, none of which the other
+// two steps write).
+template <typename T, int D, bool DEFECT>
+__global__ void __launch_bounds__(256)
+kb_beta_cone_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[inst_of_block(map, L)];
+  if (stopped(s)) return;
+  const double inv_sigma = 1.0 / glob(s.ctl)->sigma;
+  beta_cone_body<T, D>(s.g, s.q[par], s.q[par ^ 1], s.beta, s.sw, s.W, s.dw, s.ctl, L - s.blk0);
+  rhs_body<T, D, DEFECT>(s.g, s.q[par ^ 1], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
+}
+
 // Right-hand side (or its defect against phi) of the Poisson solve into the
 // transform work plane, from (q[par], alpha).
 template <typename T, int D, bool DEFECT>

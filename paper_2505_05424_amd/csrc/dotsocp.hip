@@ -700,17 +700,23 @@ int launch_q(const Exec& E, int par, hipStream_t st) {
 }
 
 // beta update of the iteration with parity par (q[par] the old q, q[par ^ 1]
-// the new one); with rhs_next also the right-hand side of the next iteration.
+// the new one); with cone_next also the z-step of the next iteration, with
+// rhs_next also its right-hand side (both only after an iteration without a
+// check).
 template <typename T, int D>
-int launch_beta(const Exec& E, int par, int check, hipStream_t st, bool rhs_next) {
+int launch_beta(const Exec& E, int par, int check, hipStream_t st, bool rhs_next, bool cone_next = false) {
   const Inst<T>* I = (const Inst<T>*)E.d_inst;
+  constexpr bool kMixed = !std::is_same<T, double>::value;
   ProfScope ps(E.prof, DOT_K_BETA, st);
-  if (rhs_next) {
-    constexpr bool kMixed = !std::is_same<T, double>::value;
+  if (cone_next && rhs_next)
+    hipLaunchKernelGGL((kb_beta_cone_rhs<T, D, kMixed>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes,
+                       par);
+  else if (cone_next)
+    hipLaunchKernelGGL((kb_beta_cone<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
+  else if (rhs_next)
     hipLaunchKernelGGL((kb_beta_rhs<T, D, kMixed>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par);
-  } else {
+  else
     hipLaunchKernelGGL((kb_beta<T, D>), dim3(E.grid_nodes), dim3(kBlock), 0, st, I, E.map_nodes, par, check);
-  }
   HIP_OK(hipGetLastError());
   return DOT_OK;
 }
@@ -741,17 +747,13 @@ int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
   return DOT_OK;
 }
 
-// One iteration of every instance of E: Poisson solve, cone and updates, and
-// on check iterations the residual reductions and the control update.
-// rhs_ready: the previous iteration's beta launch already computed this
-// iteration's right-hand side. Returns through *rhs_next whether this one
-// computed the next iteration's (it does when it has no residual check and
-// `more` says another iteration follows in the same launch sequence).
 // What one iteration hands to the next inside a launch sequence: its
-// right-hand side already computed (sequential order), or its beta update
-// still to run (overlapped order).
+// right-hand side and its z-step already computed by the previous beta
+// launch (sequential order), or the previous beta update still to run, fused
+// with this iteration's z-step (overlapped order).
 struct Carry {
   bool rhs_ready = false;
+  bool cone_ready = false;
   bool beta_pending = false;
 };
 
@@ -779,18 +781,24 @@ int branch_streams(GraphCache* g) {
 // One iteration of every instance of E: Poisson solve, cone and updates, and
 // on check iterations the residual reductions and the control update.
 //
-// Sequential order (one stream): [rhs] passes | cone | q | beta (+ next rhs).
+// Sequential order (one stream): [rhs] passes [cone] q beta, where an
+// iteration without a check followed by another in the same sequence (`more`)
+// runs the next iteration's z-step and right-hand side in its beta launch
+// (the z-step reads only the new q and beta; the right-hand side the new q,
+// alpha and phi). An executor with an instance whose last axis takes the
+// one-lane elimination keeps the z-step after the passes (those keep their
+// checkpoints in W plane 0) and fuses only the right-hand side.
 // Overlapped order: the z-step reads only q and beta, so it runs on a second
 // stream (`side`, a parallel branch inside a captured graph) while the main
 // stream computes the right-hand side and the transforms; the beta update of
 // an iteration without a check is deferred to the side branch of the next
-// iteration, ahead of its z-step, beside the next right-hand side (the two
+// iteration, fused with its z-step, beside the next right-hand side (the two
 // read q and alpha and write disjoint planes):
-//   main: rhs -> passes ------------\
-//   side: [beta of it-1] -> cone ----+-> q [-> beta -> resid -> finalize]
+//   main: rhs -> passes ---------------\
+//   side: [beta of it-1 +] cone --------+-> q [-> beta -> resid -> finalize]
 // An iteration with a check, or the last one of a sequence (`more` false),
-// runs its beta update on the main stream, so that every sequence ends with a
-// complete iterate. Both orders compute the same values.
+// runs its beta update alone, so that every sequence ends with a complete
+// iterate. All orders compute the same values.
 template <typename T, int D>
 int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more, Carry* cy) {
   const int par = it & 1;
@@ -800,8 +808,11 @@ int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more,
     GraphCache* g = E.graphs;
     HIP_OK(hipEventRecord(g->fork, st));
     HIP_OK(hipStreamWaitEvent(side, g->fork, 0));
-    if (cy->beta_pending && (rc = launch_beta<T, D>(E, par ^ 1, 0, side, false))) return rc;
-    if ((rc = launch_cone<T, D>(E, par, side))) return rc;
+    if (cy->beta_pending)
+      rc = launch_beta<T, D>(E, par ^ 1, 0, side, false, true);
+    else
+      rc = launch_cone<T, D>(E, par, side);
+    if (rc) return rc;
     HIP_OK(hipEventRecord(g->join, side));
     if ((rc = poisson_iter<T, D>(E, par, st, false))) return rc;
     HIP_OK(hipStreamWaitEvent(st, g->join, 0));
@@ -810,14 +821,19 @@ int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more,
     if (!cy->beta_pending && (rc = launch_beta<T, D>(E, par, check, st, false))) return rc;
     if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
     cy->rhs_ready = false;
+    cy->cone_ready = false;
     return DOT_OK;
   }
   if ((rc = poisson_iter<T, D>(E, par, st, cy->rhs_ready))) return rc;
+  if (!cy->cone_ready && (rc = launch_cone<T, D>(E, par, st))) return rc;
+  if ((rc = launch_q<T, D>(E, par, st))) return rc;
   // kernel classes timed one by one run unfused
   const bool fuse = !check && more && !(E.prof && E.prof->cls >= 0);
-  if ((rc = update_iter<T, D>(E, par, check, st, fuse))) return rc;
+  const bool fuse_cone = fuse && E.ntri_long == 0;
+  if ((rc = launch_beta<T, D>(E, par, check, st, fuse, fuse_cone))) return rc;
   if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;
   cy->rhs_ready = fuse;
+  cy->cone_ready = fuse_cone;
   cy->beta_pending = false;
   return DOT_OK;
 }
@@ -886,7 +902,7 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
     const int it = it0 + j;
     int rc;
     if (graphs && E.graphs->warm && it % kGraphIters == 0 && max_iters - j >= kGraphIters && !cy.rhs_ready &&
-        !cy.beta_pending) {
+        !cy.cone_ready && !cy.beta_pending) {
       hipGraphExec_t& ex = E.graphs->exec;
       if (!ex && (rc = capture_block<T, D>(E, it, &ex))) return rc;
       HIP_OK(hipGraphLaunch(ex, st));

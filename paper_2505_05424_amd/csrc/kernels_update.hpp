@@ -155,12 +155,25 @@ __device__ __forceinline__ void cone_arg(const T (&bt)[4 * D + 2], double q0, co
   }
 }
 
-// a1 + a2 per cell (the z-step of Algorithm 2): z = Pi(u), w = z - d + beta/sigma;
-// the weighted components sqrt(omega/2) w_{d,v} go to the W planes (for the
-// q_d update) and w_{K-1} - w_0 to the FP64 plane DW (for the q0 update: in
-// the storage type its rounding would enter every alpha0 increment, which
-// near convergence are smaller than that rounding). Reads only q and beta, so
-// it may run while the phi-step is being solved.
+// z-step output of one cell from its projected u = Pi(...) and the beta
+// values bt the argument was formed with: w = z - d + beta/sigma; the
+// weighted components sqrt(omega/2) w_{d,v} go to the W planes (for the q_d
+// update) and w_{K-1} - w_0 to the FP64 plane DW (for the q0 update: in the
+// storage type its rounding would enter every alpha0 increment, which near
+// convergence are smaller than that rounding).
+template <typename T, int D>
+__device__ __forceinline__ void cone_store(const double (&u)[4 * D + 2], const T (&bt)[4 * D + 2], double sw,
+                                           double inv_sigma, gp<T> W, gp<double> DW, uint32_t nb, uint32_t i) {
+  constexpr int K = 4 * D + 2;
+  const double w0 = u[0] - 1.0 + (double)bt[0] * inv_sigma;
+  const double wl = u[K - 1] - 1.0 + (double)bt[K - 1] * inv_sigma;
+#pragma unroll
+  for (int k = 1; k < K - 1; ++k) W[(size_t)(k - 1) * nb + i] = (T)(sw * (u[k] + (double)bt[k] * inv_sigma));
+  DW[i] = wl - w0;
+}
+
+// a1 + a2 per cell (the z-step of Algorithm 2): z = Pi(u), then cone_store.
+// Reads only q and beta, so it may run while the phi-step is being solved.
 template <typename T, int D>
 __device__ __forceinline__ void cone_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ beta_,
                                           const double* __restrict__ sw_sp, T* __restrict__ W_,
@@ -188,11 +201,7 @@ __device__ __forceinline__ void cone_body(const Geo& g, const T* __restrict__ q_
     double u[K];
     cone_arg<T, D>(bt, q0, fa, fb, sw, inv_sigma, u);
     soc_project<K>(u);
-    const double w0 = u[0] - 1.0 + (double)bt[0] * inv_sigma;
-    const double wl = u[K - 1] - 1.0 + (double)bt[K - 1] * inv_sigma;
-#pragma unroll
-    for (int k = 1; k < K - 1; ++k) W[(size_t)(k - 1) * nb + i] = (T)(sw * (u[k] + (double)bt[k] * inv_sigma));
-    DW[i] = wl - w0;
+    cone_store<T, D>(u, bt, sw, inv_sigma, W, DW, nb, i);
     shift_fq<T, D>(fa, fb);
   }
 }
@@ -442,9 +451,39 @@ __device__ __forceinline__ void block_slot11(double v, double* __restrict__ part
   }
 }
 
-// beta update of a5 per cell: z recomputed from the old (q, beta),
-// beta += tau sigma (z - B F q_new - d); at residual checks the block sums of
-// |z - B F q_new - d|^2 go to partials slot 11. Block 0 counts the iteration.
+// beta update of a5 at one cell: z = Pi(u) from the old q (q0o, F q values
+// fa / fb of slices t and t+1) and the old beta bt, then
+// beta += tau sigma (z - B F q_new - d) with the new q (q0n, ga / gb) into bn;
+// ssq accumulates |z - B F q_new - d|^2.
+template <typename T, int D>
+__device__ __forceinline__ void beta_cell(const T (&bt)[4 * D + 2], double q0o, const T (&fa)[kMaxAxes][2],
+                                          const T (&fb)[kMaxAxes][2], double q0n, const T (&ga)[kMaxAxes][2],
+                                          const T (&gb)[kMaxAxes][2], double sw, double sigma, double tau,
+                                          double inv_sigma, double& ssq, T (&bn)[4 * D + 2]) {
+  constexpr int K = 4 * D + 2;
+  double u[K];
+  cone_arg<T, D>(bt, q0o, fa, fb, sw, inv_sigma, u);
+  soc_project<K>(u);
+  auto upd = [&](int k, double bq) {
+    const double r = u[k] - bq;
+    ssq = fma(r, r, ssq);
+    bn[k] = (T)((double)bt[k] + tau * sigma * r);
+  };
+  upd(0, 1.0 - q0n);
+#pragma unroll
+  for (int d = 1; d <= D; ++d) {
+    const int k = 1 + 4 * (d - 1);
+    upd(k + 0, sw * (double)ga[d][0]);
+    upd(k + 1, sw * (double)ga[d][1]);
+    upd(k + 2, sw * (double)gb[d][0]);
+    upd(k + 3, sw * (double)gb[d][1]);
+  }
+  upd(K - 1, 1.0 + q0n);
+}
+
+// beta update of a5 per cell (z recomputed from the old q and beta); at
+// residual checks the block sums of |z - B F q_new - d|^2 go to partials
+// slot 11. Block 0 counts the iteration.
 template <typename T, int D>
 __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ qn_,
                                           T* __restrict__ beta_, const double* __restrict__ sw_sp, Ctl* __restrict__ ctl,
@@ -467,34 +506,66 @@ __device__ __forceinline__ void beta_body(const Geo& g, const T* __restrict__ q_
     for (int t = c.t0; t < tend; ++t, i += nx) {
       load_fq<T, D>(g, q, i + nx, c, fb);
       load_fq<T, D>(g, qn, i + nx, c, gb);
-      T bt[K];
+      T bt[K], bn[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) bt[k] = beta[(size_t)k * nb + i];
-      double u[K];
-      cone_arg<T, D>(bt, (double)q[i], fa, fb, sw, inv_sigma, u);
-      soc_project<K>(u);
-      // r = z - (B F q_new + d), component by component
-      const double q0 = (double)qn[i];
-      auto upd = [&](int k, double bq) {
-        const double r = u[k] - bq;
-        ssq = fma(r, r, ssq);
-        beta[(size_t)k * nb + i] = (T)((double)bt[k] + tau * sigma * r);
-      };
-      upd(0, 1.0 - q0);
+      beta_cell<T, D>(bt, (double)q[i], fa, fb, (double)qn[i], ga, gb, sw, sigma, tau, inv_sigma, ssq, bn);
 #pragma unroll
-      for (int d = 1; d <= D; ++d) {
-        const int k = 1 + 4 * (d - 1);
-        upd(k + 0, sw * (double)ga[d][0]);
-        upd(k + 1, sw * (double)ga[d][1]);
-        upd(k + 2, sw * (double)gb[d][0]);
-        upd(k + 3, sw * (double)gb[d][1]);
-      }
-      upd(K - 1, 1.0 + q0);
+      for (int k = 0; k < K; ++k) beta[(size_t)k * nb + i] = bn[k];
       shift_fq<T, D>(fa, fb);
       shift_fq<T, D>(ga, gb);
     }
   }
   if (check) block_slot11(ssq, partials, blk, g.nsweep);
+  if (blk == 0 && threadIdx.x == 0) glob(ctl)->iter += 1;
+}
+
+// beta update of one iteration (old q in q_, new q in qn_) and the z-step of
+// the next, which reads exactly the new q and the new beta, in one sweep: the
+// new beta values and the F q_new values are still in registers when the
+// cone argument of the next iteration is formed, so neither is read again.
+// Used between iterations without a residual check (sigma is the same for
+// both steps). Computes the values of beta_body followed by cone_body.
+template <typename T, int D>
+__device__ __forceinline__ void beta_cone_body(const Geo& g, const T* __restrict__ q_, const T* __restrict__ qn_,
+                                               T* __restrict__ beta_, const double* __restrict__ sw_sp,
+                                               T* __restrict__ W_, double* __restrict__ DW_, Ctl* __restrict__ ctl,
+                                               uint32_t blk) {
+  constexpr int K = 4 * D + 2;
+  const Column c = column_of<D>(g, blk);
+  const int tend = min(c.t1, g.n[0]);
+  const double sigma = glob(ctl)->sigma, tau = glob(ctl)->tau, inv_sigma = 1.0 / sigma;
+  if (c.live && c.t0 < tend) {
+    gp<const T> q = glob(q_);
+    gp<const T> qn = glob(qn_);
+    gp<T> beta = glob(beta_);
+    gp<T> W = glob(W_);
+    gp<double> DW = glob(DW_);
+    const uint32_t nb = (uint32_t)g.nb, nx = (uint32_t)g.nx;
+    const double sw = glob(sw_sp)[c.xs];
+    uint32_t i = (uint32_t)c.t0 * nx + c.xs;
+    T fa[kMaxAxes][2], fb[kMaxAxes][2], ga[kMaxAxes][2], gb[kMaxAxes][2];
+    load_fq<T, D>(g, q, i, c, fa);
+    load_fq<T, D>(g, qn, i, c, ga);
+    double ssq = 0.0;
+    for (int t = c.t0; t < tend; ++t, i += nx) {
+      load_fq<T, D>(g, q, i + nx, c, fb);
+      load_fq<T, D>(g, qn, i + nx, c, gb);
+      T bt[K], bn[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) bt[k] = beta[(size_t)k * nb + i];
+      const double q0n = (double)qn[i];
+      beta_cell<T, D>(bt, (double)q[i], fa, fb, q0n, ga, gb, sw, sigma, tau, inv_sigma, ssq, bn);
+#pragma unroll
+      for (int k = 0; k < K; ++k) beta[(size_t)k * nb + i] = bn[k];
+      double u[K];
+      cone_arg<T, D>(bn, q0n, ga, gb, sw, inv_sigma, u);
+      soc_project<K>(u);
+      cone_store<T, D>(u, bn, sw, inv_sigma, W, DW, nb, i);
+      shift_fq<T, D>(fa, fb);
+      shift_fq<T, D>(ga, gb);
+    }
+  }
   if (blk == 0 && threadIdx.x == 0) glob(ctl)->iter += 1;
 }
 

@@ -27,20 +27,29 @@ def kernel_bytes(D: int, n: Sequence[int], w: int) -> Dict[str, float]:
     mixed = w != 8
     a = 8  # alpha
     last_inv = (w + 16) * Nc if mixed else 2 * w * Nc  # time-axis inverse adds into phi (mixed)
+    rhs = w * Q + a * Q + w * Nc + (8 * Nc if mixed else 0)
+    beta = w * (2 * Q + 2 * K * S)
+    beta_cone = w * (2 * Q + 2 * K * S + 4 * D * S) + 8 * S
     return {
         # b (FP64) or b - A^*A phi (mixed): read q, alpha (and phi); write the work plane
-        "rhs": w * Q + a * Q + w * Nc + (8 * Nc if mixed else 0),
+        "rhs": rhs,
         "dct_first": 2 * w * Nc,
         "dct_mid": 2 * w * Nc,
         "dct_last": 2 * w * Nc,
         # D launches: D-1 plain inverse passes and the time-axis one
         "dct_inv": ((D - 1) * 2 * w * Nc + last_inv) / D,
-        # cone (z-step): read q, beta; write 4D weighted w planes and w_{K-1} - w_0
-        "cone": w * (Q + K * S + (4 * D + 1) * S),
-        # q-step: read phi, alpha, the 4D + 1 w planes; write q, alpha
-        "qd": w * (Q + (4 * D + 1) * S) + 2 * a * Q + 8 * Nc,
+        # cone (z-step): read q, beta; write 4D weighted w planes and w_{K-1} - w_0 (FP64)
+        "cone": w * (Q + K * S + 4 * D * S) + 8 * S,
+        # q-step: read phi, alpha, the 4D w planes and w_{K-1} - w_0; write q, alpha
+        "qd": w * (Q + 4 * D * S) + 8 * S + 2 * a * Q + 8 * Nc,
         # beta: read q_old, q_new, beta; write beta
-        "beta": w * (2 * Q + 2 * K * S),
+        "beta": beta,
+        # beta update and the next z-step in one sweep: read q_old, q_new, beta;
+        # write beta, the 4D w planes and w_{K-1} - w_0
+        "beta_cone": beta_cone,
+        # the fused launches with the next right-hand side (q_new counted once)
+        "beta_rhs": beta + rhs - w * Q,
+        "beta_cone_rhs": beta_cone + rhs - w * Q,
         # residual partials: read phi, q, alpha, beta
         "resid": w * (Q + K * S) + a * Q + 8 * Nc,
         "final": 0.0,
