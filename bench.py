@@ -445,9 +445,12 @@ def serving_section(torch, rate, seconds, drain_s, seed=5000):
     2D solves (sides log-uniform in [32, 256], n0 from {16, 32, 64}, every
     second one masked) and 10% 3D solves (32 x 64^3), mixed precision, tol
     1e-6; continuous batching with admission by HBM footprint and backfill
-    (one context per D, each on its own thread and stream). Latency is
-    arrival -> result in host memory. Requests still running `drain_s` after
-    the last arrival are reported as unfinished (their latency is censored)."""
+    (one context per D, each on its own thread and stream). A request still
+    above 1e-6 at the mixed cap continues in an FP64 context of its
+    dimension from its final state (promoted exactly) for up to
+    FINISH_MAX_ITER iterations in all. Latency is arrival -> result in host
+    memory. Requests still running `drain_s` after the last arrival are
+    reported as unfinished (their latency is censored)."""
     from paper_2505_05424_amd.serving import Server
     rng = np.random.default_rng(seed)
     t_arr = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * seconds * 2) + 10))
@@ -455,7 +458,9 @@ def serving_section(torch, rate, seconds, drain_s, seed=5000):
     log(f"serving: generating {len(t_arr)} requests (rate {rate:.3f}/s over {seconds:.0f} s)")
     reqs = [dotgen.serving_request(i, seed=seed) for i in range(len(t_arr))]
     srv = Server(precision=B.DOT_MIXED, budgets={2: 96 << 30, 3: 64 << 30}, slots={2: 160, 3: 32},
-                 step_iters=40, tol=TOL, max_iter=BATCH_MAX_ITER)
+                 step_iters=40, tol=TOL, max_iter=BATCH_MAX_ITER, finish_fp64=True,
+                 finish_iters=FINISH_MAX_ITER - BATCH_MAX_ITER, finish_budgets={2: 24 << 30, 3: 32 << 30},
+                 finish_slots={2: 32, 3: 8})
     # warm-up: one small request per context (first launches, module loads)
     warm = [srv.submit(dotgen.tiny_instance(2, (8, 16, 16), seed=1)),
             srv.submit(dotgen.tiny_instance(3, (4, 8, 8, 8), seed=2))]
@@ -495,7 +500,7 @@ def serving_section(torch, rate, seconds, drain_s, seed=5000):
                    for D, ln in srv.lanes.items()}
     srv.abandon()
     fin = [h for h in handles if h.done.is_set() and h.result is not None]
-    conv = [h for h in fin if B.TERM_NAMES[h.result.term] == "converged"]
+    conv = [h for h in fin if _converged(h.result)]
     lat = np.array([h.latency for h in fin]) if fin else np.zeros(1)
     wall = (max(h.t_done for h in fin) if fin else t_stop) - t0
     by_d = {}
@@ -517,6 +522,13 @@ def serving_section(torch, rate, seconds, drain_s, seed=5000):
         "hit_iteration_cap": len(fin) - len(conv),
         "unfinished_at_cutoff": len(handles) - len(fin),
         "iteration_cap": BATCH_MAX_ITER,
+        "finished_in_fp64": {f"r{i}-" + "x".join(str(k) for k in h.inst.n) + ("-mask" if h.inst.mask is not None
+                                                                             else ""):
+                             {"mixed_iters": h.mixed_result.iters, "mixed_eta_dot": h.mixed_result.eta_dot,
+                              "iters": h.result.iters, "eta_dot": h.result.eta_dot,
+                              "term": B.TERM_NAMES[h.result.term], "latency_s": h.latency}
+                             for i, h in enumerate(handles) if h.result is not None and h.finished_in_fp64},
+        "total_iteration_cap": FINISH_MAX_ITER,
         "wall_s": wall,
         "solves_per_s": len(conv) / wall,
         "instance_iters_per_s": sum(h.result.iters for h in fin) / wall,

@@ -468,15 +468,16 @@ int dot_ctx_fetch(dot_ctx* ctx, uint64_t ticket, double* rho_out, double* m_out,
 /* Free arena bytes and the counts of admitted and retired requests. */
 int dot_ctx_stats(const dot_ctx* ctx, size_t* free_bytes, int64_t* admitted, int64_t* retired);
 /* Checkpoint of a running request (restart from the latest iterate, Sec. 5.3,
- * here without losing any state): between two dot_ctx_step calls, copies the
+ * here without losing any state), or of a finished one kept at its iteration
+ * cap (dot_ctx_keep_capped, before its fetch): between two dot_ctx_step calls, copies the
  * whole device state of the request's current level -- every plane (phi, q,
  * q_new, alpha, beta and the workspaces) and its control block (sigma,
  * counters, sigma schedule, last residuals, iteration cap) -- with a header
  * naming D, precision, grids and level into the host buffer `buf` of `cap`
  * bytes. *bytes receives the size needed; with buf NULL only the size is
  * reported. The request keeps running in this context. DOT_EINVAL for an
- * unknown ticket, a queued or finished request, or cap too small. Blocks on
- * `stream`. */
+ * unknown ticket, a queued request, a finished one without a kept
+ * checkpoint, or cap too small. Blocks on `stream`. */
 int dot_ctx_export(dot_ctx* ctx, uint64_t ticket, void* buf, size_t cap, size_t* bytes, void* stream);
 /* Queues a request that resumes from a checkpoint of dot_ctx_export (made by
  * this or another context with the same D and precision): p and levels must
@@ -484,11 +485,26 @@ int dot_ctx_export(dot_ctx* ctx, uint64_t ticket, void* buf, size_t cap, size_t*
  * header); the host arrays of p are copied before return. At admission its
  * state and control block are those of the checkpoint, so it continues the
  * exported iterate exactly: it finishes with bitwise the result the exported
- * request would have reached without interruption. The time budget of p
+ * request would have reached without interruption. The request runs to
+ * p->max_iter: a checkpoint of a request that stopped at a smaller cap
+ * (dot_ctx_keep_capped) continues from there. A mixed-precision checkpoint
+ * imported into an FP64 context is promoted as by dot_state_promote (phi and
+ * alpha copied, q, q_new and beta widened exactly, sigma, counters and sigma
+ * schedule kept), so the request continues that iterate in FP64. The
+ * checkpoint's iteration count must be a multiple of 10 (every export between
+ * steps, and a cap that is a multiple of 10, give one). The time budget of p
  * restarts at the new admission. DOT_EINVAL on any mismatch, as
  * dot_ctx_submit otherwise. */
 int dot_ctx_import(dot_ctx* ctx, const dot_problem* p, int32_t levels, const void* buf, size_t bytes,
                    uint64_t* ticket);
+/* With keep != 0, a request of this context that stops at its max_iter
+ * without converging keeps a checkpoint of its final state (the layout of
+ * dot_ctx_export) in host memory until dot_ctx_fetch: dot_ctx_export then
+ * returns it for the finished request, so that it can continue elsewhere --
+ * typically a mixed-precision request whose FP32 state levels off above its
+ * tolerance, continued in an FP64 context (see dot_ctx_import). Off by
+ * default (a kept checkpoint holds the whole state). */
+int dot_ctx_keep_capped(dot_ctx* ctx, int32_t keep);
 /* Message of the last failed call on this context ("" if none). */
 const char* dot_ctx_last_error(const dot_ctx* ctx);
 

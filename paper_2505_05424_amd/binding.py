@@ -35,6 +35,7 @@ EXPORTED = [
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
     "dot_step_residuals_noalloc", "dot_ctx_export", "dot_ctx_import", "dot_ctx_last_error", "dot_batch_promote",
+    "dot_ctx_keep_capped",
 ]
 NOALLOC_SCRATCH_BYTES = 8 << 20
 
@@ -182,6 +183,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_ctx_import.argtypes = [vp, ctypes.POINTER(dot_problem), i32, vp, ctypes.c_size_t,
                                    ctypes.POINTER(ctypes.c_uint64)]
     lib.dot_ctx_last_error.argtypes = [vp]
+    lib.dot_ctx_keep_capped.argtypes = [vp, i32]
     lib.dot_ctx_last_error.restype = ctypes.c_char_p
     lib.dot_ctx_destroy.argtypes = [vp]
     lib.dot_ctx_destroy.restype = None
@@ -781,6 +783,12 @@ def dot_ctx_import(ctx: Ctx, inst, checkpoint: bytes, levels: int = 0, **kw) -> 
                                  ctypes.byref(t)))
     ctx.shapes[t.value] = (inst.D, tuple(int(k) for k in inst.n))
     return t.value
+
+
+def dot_ctx_keep_capped(ctx: Ctx, keep: bool = True):
+    """Requests that stop at their iteration cap keep a checkpoint of their
+    final state until fetched (dot_ctx_export returns it)."""
+    _check(load().dot_ctx_keep_capped(ctx.handle, int(bool(keep))))
 
 
 def dot_ctx_last_error(ctx: Ctx) -> str:

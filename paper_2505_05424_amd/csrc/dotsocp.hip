@@ -189,6 +189,29 @@ struct dot_plan {
 
 namespace {
 
+// State layout of one instance (byte offsets): phi (FP64) | transform scratch
+// (mixed only) | q (D+1) | q_new (D+1) | alpha (D+1, FP64) | beta (K) | W (4D)
+// | dw (FP64) | control block | partials; bulk planes in the precision's
+// scalar type (the same arithmetic as dot_footprint_bytes).
+struct StateLayout {
+  size_t off_phi, off_scr, off_q, off_qn, off_alpha, off_beta, off_w, off_dw, ctl_offset;
+};
+StateLayout state_layout(int D, int64_t nb, int precision) {
+  const size_t pb = (size_t)nb * (precision == DOT_MIXED ? sizeof(float) : sizeof(double));
+  const int K = 4 * D + 2;
+  StateLayout l;
+  l.off_phi = 0;
+  l.off_scr = align256((size_t)nb * sizeof(double));
+  l.off_q = l.off_scr + (precision == DOT_MIXED ? align256(pb) : 0);
+  l.off_qn = l.off_q + (size_t)(D + 1) * pb;
+  l.off_alpha = align256(l.off_qn + (size_t)(D + 1) * pb);
+  l.off_beta = l.off_alpha + (size_t)(D + 1) * nb * sizeof(double);
+  l.off_w = l.off_beta + (size_t)K * pb;
+  l.off_dw = align256(l.off_w + (size_t)(4 * D) * pb);
+  l.ctl_offset = align256(l.off_dw + (size_t)nb * sizeof(double));
+  return l;
+}
+
 template <typename T>
 int upload(T** dst, const std::vector<T>& v) {
   HIP_OK(hipMalloc((void**)dst, std::max<size_t>(1, v.size()) * sizeof(T)));
@@ -1677,22 +1700,21 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   }
   rc = P->precision == DOT_FP64 ? build_eigs<double>(P.get()) : build_eigs<float>(P.get());
   if (rc) return rc;
-  // state layout: phi (FP64) | scratch (mixed) | q (D+1) | q_new (D+1) | alpha (D+1, FP64) | beta (K) |
-  // W (4D) | dw (FP64) | control block | partials (the same arithmetic as dot_footprint_bytes)
   const size_t pb = (size_t)g.nb * P->scalar_bytes;
-  P->off_phi = 0;
-  P->off_scr = align256((size_t)g.nb * sizeof(double));
-  P->off_q = P->off_scr + (P->precision == DOT_MIXED ? align256(pb) : 0);
-  P->off_qn = P->off_q + (size_t)(D + 1) * pb;
-  P->off_alpha = align256(P->off_qn + (size_t)(D + 1) * pb);
-  P->off_beta = P->off_alpha + (size_t)(D + 1) * g.nb * sizeof(double);
-  P->off_w = P->off_beta + (size_t)P->K * pb;
+  const StateLayout lay = state_layout(D, g.nb, P->precision);
+  P->off_phi = lay.off_phi;
+  P->off_scr = lay.off_scr;
+  P->off_q = lay.off_q;
+  P->off_qn = lay.off_qn;
+  P->off_alpha = lay.off_alpha;
+  P->off_beta = lay.off_beta;
+  P->off_w = lay.off_w;
   P->n_planes = 2 * (D + 1) + P->K + 4 * D;
   set_sweep(g, default_tc(g.nx, g.N[0]));
   P->nblocks = g.nsweep;
   P->partial_rows = (int64_t)g.nxb * g.N[0];
-  P->off_dw = align256(P->off_w + (size_t)(4 * D) * pb);
-  P->ctl_offset = align256(P->off_dw + (size_t)g.nb * sizeof(double));
+  P->off_dw = lay.off_dw;
+  P->ctl_offset = lay.ctl_offset;
   P->partials_offset = P->ctl_offset + align256(sizeof(Ctl));
   P->state_bytes = P->partials_offset + align256((size_t)P->partial_rows * kNumSums * sizeof(double));
   if (P->precision == DOT_MIXED) HIP_OK(hipMalloc(&P->step_scratch, pb));
@@ -2308,6 +2330,27 @@ namespace {
 
 // Promotion of the mixed iterate in `mixed_state` (layout of M) whose control
 // block is at `mctl` (the state's own, or a batch member's) into fp64_state.
+// Control block of an FP64 continuation of a mixed-precision iterate: the
+// FP64 plan's parameters, the iterate's sigma, residuals, counters and sigma
+// schedule.
+Ctl promoted_ctl(const dot_plan* F, const Ctl& m) {
+  Ctl f = initial_ctl(F);
+  f.sigma = m.sigma;
+  for (int k = 0; k < 8; ++k) f.eta[k] = m.eta[k];
+  f.objective = m.objective;
+  f.dual_objective = m.dual_objective;
+  f.iter = m.iter;
+  f.checks = m.checks;
+  f.sigma_changes = m.sigma_changes;
+  f.next_update = m.next_update;
+  f.gap = m.gap;
+  for (int k = 0; k < kSigmaHist; ++k) {
+    f.hist_sigma[k] = m.hist_sigma[k];
+    f.hist_iter[k] = m.hist_iter[k];
+  }
+  return f;
+}
+
 int promote_impl(const dot_plan* M, const void* mixed_state, const Ctl* mctl, dot_plan* F, void* fp64_state,
                  hipStream_t st) {
   if (M->precision != DOT_MIXED || F->precision != DOT_FP64)
@@ -2338,22 +2381,7 @@ int promote_impl(const dot_plan* M, const void* mixed_state, const Ctl* mctl, do
   // and sigma schedule
   HIP_OK(hipMemcpyAsync(M->host_ctl, mctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
   HIP_OK(hipStreamSynchronize(st));
-  const Ctl m = *M->host_ctl;
-  Ctl f = initial_ctl(F);
-  f.sigma = m.sigma;
-  for (int k = 0; k < 8; ++k) f.eta[k] = m.eta[k];
-  f.objective = m.objective;
-  f.dual_objective = m.dual_objective;
-  f.iter = m.iter;
-  f.checks = m.checks;
-  f.sigma_changes = m.sigma_changes;
-  f.next_update = m.next_update;
-  f.gap = m.gap;
-  for (int k = 0; k < kSigmaHist; ++k) {
-    f.hist_sigma[k] = m.hist_sigma[k];
-    f.hist_iter[k] = m.hist_iter[k];
-  }
-  *F->host_ctl = f;
+  *F->host_ctl = promoted_ctl(F, *M->host_ctl);
   HIP_OK(hipMemcpyAsync(fs + F->ctl_offset, F->host_ctl, sizeof(Ctl), hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
   return DOT_OK;
@@ -2537,6 +2565,9 @@ struct Request {
   int ck_level = 0;
   std::vector<unsigned char> ck_planes;  // the level's state up to its control block
   Ctl ck_ctl{};
+  // checkpoint of the final state of a request that stopped at its iteration
+  // cap in a context that keeps them (dot_ctx_keep_capped); freed by fetch
+  std::vector<unsigned char> final_ck;
   ~Request() {
     for (auto* P : plans) dot_plan_destroy(P);
   }
@@ -2568,6 +2599,7 @@ struct dot_ctx {
   Prof prof;
   int device = 0;
   int64_t admitted = 0, retired = 0;
+  bool keep_capped = false;             // keep checkpoints of requests retired at their iteration cap
   mutable std::mutex mu;                // every dot_ctx_* call holds it
   mutable std::string err;              // message of the last failed call on this context
   ~dot_ctx() { delete graphs; }
@@ -2747,6 +2779,9 @@ int ctx_admit(dot_ctx* C, hipStream_t st) {
   return DOT_OK;
 }
 
+int write_checkpoint(dot_ctx* C, Request* r, unsigned char* out, hipStream_t st);
+size_t checkpoint_bytes(const Request* r);
+
 // Retire instances that stopped or reached their iteration cap: results to
 // host, arena block and slot freed.
 int ctx_retire(dot_ctx* C, hipStream_t st) {
@@ -2795,6 +2830,10 @@ int ctx_retire(dot_ctx* C, hipStream_t st) {
     if (rc) return rc;
     fill_result(c, &r->res);
     if (!c.stop && c.iter < r->plan->max_iter) r->res.term = DOT_TIMEOUT;
+    if (C->keep_capped && c.stop == 2) {
+      r->final_ck.resize(checkpoint_bytes(r));
+      if ((rc = write_checkpoint(C, r, r->final_ck.data(), st))) return rc;
+    }
     r->status = kDone;
     C->arena.release(r->block, r->bytes);
     C->slots[sl] = nullptr;
@@ -3006,15 +3045,10 @@ struct CkHeader {
   uint64_t ctl_bytes;
 };
 
-int ctx_export_impl(dot_ctx* C, uint64_t ticket, void* buf, size_t cap, size_t* bytes, hipStream_t st) {
-  Request* r = find_req(C, ticket);
-  if (!r) return fail(DOT_EINVAL, "unknown ticket");
-  if (r->status != kRunning) return fail(DOT_EINVAL, "only a running request can be exported");
+// Checkpoint of request r's current level (running, between steps) into out
+// (sizeof(CkHeader) + ctl_offset + sizeof(Ctl) bytes).
+int write_checkpoint(dot_ctx* C, Request* r, unsigned char* out, hipStream_t st) {
   dot_plan* P = r->plan;
-  const size_t need = sizeof(CkHeader) + P->ctl_offset + sizeof(Ctl);
-  if (bytes) *bytes = need;
-  if (!buf) return DOT_OK;
-  if (cap < need) return fail(DOT_EINVAL, "checkpoint buffer too small");
   CkHeader h{};
   h.magic = kCkMagic;
   h.D = C->D;
@@ -3027,7 +3061,6 @@ int ctx_export_impl(dot_ctx* C, uint64_t ticket, void* buf, size_t cap, size_t* 
   }
   h.plane_bytes = P->ctl_offset;
   h.ctl_bytes = sizeof(Ctl);
-  unsigned char* out = static_cast<unsigned char*>(buf);
   std::memcpy(out, &h, sizeof(h));
   HIP_OK(hipMemcpyAsync(out + sizeof(h), static_cast<char*>(C->arena_mem) + r->off, P->ctl_offset,
                         hipMemcpyDeviceToHost, st));
@@ -3038,13 +3071,35 @@ int ctx_export_impl(dot_ctx* C, uint64_t ticket, void* buf, size_t cap, size_t* 
   return DOT_OK;
 }
 
+size_t checkpoint_bytes(const Request* r) { return sizeof(CkHeader) + r->plan->ctl_offset + sizeof(Ctl); }
+
+int ctx_export_impl(dot_ctx* C, uint64_t ticket, void* buf, size_t cap, size_t* bytes, hipStream_t st) {
+  Request* r = find_req(C, ticket);
+  if (!r) return fail(DOT_EINVAL, "unknown ticket");
+  const bool kept = r->status == kDone && !r->final_ck.empty();
+  if (r->status != kRunning && !kept)
+    return fail(DOT_EINVAL, "only a running request, or one kept at its iteration cap, can be exported");
+  const size_t need = kept ? r->final_ck.size() : checkpoint_bytes(r);
+  if (bytes) *bytes = need;
+  if (!buf) return DOT_OK;
+  if (cap < need) return fail(DOT_EINVAL, "checkpoint buffer too small");
+  if (kept) {
+    std::memcpy(buf, r->final_ck.data(), need);
+    return DOT_OK;
+  }
+  return write_checkpoint(C, r, static_cast<unsigned char*>(buf), st);
+}
+
 int ctx_import_impl(dot_ctx* C, const dot_problem* p, int32_t levels, const void* buf, size_t bytes,
                     uint64_t* ticket) {
   if (!buf || bytes < sizeof(CkHeader)) return fail(DOT_EINVAL, "checkpoint too short");
   CkHeader h;
   std::memcpy(&h, buf, sizeof(h));
   if (h.magic != kCkMagic) return fail(DOT_EINVAL, "not a serving checkpoint");
-  if (h.D != C->D || h.precision != C->precision) return fail(DOT_EINVAL, "checkpoint D / precision differ from the context");
+  // a mixed-precision checkpoint may continue in an FP64 context (promoted)
+  const bool promote = h.precision == DOT_MIXED && C->precision == DOT_FP64;
+  if (h.D != C->D || (h.precision != C->precision && !promote))
+    return fail(DOT_EINVAL, "checkpoint D / precision differ from the context");
   if (h.levels != levels || h.level < 0 || h.level > levels)
     return fail(DOT_EINVAL, "checkpoint levels differ from the request's");
   for (int d = 0; d <= p->D && d < 4; ++d)
@@ -3056,18 +3111,48 @@ int ctx_import_impl(dot_ctx* C, const dot_problem* p, int32_t levels, const void
   int rc = ctx_submit_impl(C, p, levels, &t, &r);
   if (rc) return rc;
   dot_plan* P = r->plans[h.level];
-  bool same = P->ctl_offset == h.plane_bytes;
+  const StateLayout src = state_layout(h.D, P->g.nb, h.precision);
+  bool same = src.ctl_offset == h.plane_bytes;
   for (int d = 0; d < 4; ++d) same = same && P->n[d] == h.level_n[d];
-  if (!same) {
+  const unsigned char* in = static_cast<const unsigned char*>(buf) + sizeof(CkHeader);
+  Ctl ck;
+  std::memcpy(&ck, in + h.plane_bytes, sizeof(Ctl));
+  // the q planes of an imported state are read with the parity of an
+  // admission, which holds for iteration counts that are multiples of 10
+  const bool aligned = ck.iter % 10 == 0;
+  if (!same || !aligned) {
     // undo the submission: the request was queued last
     C->queue.pop_back();
     C->all.pop_back();
-    return fail(DOT_EINVAL, "checkpoint state layout differs from the problem's");
+    return fail(DOT_EINVAL, !same ? "checkpoint state layout differs from the problem's"
+                                  : "checkpoint not at a multiple of 10 iterations");
   }
-  const unsigned char* in = static_cast<const unsigned char*>(buf) + sizeof(CkHeader);
   r->ck_level = h.level;
-  r->ck_planes.assign(in, in + h.plane_bytes);
-  std::memcpy(&r->ck_ctl, in + h.plane_bytes, sizeof(Ctl));
+  if (!promote) {
+    r->ck_planes.assign(in, in + h.plane_bytes);
+    r->ck_ctl = ck;
+  } else {
+    // the FP64 state of the iterate (as dot_state_promote): phi and alpha
+    // copied, q, q_new and beta widened exactly, the z-step planes zero
+    const int64_t nb = P->g.nb;
+    const int D = h.D, K = 4 * D + 2;
+    r->ck_planes.assign(P->ctl_offset, 0);
+    unsigned char* out = r->ck_planes.data();
+    std::memcpy(out + P->off_phi, in + src.off_phi, (size_t)nb * sizeof(double));
+    std::memcpy(out + P->off_alpha, in + src.off_alpha, (size_t)(D + 1) * nb * sizeof(double));
+    auto widen = [&](size_t from, size_t to, int64_t n) {
+      const float* a = reinterpret_cast<const float*>(in + from);
+      double* b = reinterpret_cast<double*>(out + to);
+      for (int64_t i = 0; i < n; ++i) b[i] = (double)a[i];
+    };
+    widen(src.off_q, P->off_q, (int64_t)2 * (D + 1) * nb);
+    widen(src.off_beta, P->off_beta, (int64_t)K * nb);
+    r->ck_ctl = promoted_ctl(P, ck);
+  }
+  // the request continues to its own max_iter (a request stopped at an
+  // earlier cap runs on)
+  r->ck_ctl.iter_limit = P->max_iter;
+  if (r->ck_ctl.stop == 2 && r->ck_ctl.iter < P->max_iter) r->ck_ctl.stop = 0;
   *ticket = t;
   return DOT_OK;
 }
@@ -3167,6 +3252,12 @@ int dot_ctx_import(dot_ctx* C, const dot_problem* p, int32_t levels, const void*
   CTX_ENTER(C);
   if (!p || !ticket) return ctx_ret(C, fail(DOT_EINVAL, "null argument"));
   return ctx_ret(C, ctx_import_impl(C, p, levels, buf, bytes, ticket));
+}
+
+int dot_ctx_keep_capped(dot_ctx* C, int32_t keep) {
+  CTX_ENTER(C);
+  C->keep_capped = keep != 0;
+  return DOT_OK;
 }
 
 const char* dot_ctx_last_error(const dot_ctx* C) { return C ? C->err.c_str() : ""; }

@@ -324,3 +324,97 @@ def test_checkpoint_errors_and_context_messages():
         B.dot_ctx_create(2, B.DOT_FP64, 1 << 24, 2, device=4096)
     ctx.close()
     ctx3.close()
+
+
+def _promoted_reference(inst, tol, cap1, cap2):
+    """A mixed solve run to iteration cap1, promoted (dot_state_promote) and
+    continued in FP64 up to iteration cap2."""
+    st = G.stream_handle()
+    mp = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=B.DOT_MIXED, tol=tol,
+                           max_iter=cap1)
+    fp = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, precision=B.DOT_FP64, tol=tol,
+                           max_iter=cap2)
+    ms, fs = G.GpuState(mp), G.GpuState(fp)
+    ms.reset()
+    rm = ms.run(cap1)
+    B.dot_state_promote(mp, ms.ptr, fp, fs.ptr, st)
+    rf = fs.run(cap2 - cap1)
+    rho, m = fs.extract()
+    return rm, rf, rho, m
+
+
+@pytest.mark.parametrize("D,n", [(2, (8, 20, 24)), (3, (4, 6, 5, 7))], ids=["2d-masked", "3d"])
+def test_capped_mixed_request_continues_in_fp64_as_a_promoted_solve(D, n):
+    """dot_ctx_keep_capped: a mixed request stopped at its cap keeps its final
+    state until fetched; imported into an FP64 context it is promoted and
+    continues that iterate, bitwise as dot_state_promote followed by dot_run."""
+    inst = dotgen.tiny_instance(D, n, seed=121, floor=0.0, masked=(D == 2))
+    tol, cap1, cap2 = 1e-7, 300, 40000
+    st = G.stream_handle()
+    print(f"[case] capped mixed -> FP64 {D}d {n}", flush=True)
+    ctx = B.dot_ctx_create(D, B.DOT_MIXED, 1 << 26, 2)
+    B.dot_ctx_keep_capped(ctx)
+    t = B.dot_ctx_submit(ctx, inst, tol=tol, max_iter=cap1)
+    for _ in range(100):
+        B.dot_ctx_step(ctx, 10, st)
+        if B.dot_ctx_poll(ctx, t) == B.CTX_DONE:
+            break
+    ck = B.dot_ctx_export(ctx, t, st)  # the kept final state
+    r1, _, _ = B.dot_ctx_fetch(ctx, t)
+    assert B.TERM_NAMES[r1.term] == "maxiter" and r1.iters == cap1
+    with pytest.raises(B.DotError):
+        B.dot_ctx_export(ctx, t, st)  # fetched: forgotten with its checkpoint
+    ctx2 = B.dot_ctx_create(D, B.DOT_FP64, 1 << 26, 2)
+    t2 = B.dot_ctx_import(ctx2, inst, ck, tol=tol, max_iter=cap2)
+    for _ in range(5000):
+        B.dot_ctx_step(ctx2, 20, st)
+        if B.dot_ctx_poll(ctx2, t2) == B.CTX_DONE:
+            break
+    r2, rho2, m2 = B.dot_ctx_fetch(ctx2, t2)
+    rm, rf, rho, m = _promoted_reference(inst, tol, cap1, cap2)
+    _same(r1, rm)  # the capped mixed request is its solve alone
+    assert B.TERM_NAMES[r2.term] == "converged" and cap1 < r2.iters < cap2
+    _same(r2, rf)
+    assert np.array_equal(rho2, rho)
+    for a, b in zip(m2, m):
+        assert np.array_equal(a, b)
+    # without keep_capped nothing is kept; a converged request keeps nothing either
+    ctx3 = B.dot_ctx_create(D, B.DOT_MIXED, 1 << 26, 2)
+    t3 = B.dot_ctx_submit(ctx3, inst, tol=tol, max_iter=cap1)
+    for _ in range(100):
+        B.dot_ctx_step(ctx3, 10, st)
+        if B.dot_ctx_poll(ctx3, t3) == B.CTX_DONE:
+            break
+    with pytest.raises(B.DotError):
+        B.dot_ctx_export(ctx3, t3, st)
+    ctx.close()
+    ctx2.close()
+    ctx3.close()
+
+
+def test_server_finishes_capped_mixed_requests_in_fp64():
+    """Server(finish_fp64=True): mixed requests stopped at the mixed cap move
+    to the FP64 lane of their dimension and converge there; each result is
+    the promoted solve's, bitwise."""
+    from paper_2505_05424_amd.serving import Server
+    insts = [dotgen.tiny_instance(2, (8, 20, 24), seed=131, floor=0.0, masked=True),
+             dotgen.tiny_instance(3, (4, 6, 5, 7), seed=132, floor=0.0),
+             dotgen.tiny_instance(2, (12, 33, 21), seed=133, floor=0.0, n_comp=3)]
+    tol, cap1, extra = 1e-7, 300, 39700
+    print(f"[case] server FP64 finish, {len(insts)} requests", flush=True)
+    srv = Server(precision=B.DOT_MIXED, budgets={2: 1 << 26, 3: 1 << 26}, slots={2: 2, 3: 2}, step_iters=20,
+                 tol=tol, max_iter=cap1, keep_solution=True, finish_fp64=True, finish_iters=extra,
+                 finish_budgets={2: 1 << 26, 3: 1 << 26}, finish_slots={2: 2, 3: 2})
+    reqs = [srv.submit(inst) for inst in insts]
+    for r in reqs:
+        assert r.done.wait(300)
+    srv.close()
+    for inst, req in zip(insts, reqs):
+        assert req.error is None and req.finished_in_fp64
+        rm, rf, rho, m = _promoted_reference(inst, tol, cap1, cap1 + extra)
+        _same(req.mixed_result, rm)
+        assert B.TERM_NAMES[req.result.term] == "converged"
+        _same(req.result, rf)
+        assert np.array_equal(req.rho, rho)
+        for a, b in zip(req.m, m):
+            assert np.array_equal(a, b)
