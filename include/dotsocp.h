@@ -218,7 +218,7 @@ int dot_step_residuals_noalloc(dot_plan* plan, const void* phi, const void* z, c
 typedef enum {
   DOT_K_DCT_FIRST = 0, /* time-axis forward pass */
   DOT_K_DCT_MID = 1,   /* forward passes on the middle spatial axes */
-  DOT_K_DCT_LAST = 2,  /* last axis: forward, 1/Lambda, inverse */
+  DOT_K_DCT_LAST = 2,  /* last axis: forward, 1/Lambda, inverse (or its tridiagonal elimination) */
   DOT_K_DCT_INV = 3,   /* inverse passes on the other axes */
   DOT_K_CONE = 4,      /* cone gather + projection (z-step) into the weighted w planes */
   DOT_K_QD = 5,        /* q-step and alpha update (q0 and q_d) */
@@ -234,7 +234,8 @@ typedef enum {
  * the summed event time in ms and the number of launches since the last read
  * and clears them. While a class is recorded, graphs are off and every class
  * runs as its own launch (otherwise an iteration without a residual check
- * computes the next iteration's right-hand side inside its beta launch). */
+ * computes the next iteration's z-step and right-hand side inside its beta
+ * launch, and large instances run the z-step beside the phi-step). */
 int dot_profile_select(dot_plan* plan, int32_t kernel_class);
 int dot_profile_read(dot_plan* plan, double* total_ms, int64_t* launches);
 
