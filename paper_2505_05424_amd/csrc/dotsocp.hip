@@ -785,10 +785,12 @@ struct Carry {
 // one-lane elimination (it keeps its checkpoints in W plane 0, which the
 // z-step writes), and at least kOverlapMinNodes grid nodes in all. The fork
 // and the join cost about 10 us per iteration; below that size the kernels
-// they would overlap are shorter (measured per iteration: 2D 32x64^2 FP64
-// 55 -> 66 us overlapped; 2D 64x256^2 mixed 492 -> 474 us, FP64 789 -> 732 us,
-// the 64-instance 2D batch 1225 -> 1161 us).
-constexpr int64_t kOverlapMinNodes = int64_t(1) << 20;
+// they would overlap are shorter. Measured per iteration, sequential ->
+// overlapped (with the fused beta and z-step in both orders): 2D 64x128^2
+// mixed (1.08M nodes) 132 -> 141 us; 2D 64x192^2 mixed (2.4M) 299 -> 291 us;
+// 2D 64x256^2 mixed 465 -> 447 us, FP64 699 -> 685 us; 3D 32x64^3 mixed
+// 1185 -> 1162 us; the 64-instance 2D batch 1154 -> 1086 us.
+constexpr int64_t kOverlapMinNodes = int64_t(1) << 21;
 bool overlapped(const Exec& E) {
   return E.graphs && !(E.prof && E.prof->cls >= 0) && E.ntri_long == 0 && E.nodes >= kOverlapMinNodes;
 }

@@ -111,12 +111,12 @@ def test_batch_mixing_tridiagonal_and_transform_last_axes(prec):
 
 @pytest.mark.parametrize("prec", [B.DOT_FP64, B.DOT_MIXED])
 def test_overlapped_order_gives_the_sequential_bits(prec):
-    """From 2^20 grid nodes an executor runs the z-step on a second graph
+    """From 2^21 grid nodes an executor runs the z-step on a second graph
     branch beside the phi-step and defers beta updates; the same kernels in the
     one-stream order (a kernel class being timed switches to it) give bitwise
     the same iterates. Also a batch large enough to overlap against each member
     solved alone below the threshold (one stream)."""
-    big = dotgen.tiny_instance(2, (16, 256, 256), seed=41, floor=0.0, n_comp=3)  # 1.12 M nodes
+    big = dotgen.tiny_instance(2, (32, 256, 256), seed=41, floor=0.0, n_comp=3)  # 2.18 M nodes
     small = dotgen.tiny_instance(2, (8, 20, 24), seed=42, floor=0.0, masked=True)
     iters = 60
     st = G.stream_handle()
