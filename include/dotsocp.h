@@ -164,10 +164,12 @@ int dot_step_divergence(dot_plan* plan, const void* q, const void* alpha, double
  * / h^2), solved by elimination with the recurrences in FP64 registers; same
  * linear system, same phi up to rounding (forward error within the condition
  * number of the line systems times the FP64 unit, which grows with the square
- * of the axis length). In DOT_MIXED the transforms work on an FP32 plane, and
- * so does the elimination's intermediate d' between its forward and backward
- * sweep (stored in the plane's type; the c' checkpoints are FP64), i.e. the
- * FP32 rounding of the other transform passes. Such
+ * of the axis length). In DOT_MIXED the transforms work on an FP32 plane; a
+ * line of up to 576 nodes is eliminated with its values staged in FP64 (LDS
+ * and registers) between one FP32 load and one FP32 store, while the
+ * one-lane elimination of longer lines keeps its intermediate d' between the
+ * forward and backward sweep in the plane's type (the c' checkpoints are
+ * FP64), i.e. the FP32 rounding of the other transform passes. Such
  * an axis has no transform-tile limit (every axis stays within the 4096
  * segments dot_plan_create accepts); the other axes must fit a tile. */
 int dot_step_poisson(dot_plan* plan, void* b_to_phi, void* stream);
