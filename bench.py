@@ -558,7 +558,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(instances are independent; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              "(instances are independent: several GPUs would each take their own instances)", file=sys.stderr)
         sys.exit(2)
 
     import torch
