@@ -258,7 +258,12 @@ int32_t dot_batch_size(const dot_batch* batch);
 /* zero state, sigma0 and counters for every instance */
 int dot_batch_reset(dot_batch* batch, void* workspace, void* stream);
 /* up to max_iters iterations of all instances in lockstep (stopped instances
- * do no work); blocks; fills results[count] (may be NULL). Time budgets
+ * do no work); blocks; fills results[count] (may be NULL). Compaction: at the
+ * start of the call and at each poll of the control blocks (every 40
+ * iterations) the launches are laid out anew over the instances still running
+ * once the stopped ones hold at least 1/8 of the workgroups of a node sweep,
+ * so stopped instances stop taking dispatch slots (their descriptors and
+ * states stay; results are unchanged). Time budgets
  * (dot_problem.time_limit_s): the call returns at the first poll after the
  * smallest nonzero budget among the instances has run out, unless it has done
  * max_iters iterations by then. On such an early return an unfinished
@@ -266,6 +271,10 @@ int dot_batch_reset(dot_batch* batch, void* workspace, void* stream);
  * unfinished instances (no budget, or one not yet spent) report DOT_RUNNING.
  * Every state is resumable by another dot_batch_run. */
 int dot_batch_run(dot_batch* batch, void* workspace, int32_t max_iters, void* stream, dot_result* results);
+/* Instances that have workgroups in the batch's launches (all after
+ * dot_batch_create and dot_batch_reset; fewer after a run that compacted the
+ * layout); -1 for a null batch. */
+int32_t dot_batch_laid_out(const dot_batch* batch);
 /* rho / m of instance `index`, as dot_extract */
 int dot_batch_extract(dot_batch* batch, const void* workspace, int32_t index, double* rho_out, double* m_out,
                       void* stream);

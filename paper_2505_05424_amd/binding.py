@@ -26,7 +26,8 @@ EXPORTED = [
     "dot_state_reset", "dot_run", "dot_extract",
     "dot_step_divergence", "dot_step_poisson", "dot_step_rhs_poisson", "dot_step_cone",
     "dot_step_update", "dot_step_residuals", "dot_profile_select", "dot_profile_read", "dot_solve",
-    "dot_batch_create", "dot_batch_destroy", "dot_batch_workspace_bytes", "dot_batch_size", "dot_batch_reset",
+    "dot_batch_create", "dot_batch_destroy", "dot_batch_workspace_bytes", "dot_batch_size",
+    "dot_batch_laid_out", "dot_batch_reset",
     "dot_batch_run", "dot_batch_extract", "dot_batch_profile_select", "dot_batch_profile_read",
     "dot_plan_set_graphs", "dot_batch_set_graphs",
     "dot_plan_set_schedule", "dot_batch_set_schedule", "dot_plan_get_schedule", "dot_batch_get_schedule",
@@ -163,6 +164,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_batch_workspace_bytes.restype = ctypes.c_size_t
     lib.dot_batch_size.argtypes = [vp]
     lib.dot_batch_size.restype = i32
+    lib.dot_batch_laid_out.argtypes = [vp]
+    lib.dot_batch_laid_out.restype = i32
     lib.dot_batch_reset.argtypes = [vp, vp, vp]
     lib.dot_batch_run.argtypes = [vp, vp, i32, vp, ctypes.POINTER(dot_result)]
     lib.dot_batch_extract.argtypes = [vp, vp, i32, ctypes.POINTER(ctypes.c_double),
@@ -213,7 +216,8 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                          ctypes.POINTER(dot_result)]
     for name in EXPORTED:
         if name not in ("dot_last_error", "dot_plan_destroy", "dot_batch_destroy", "dot_batch_workspace_bytes",
-                        "dot_batch_size", "dot_footprint_bytes", "dot_ctx_destroy", "dot_ctx_last_error"):
+                        "dot_batch_size", "dot_batch_laid_out", "dot_footprint_bytes", "dot_ctx_destroy",
+                        "dot_ctx_last_error"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -512,6 +516,12 @@ def dot_batch_destroy(batch: Batch):
 
 def dot_batch_reset(batch: Batch, ws_ptr: int, stream: int = 0):
     _check(load().dot_batch_reset(batch.handle, ctypes.c_void_p(ws_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_batch_laid_out(batch: Batch) -> int:
+    """Instances with workgroups in the batch's launches (fewer than the batch
+    after a run that compacted the layout around stopped instances)."""
+    return int(load().dot_batch_laid_out(batch.handle))
 
 
 def dot_batch_run(batch: Batch, ws_ptr: int, max_iters: int, stream: int = 0):

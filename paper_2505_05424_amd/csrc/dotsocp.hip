@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -126,6 +127,13 @@ struct GraphCache {
     if (join) (void)hipEventDestroy(join);
   }
 };
+
+// Drops the captured iterations (the next run captures them anew, e.g. after
+// the launch layout changed).
+void drop_graph(GraphCache& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.exec = nullptr;
+}
 
 // Transform schedule of an executor: tile width (lines per workgroup) and
 // waves per workgroup of the passes over each axis; 0 takes the launch-size
@@ -580,6 +588,7 @@ Ctl initial_ctl(const dot_plan* P) {
 // per phase, grid size, LDS bytes and waves.
 struct Exec {
   int D = 0, precision = 0, ninst = 0, cadence = 5;
+  int nact = 0;  // instances with workgroups in the launch grids (a compacted batch leaves out stopped ones)
   void* d_inst = nullptr;
   const uint16_t* map_nodes = nullptr;
   const uint16_t* map_axis[kMaxAxes] = {nullptr, nullptr, nullptr, nullptr};
@@ -671,7 +680,7 @@ int run_passes(const Exec& E, int par, double sigma, hipStream_t st) {
   if ((rc = launch_pass<T, D, kFwd, SRC, kDstPlane>(E, 0, par, sigma, st))) return rc;
   for (int a = 1; a < D; ++a)
     if ((rc = launch_pass<T, D, kFwd, kSrcPlane, kDstPlane>(E, a, par, sigma, st))) return rc;
-  if (E.ntri < E.ninst && (rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane, kDstPlane>(E, D, par, sigma, st)))
+  if (E.ntri < E.nact && (rc = launch_pass<T, D, kFwdScaleInv, kSrcPlane, kDstPlane>(E, D, par, sigma, st)))
     return rc;
   if (E.ntri > 0 && (rc = launch_tri<T, D>(E, st))) return rc;
   for (int a = D - 1; a >= 1; --a)
@@ -901,10 +910,13 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
 // at stride ctl_stride) is refreshed from ctl_dev every `poll` iterations and
 // the loop ends once every instance has stopped. Whole blocks of 10
 // iterations that start at a multiple of 10 replay a captured graph when the
-// executor has a graph cache and no kernel class is being timed.
+// executor has a graph cache and no kernel class is being timed. on_poll runs
+// after each poll that does not end the loop, with the fresh control blocks
+// in ctl_host; it may lay the executor out anew (and drop its graph).
 template <typename T, int D>
 int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t ctl_stride, void* ctl_host,
-              hipStream_t st, int* done_iters, int nctl = -1, double time_limit = 0.0, bool* timed_out = nullptr) {
+              hipStream_t st, int* done_iters, int nctl = -1, double time_limit = 0.0, bool* timed_out = nullptr,
+              const std::function<int()>* on_poll = nullptr) {
   const int poll = 40;
   const auto t_start = std::chrono::steady_clock::now();
   if (nctl < 0) nctl = E.ninst;
@@ -954,6 +966,15 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
           std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count() >= time_limit) {
         if (timed_out) *timed_out = true;
         break;
+      }
+      // the executor's layout may change here (nothing is deferred at a poll)
+      if (on_poll && j < max_iters) {
+        if ((rc = (*on_poll)())) return rc;
+        side = nullptr;
+        if (overlapped(E)) {
+          if ((rc = branch_streams(E.graphs))) return rc;
+          side = E.graphs->side;
+        }
       }
     }
   }
@@ -1008,6 +1029,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.D = P->D;
   E.precision = P->precision;
   E.ninst = 1;
+  E.nact = 1;
   E.cadence = P->cadence;
   E.d_inst = static_cast<char*>(P->d_inst) + slot * inst_slot_bytes();
   E.map_nodes = nullptr;  // one instance: blocks need no map
@@ -1290,28 +1312,46 @@ struct dot_batch {
   Exec E;
   Ctl* host_ctl = nullptr;     // pinned, one entry per instance at ctl_stride
   int it = 0;                  // iterations done (all instances in lockstep)
+  std::vector<char> active;    // instances laid out in the launch grids (empty: all)
   Prof prof;
   GraphCache graphs;
 };
 
 namespace {
 
+// Whether instance i of a batch has workgroups in its launch grids.
+bool laid_out(const dot_batch* B, int i) { return B->active.empty() || B->active[i]; }
+
 // Block maps (block -> instance; the node grid first, then one per axis) and
-// the per-axis launch geometry of a batch under schedule s. The new maps are
-// uploaded before anything of the old layout changes, so on failure the batch
-// keeps its previous layout and schedule; on success s becomes B->sched.
-int batch_layout(dot_batch* B, const Sched& s) {
+// the per-axis launch geometry of a batch under schedule s, over the
+// instances marked in `act` (nullptr: those laid out now; empty: all). The
+// new maps are uploaded before anything of the old layout changes, so on
+// failure the batch keeps its previous layout and schedule; on success s
+// becomes B->sched and `act` B->active. Which instances share the grids and
+// the schedule change no computed value: an instance's workgroups index its
+// own planes by their position among its own blocks.
+int batch_layout(dot_batch* B, const Sched& s, const std::vector<char>* act = nullptr) {
+  const std::vector<char> on = act ? *act : B->active;
   const int count = (int)B->plans.size();
-  dot_plan* const* plans = B->plans.data();
+  std::vector<dot_plan*> plans;
+  std::vector<int> idx;
+  for (int i = 0; i < count; ++i)
+    if (on.empty() || on[i]) {
+      plans.push_back(B->plans[i]);
+      idx.push_back(i);
+    }
+  if (plans.empty()) return fail(DOT_EINVAL, "a batch layout needs at least one instance");
+  const int n = (int)plans.size();
   std::vector<uint16_t> maps;
-  for (int i = 0; i < count; ++i) maps.insert(maps.end(), (size_t)plans[i]->nblocks, (uint16_t)i);
+  for (int k = 0; k < n; ++k) maps.insert(maps.end(), (size_t)plans[k]->nblocks, (uint16_t)idx[k]);
   size_t map_off[kMaxAxes] = {0, 0, 0, 0};
   AxisGeom ag[kMaxAxes];
   for (int a = 0; a <= B->D; ++a) {
     map_off[a] = maps.size();
-    ag[a] = B->precision == DOT_FP64 ? axis_geom<double>(plans, count, a, s) : axis_geom<float>(plans, count, a, s);
-    for (int i = 0; i < count; ++i)
-      maps.insert(maps.end(), (size_t)tiles_for(plans[i]->lines[a], ag[a].cw), (uint16_t)i);
+    ag[a] = B->precision == DOT_FP64 ? axis_geom<double>(plans.data(), n, a, s)
+                                     : axis_geom<float>(plans.data(), n, a, s);
+    for (int k = 0; k < n; ++k)
+      maps.insert(maps.end(), (size_t)tiles_for(plans[k]->lines[a], ag[a].cw), (uint16_t)idx[k]);
   }
   uint16_t* fresh = nullptr;
   HIP_OK(hipMalloc((void**)&fresh, maps.size() * sizeof(uint16_t)));
@@ -1326,15 +1366,17 @@ int batch_layout(dot_batch* B, const Sched& s) {
   }
   B->d_maps = fresh;
   B->sched = s;
+  B->active = on;
   Exec& E = B->E;
+  E.nact = n;
   E.grid_nodes = (unsigned)map_off[0];
   E.ntri = 0;
   E.ntri_long = 0;
   E.nodes = 0;
-  for (int i = 0; i < count; ++i) {
-    E.ntri += plans[i]->tri ? 1 : 0;
-    E.ntri_long += plans[i]->tri && plans[i]->g.N[plans[i]->D] > kTriPartMaxNodes ? 1 : 0;
-    E.nodes += plans[i]->g.nb;
+  for (dot_plan* P : plans) {
+    E.ntri += P->tri ? 1 : 0;
+    E.ntri_long += P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
+    E.nodes += P->g.nb;
   }
   E.map_nodes = B->d_maps;
   for (int a = 0; a <= B->D; ++a) {
@@ -1357,6 +1399,7 @@ int batch_descriptors(dot_batch* B, void* ws, hipStream_t st) {
     dot_plan* P = B->plans[i];
     Ctl* ctl = reinterpret_cast<Ctl*>(static_cast<char*>(ws) + (size_t)i * B->ctl_stride);
     host[i] = state_inst<T>(P, static_cast<char*>(ws) + B->state_off[i], ctl);
+    if (!laid_out(B, i)) continue;  // no workgroup maps to it (blk0 and tile0 stay 0)
     host[i].blk0 = blk;
     blk += (uint32_t)P->nblocks;
     for (int a = 0; a <= B->D; ++a) {
@@ -1369,16 +1412,53 @@ int batch_descriptors(dot_batch* B, void* ws, hipStream_t st) {
   return DOT_OK;
 }
 
+// Compaction: lays the batch out over the instances that have not stopped,
+// by the control blocks in B->host_ctl, so that a stopped instance's
+// workgroups (each reads its descriptor and stop flag, then returns) stop
+// taking dispatch slots. With `any_change` the layout follows every change of
+// that set (instances that run again after a reset come back); otherwise it
+// drops stopped instances once they hold at least 1/8 of the node-grid
+// workgroups. Keeps the layout when no instance runs.
+template <typename T>
+int batch_compact(dot_batch* B, void* ws, hipStream_t st, bool any_change) {
+  const int count = (int)B->plans.size();
+  std::vector<char> now(count);
+  int64_t dropped = 0, kept = 0;
+  int live = 0;
+  bool differs = false;
+  for (int i = 0; i < count; ++i) {
+    const Ctl* c = reinterpret_cast<const Ctl*>(reinterpret_cast<const char*>(B->host_ctl) + (size_t)i * B->ctl_stride);
+    now[i] = c->stop ? 0 : 1;
+    live += now[i];
+    const bool was = laid_out(B, i);
+    differs = differs || (was != (now[i] != 0));
+    if (was && !now[i]) dropped += B->plans[i]->nblocks;
+    if (now[i]) kept += B->plans[i]->nblocks;
+    if (!was && now[i]) any_change = true;  // an instance to bring back: always
+  }
+  if (live == 0 || !differs) return DOT_OK;
+  if (!any_change && dropped * 8 < dropped + kept) return DOT_OK;
+  drop_graph(B->graphs);
+  int rc = batch_layout(B, B->sched, &now);
+  if (rc) return rc;
+  return batch_descriptors<T>(B, ws, st);
+}
+
 template <typename T, int D>
 struct BatchRunF {
   static int run(dot_batch* B, void* ws, int max_iters, hipStream_t st, int* done, bool* timed_out) {
-    int rc = batch_descriptors<T>(B, ws, st);
-    if (rc) return rc;
+    const int count = (int)B->plans.size();
+    HIP_OK(hipMemcpyAsync(B->host_ctl, ws, B->ctl_stride * count, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    int rc = batch_compact<T>(B, ws, st, true);
+    if (rc || (rc = batch_descriptors<T>(B, ws, st))) return rc;
     // the smallest time budget of the instances bounds the call
     double limit = 0.0;
     for (auto* P : B->plans)
       if (P->time_limit > 0.0) limit = limit > 0.0 ? std::min(limit, P->time_limit) : P->time_limit;
-    return run_iters<T, D>(B->E, B->it, max_iters, ws, B->ctl_stride, B->host_ctl, st, done, -1, limit, timed_out);
+    const std::function<int()> compact = [&]() { return batch_compact<T>(B, ws, st, false); };
+    return run_iters<T, D>(B->E, B->it, max_iters, ws, B->ctl_stride, B->host_ctl, st, done, -1, limit, timed_out,
+                           &compact);
   }
 };
 
@@ -1534,11 +1614,6 @@ std::vector<std::vector<std::pair<int, int>>> all_candidates(dot_plan* const* pl
   std::vector<std::vector<std::pair<int, int>>> c;
   for (int a = 0; a <= plans[0]->D; ++a) c.push_back(axis_candidates<T>(plans, count, a, max_smem));
   return c;
-}
-
-void drop_graph(GraphCache& g) {
-  if (g.exec) (void)hipGraphExecDestroy(g.exec);
-  g.exec = nullptr;
 }
 
 template <typename T, int D>
@@ -1943,6 +2018,14 @@ size_t dot_batch_workspace_bytes(const dot_batch* B) { return B ? B->ws_bytes : 
 
 int32_t dot_batch_size(const dot_batch* B) { return B ? (int32_t)B->plans.size() : 0; }
 
+int32_t dot_batch_laid_out(const dot_batch* B) {
+  if (!B) return -1;
+  if (B->active.empty()) return (int32_t)B->plans.size();
+  int32_t n = 0;
+  for (char a : B->active) n += a ? 1 : 0;
+  return n;
+}
+
 int dot_batch_reset(dot_batch* B, void* ws, void* stream) {
   if (!B || !ws) return fail(DOT_EINVAL, "null argument");
   hipStream_t st = (hipStream_t)stream;
@@ -1955,6 +2038,12 @@ int dot_batch_reset(dot_batch* B, void* ws, void* stream) {
   HIP_OK(hipMemcpyAsync(ws, B->host_ctl, B->ctl_stride * count, hipMemcpyHostToDevice, st));
   HIP_OK(hipStreamSynchronize(st));
   B->it = 0;
+  if (!B->active.empty()) {
+    // every instance runs again: lay them all out (a compacted layout left some out)
+    drop_graph(B->graphs);
+    const std::vector<char> all;
+    return batch_layout(B, B->sched, &all);
+  }
   return DOT_OK;
 }
 
@@ -2672,6 +2761,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
     ++idx;
   }
   E.ninst = idx;
+  E.nact = idx;
   E.grid_nodes = blk;
   for (dot_plan* P : act) {
     E.ntri += P->tri ? 1 : 0;
