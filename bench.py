@@ -338,10 +338,10 @@ def batched_section(torch, st, count, seed=4000):
     instances, to eta_dot <= 1e-6 with a cap of BATCH_MAX_ITER iterations;
     members still above the tolerance at the cap (masked instances that need
     more iterations, or that level off at their FP32 storage floor) are then
-    promoted to FP64 (dot_batch_promote) and finished alone up to
-    FINISH_MAX_ITER iterations in all. Against it: the same `count` instances
-    solved one at a time in plain FP64 (cap FINISH_MAX_ITER). Only results
-    with eta_dot <= 1e-6 count as solves."""
+    promoted into one FP64 batch of their problems (dot_batch_promote_member)
+    and finished together up to FINISH_MAX_ITER iterations in all. Against
+    it: the same `count` instances solved one at a time in plain FP64 (cap
+    FINISH_MAX_ITER). Only results with eta_dot <= 1e-6 count as solves."""
     insts = dotgen.config4_instances(count, seed=seed)
     batch = B.dot_batch_create(insts, tol=TOL, max_iter=FINISH_MAX_ITER, precision=B.DOT_MIXED)
     ws = torch.zeros(batch.workspace_bytes, dtype=torch.uint8, device="cuda")
@@ -364,25 +364,40 @@ def batched_section(torch, st, count, seed=4000):
     torch.cuda.synchronize()
     el_batch = time.perf_counter() - t0
     conv_batch = sum(1 for r in res if _converged(r))
-    # FP64 finish of the members still running (inside the timed region)
+    # FP64 finish of the members still running (inside the timed region): all
+    # of them promoted into one FP64 batch of their problems, run together
     finished = {}
-    for i, r in enumerate(res):
-        if _converged(r):
-            continue
-        inst = insts[i]
-        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=TOL,
-                                 max_iter=FINISH_MAX_ITER)
-        buf = torch.zeros(int(plan.info.state_bytes), dtype=torch.uint8, device="cuda")
-        B.dot_batch_promote(batch, ws.data_ptr(), i, plan, buf.data_ptr(), st)
-        rf = B.dot_run(plan, buf.data_ptr(), FINISH_MAX_ITER - r.iters, st)
-        finished[inst.label] = {"mixed_iters": r.iters, "mixed_eta_dot": r.eta_dot, "fp64_iters_after": rf.iters - r.iters,
-                                "eta_dot": rf.eta_dot, "term": B.TERM_NAMES[rf.term],
-                                "objective_change_rel": abs(rf.objective - r.objective) / abs(rf.objective)}
-        res[i] = rf
-        log(f"batched: fp64 finish {inst.label}: {r.iters} mixed + {rf.iters - r.iters} fp64 iterations, "
-            f"eta {rf.eta_dot:.2e}")
-        del buf
-        plan.close()
+    pending = [i for i, r in enumerate(res) if not _converged(r)]
+    if pending:
+        fb = B.dot_batch_create([insts[i] for i in pending], tol=TOL, max_iter=FINISH_MAX_ITER,
+                                precision=B.DOT_FP64)
+        fws = torch.zeros(fb.workspace_bytes, dtype=torch.uint8, device="cuda")
+        B.dot_batch_reset(fb, fws.data_ptr(), st)
+        for slot, i in enumerate(pending):
+            B.dot_batch_promote_member(batch, ws.data_ptr(), i, fb, fws.data_ptr(), slot, st)
+        left = FINISH_MAX_ITER - done
+        k = 0
+        rf_all = None
+        while k < left:
+            step = min(5000, left - k)
+            rf_all = B.dot_batch_run(fb, fws.data_ptr(), step, st)
+            k += step
+            nconv = sum(1 for r in rf_all if _converged(r))
+            log(f"batched: fp64 finish batch of {len(pending)}: {k} iterations, {nconv} converged, "
+                f"{time.perf_counter() - t0:.1f} s")
+            if all(B.TERM_NAMES[r.term] in ("converged", "diverged") for r in rf_all):
+                break
+        for slot, i in enumerate(pending):
+            r, rf = res[i], rf_all[slot]
+            finished[insts[i].label] = {"mixed_iters": r.iters, "mixed_eta_dot": r.eta_dot,
+                                        "fp64_iters_after": rf.iters - r.iters, "eta_dot": rf.eta_dot,
+                                        "term": B.TERM_NAMES[rf.term],
+                                        "objective_change_rel": abs(rf.objective - r.objective) / abs(rf.objective)}
+            res[i] = rf
+            log(f"batched: fp64 finish {insts[i].label}: {r.iters} mixed + {rf.iters - r.iters} fp64 iterations, "
+                f"eta {rf.eta_dot:.2e}")
+        del fws
+        fb.close()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     conv = sum(1 for r in res if _converged(r))

@@ -410,6 +410,18 @@ int dot_state_promote(const dot_plan* mixed_plan, const void* mixed_state, dot_p
  * instance's problem in DOT_FP64. The batch is not modified. */
 int dot_batch_promote(const dot_batch* batch, const void* workspace, int32_t index, dot_plan* fp64_plan,
                       void* fp64_state, void* stream);
+/* The same into member `slot` of a DOT_FP64 batch (`fp64_batch`, workspace
+ * `fp64_workspace`), whose problem at that slot must be instance `index`'s
+ * problem: its state and control block are overwritten, so that
+ * dot_batch_run on the FP64 batch continues every promoted member together
+ * (one launch per kernel, each member bitwise as dot_batch_promote +
+ * dot_run). Members of a batch iterate in lockstep, so the FP64 batch takes
+ * the mixed batch's iteration count: DOT_EINVAL if it has already run to
+ * another count (promote after dot_batch_reset, all from one mixed batch and
+ * iteration). Members not promoted keep their state (after a reset: zero, as
+ * a fresh solve). Blocks. */
+int dot_batch_promote_member(const dot_batch* batch, const void* workspace, int32_t index, dot_batch* fp64_batch,
+                             void* fp64_workspace, int32_t slot, void* stream);
 /* One-shot multilevel solve with `levels` coarser grids (0 = plain solve):
  * allocates, solves level by level on the default stream, copies rho / m of
  * the target grid (as dot_solve) and frees. res: the target level;

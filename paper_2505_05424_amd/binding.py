@@ -36,7 +36,7 @@ EXPORTED = [
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
     "dot_step_residuals_noalloc", "dot_ctx_export", "dot_ctx_import", "dot_ctx_last_error", "dot_batch_promote",
-    "dot_ctx_keep_capped",
+    "dot_ctx_keep_capped", "dot_batch_promote_member",
 ]
 NOALLOC_SCRATCH_BYTES = 8 << 20
 
@@ -205,6 +205,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
     lib.dot_prolong.argtypes = [vp, vp, vp, vp, vp]
     lib.dot_state_promote.argtypes = [vp, vp, vp, vp, vp]
     lib.dot_batch_promote.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.dot_batch_promote_member.argtypes = [vp, vp, i32, vp, vp, i32, vp]
     pd = ctypes.POINTER(ctypes.c_double)
     lib.dot_state_export.argtypes = [vp, vp, pd, pd, pd, pd, vp]
     lib.dot_state_import.argtypes = [vp, vp, pd, pd, pd, dbl, vp]
@@ -660,6 +661,14 @@ def dot_state_promote(mixed_plan, mixed_state_ptr: int, fp64_plan, fp64_state_pt
 def dot_batch_promote(batch, ws_ptr: int, index: int, fp64_plan, fp64_state_ptr: int, stream: int = 0):
     _check(load().dot_batch_promote(batch.handle, ctypes.c_void_p(ws_ptr), int(index), fp64_plan.handle,
                                     ctypes.c_void_p(fp64_state_ptr), ctypes.c_void_p(stream)))
+
+
+def dot_batch_promote_member(batch, ws_ptr: int, index: int, fp64_batch, fp64_ws_ptr: int, slot: int,
+                             stream: int = 0):
+    """Promote member `index` of a mixed batch into member `slot` of an FP64
+    batch of the same problems (see include/dotsocp.h)."""
+    _check(load().dot_batch_promote_member(batch.handle, ctypes.c_void_p(ws_ptr), int(index), fp64_batch.handle,
+                                           ctypes.c_void_p(fp64_ws_ptr), int(slot), ctypes.c_void_p(stream)))
 
 
 def dot_prolong(coarse: Plan, coarse_state_ptr: int, fine: Plan, fine_state_ptr: int, stream: int = 0):

@@ -2498,6 +2498,31 @@ int dot_batch_promote(const dot_batch* B, const void* ws, int32_t index, dot_pla
                       (hipStream_t)stream);
 }
 
+int dot_batch_promote_member(const dot_batch* Bm, const void* ws_m, int32_t index, dot_batch* Bf, void* ws_f,
+                             int32_t slot, void* stream) {
+  if (!Bm || !ws_m || !Bf || !ws_f) return fail(DOT_EINVAL, "null argument");
+  if (index < 0 || index >= (int)Bm->plans.size()) return fail(DOT_EINVAL, "instance index out of range");
+  if (slot < 0 || slot >= (int)Bf->plans.size()) return fail(DOT_EINVAL, "slot index out of range");
+  if (Bf->it != 0 && Bf->it != Bm->it)
+    return fail(DOT_EINVAL, "the FP64 batch is at iteration " + std::to_string(Bf->it) + ", the mixed one at " +
+                                std::to_string(Bm->it) + ": its members iterate in lockstep");
+  hipStream_t st = (hipStream_t)stream;
+  const char* bm = static_cast<const char*>(ws_m);
+  char* bf = static_cast<char*>(ws_f);
+  dot_plan* F = Bf->plans[slot];
+  int rc = promote_impl(Bm->plans[index], bm + Bm->state_off[index],
+                        reinterpret_cast<const Ctl*>(bm + (size_t)index * Bm->ctl_stride), F, bf + Bf->state_off[slot],
+                        st);
+  if (rc) return rc;
+  // a batch keeps its members' control blocks at the head of its workspace
+  Ctl* hc = reinterpret_cast<Ctl*>(reinterpret_cast<char*>(Bf->host_ctl) + (size_t)slot * Bf->ctl_stride);
+  *hc = *F->host_ctl;
+  HIP_OK(hipMemcpyAsync(bf + (size_t)slot * Bf->ctl_stride, hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+  HIP_OK(hipStreamSynchronize(st));
+  Bf->it = Bm->it;
+  return DOT_OK;
+}
+
 int dot_prolong(const dot_plan* C, const void* coarse_state, dot_plan* F, void* fine_state, void* stream) {
   if (!C || !F || !coarse_state || !fine_state) return fail(DOT_EINVAL, "null argument");
   if (C->D != F->D || C->precision != F->precision) return fail(DOT_EINVAL, "plans differ in D or precision");

@@ -103,3 +103,43 @@ def test_compaction_from_two_branches_to_one_stream():
     assert res[0].iters < 40 and res[1].iters == iters
     assert B.dot_batch_laid_out(batch) == 1
     _check_members(batch, ws, st, res, insts, tols, B.DOT_MIXED, iters)
+
+
+def test_promoted_members_continue_together_in_an_fp64_batch():
+    """Members of a mixed batch promoted into an FP64 batch of their problems
+    continue bitwise as dot_batch_promote + dot_run of each; the FP64 batch
+    takes the mixed batch's iteration count, and a promotion from another
+    count is refused."""
+    insts = [dotgen.tiny_instance(2, (8, 20, 24), seed=181, floor=0.0, masked=True),
+             dotgen.tiny_instance(2, (4, 7, 300), seed=182, floor=0.0),
+             dotgen.tiny_instance(2, (6, 10, 12), seed=183, floor=0.0, masked=True)]
+    torch = G.torch_mod()
+    st = G.stream_handle()
+    print("[case] promotion of mixed batch members into an FP64 batch", flush=True)
+    mb = B.dot_batch_create(insts, tol=-1.0, max_iter=10 ** 6, precision=B.DOT_MIXED)
+    mws = torch.zeros(int(mb.workspace_bytes), dtype=torch.uint8, device="cuda")
+    B.dot_batch_reset(mb, mws.data_ptr(), st)
+    B.dot_batch_run(mb, mws.data_ptr(), 120, st)
+    picked = [0, 1]
+    fb = B.dot_batch_create([insts[i] for i in picked], tol=-1.0, max_iter=10 ** 6, precision=B.DOT_FP64)
+    fws = torch.zeros(int(fb.workspace_bytes), dtype=torch.uint8, device="cuda")
+    B.dot_batch_reset(fb, fws.data_ptr(), st)
+    for slot, i in enumerate(picked):
+        B.dot_batch_promote_member(mb, mws.data_ptr(), i, fb, fws.data_ptr(), slot, st)
+    res = B.dot_batch_run(fb, fws.data_ptr(), 80, st)
+    for slot, i in enumerate(picked):
+        inst = insts[i]
+        plan = B.dot_plan_create(inst.D, inst.n, inst.rho0, inst.rho1, inst.mask, tol=-1.0, max_iter=10 ** 6)
+        s = G.GpuState(plan)
+        B.dot_batch_promote(mb, mws.data_ptr(), i, plan, s.ptr, st)
+        r = s.run(80)
+        assert res[slot].iters == r.iters == 200, (slot, res[slot].iters, r.iters)
+        assert res[slot].objective == r.objective and res[slot].eta_dot == r.eta_dot, slot
+        rho_b, m_b = B.dot_batch_extract(fb, fws.data_ptr(), slot, st)
+        rho, m = s.extract()
+        assert np.array_equal(rho_b, rho), slot
+        for a, b in zip(m_b, m):
+            assert np.array_equal(a, b), slot
+    # the FP64 batch is now at 200 iterations, the mixed one at 120
+    with pytest.raises(B.DotError):
+        B.dot_batch_promote_member(mb, mws.data_ptr(), 2, fb, fws.data_ptr(), 0, st)
