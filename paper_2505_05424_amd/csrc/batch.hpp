@@ -120,6 +120,22 @@ kb_beta_cone_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map
   rhs_body<T, D, DEFECT>(s.g, s.q[par ^ 1], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
 }
 
+// z-step and right-hand side of one iteration in one launch, where neither
+// can join the previous beta update (after a residual check, whose sigma
+// decision they must see, and at the start of a run): both read q[par] and
+// write disjoint planes (W and dw; the transform work plane), and neither
+// reads what the other writes.
+template <typename T, int D, bool DEFECT>
+__global__ void __launch_bounds__(256)
+kb_cone_rhs(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int par) {
+  const uint32_t L = xcd_remap(blockIdx.x, gridDim.x);
+  const Inst<T>& s = I[inst_of_block(map, L)];
+  if (stopped(s)) return;
+  const double inv_sigma = 1.0 / glob(s.ctl)->sigma;
+  cone_body<T, D>(s.g, s.q[par], s.beta, s.sw, s.W, s.dw, s.ctl, L - s.blk0);
+  rhs_body<T, D, DEFECT>(s.g, s.q[par], s.alpha, s.phi, s.c_lo, s.c_hi, s.work, inv_sigma, L - s.blk0);
+}
+
 // Right-hand side (or its defect against phi) of the Poisson solve into the
 // transform work plane, from (q[par], alpha).
 template <typename T, int D, bool DEFECT>
@@ -142,9 +158,9 @@ kb_resid(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int pa
   resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials, L - s.blk0);
 }
 
-// One block per instance.
+// One block of 256 threads per instance.
 template <typename T>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(256)
 kb_finalize(const Inst<T>* __restrict__ I, int update_ctl) {
   const Inst<T>& s = I[blockIdx.x];
   finalize_body(s.fa, s.partials, s.ctl, update_ctl);  // returns before the update if the instance stopped

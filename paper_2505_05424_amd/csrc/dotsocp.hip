@@ -722,6 +722,19 @@ int launch_cone(const Exec& E, int par, hipStream_t st) {
   return DOT_OK;
 }
 
+// z-step and right-hand side of iteration par in one launch (runs only
+// where the z-step may precede the phi-step: no one-lane elimination, whose
+// checkpoints use W plane 0).
+template <typename T, int D>
+int launch_cone_rhs(const Exec& E, int par, hipStream_t st) {
+  constexpr bool kMixed = !std::is_same<T, double>::value;
+  ProfScope ps(E.prof, DOT_K_CONE, st);
+  hipLaunchKernelGGL((kb_cone_rhs<T, D, kMixed>), dim3(E.grid_nodes), dim3(kBlock), 0, st, (const Inst<T>*)E.d_inst,
+                     E.map_nodes, par);
+  HIP_OK(hipGetLastError());
+  return DOT_OK;
+}
+
 template <typename T, int D>
 int launch_q(const Exec& E, int par, hipStream_t st) {
   ProfScope ps(E.prof, DOT_K_QD, st);
@@ -858,11 +871,17 @@ int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more,
     cy->cone_ready = false;
     return DOT_OK;
   }
-  if ((rc = poisson_iter<T, D>(E, par, st, cy->rhs_ready))) return rc;
-  if (!cy->cone_ready && (rc = launch_cone<T, D>(E, par, st))) return rc;
-  if ((rc = launch_q<T, D>(E, par, st))) return rc;
   // kernel classes timed one by one run unfused
-  const bool fuse = !check && more && !(E.prof && E.prof->cls >= 0);
+  const bool timing = E.prof && E.prof->cls >= 0;
+  bool rhs_ready = cy->rhs_ready, cone_ready = cy->cone_ready;
+  if (!rhs_ready && !cone_ready && E.ntri_long == 0 && !timing) {
+    if ((rc = launch_cone_rhs<T, D>(E, par, st))) return rc;
+    rhs_ready = cone_ready = true;
+  }
+  if ((rc = poisson_iter<T, D>(E, par, st, rhs_ready))) return rc;
+  if (!cone_ready && (rc = launch_cone<T, D>(E, par, st))) return rc;
+  if ((rc = launch_q<T, D>(E, par, st))) return rc;
+  const bool fuse = !check && more && !timing;
   const bool fuse_cone = fuse && E.ntri_long == 0;
   if ((rc = launch_beta<T, D>(E, par, check, st, fuse, fuse_cone))) return rc;
   if (check && (rc = check_iter<T, D>(E, par ^ 1, 1, st))) return rc;

@@ -30,6 +30,7 @@ def kernel_bytes(D: int, n: Sequence[int], w: int) -> Dict[str, float]:
     rhs = w * Q + a * Q + w * Nc + (8 * Nc if mixed else 0)
     beta = w * (2 * Q + 2 * K * S)
     beta_cone = w * (2 * Q + 2 * K * S + 4 * D * S) + 8 * S
+    cone = w * (Q + K * S + 4 * D * S) + 8 * S
     return {
         # b (FP64) or b - A^*A phi (mixed): read q, alpha (and phi); write the work plane
         "rhs": rhs,
@@ -39,7 +40,9 @@ def kernel_bytes(D: int, n: Sequence[int], w: int) -> Dict[str, float]:
         # D launches: D-1 plain inverse passes and the time-axis one
         "dct_inv": ((D - 1) * 2 * w * Nc + last_inv) / D,
         # cone (z-step): read q, beta; write 4D weighted w planes and w_{K-1} - w_0 (FP64)
-        "cone": w * (Q + K * S + 4 * D * S) + 8 * S,
+        "cone": cone,
+        # the z-step and the right-hand side of one iteration in one launch (q counted once)
+        "cone_rhs": cone + rhs - w * Q,
         # q-step: read phi, alpha, the 4D w planes and w_{K-1} - w_0; write q, alpha
         "qd": w * (Q + 4 * D * S) + 8 * S + 2 * a * Q + 8 * Nc,
         # beta: read q_old, q_new, beta; write beta
