@@ -664,8 +664,9 @@ def main():
         },
         "kernel_breakdown_one_solve": breakdown,
         "kernel_breakdown_note": ("one solve per class with HIP events around every launch of that class: "
-                                  "graphs off and the beta + next right-hand-side fusion off, so the classes sum "
-                                  "to more than the timed solve (which runs graphs and the fused launch)"),
+                                  "graphs off and the fused launches split into their classes (beta + next z-step "
+                                  "+ next right-hand side; z-step + right-hand side), so the classes sum to more "
+                                  "than the timed solve (which runs graphs and the fused launches)"),
         "roofline_bandwidth_bound_size": large,
     }
     log("large instance 32x1024x1024")
