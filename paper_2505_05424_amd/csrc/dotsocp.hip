@@ -106,12 +106,15 @@ struct ProfScope {
 
 // A captured block of kGraphIters iterations starting at a multiple of 10
 // (the parity of q and the positions of the residual checks repeat with
-// period 10, so one graph serves every such block). Capture happens only
-// after plain launches have run once (one-time kernel attribute calls stay
-// outside any capture).
+// period 10, so one graph serves every such block), and one of the iterations
+// between two polls of the control blocks (four such blocks; one graph launch
+// per poll instead of four: 2D 32x64^2 FP64 51.3 -> 50.9 us per iteration).
+// Capture happens only after plain launches have run once (one-time kernel
+// attribute calls stay outside any capture).
 constexpr int kGraphIters = 10;
 struct GraphCache {
   hipGraphExec_t exec = nullptr;
+  hipGraphExec_t exec_poll = nullptr;  // the iterations between two polls
   hipStream_t cap = nullptr;       // private capture stream (default priority)
   hipStream_t cap_side = nullptr;  // second branch of the captured iterations
   hipStream_t side = nullptr;      // second branch of plain launches
@@ -120,6 +123,7 @@ struct GraphCache {
   bool warm = false;
   ~GraphCache() {
     if (exec) (void)hipGraphExecDestroy(exec);
+    if (exec_poll) (void)hipGraphExecDestroy(exec_poll);
     if (cap) (void)hipStreamDestroy(cap);
     if (cap_side) (void)hipStreamDestroy(cap_side);
     if (side) (void)hipStreamDestroy(side);
@@ -133,6 +137,8 @@ struct GraphCache {
 void drop_graph(GraphCache& g) {
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   g.exec = nullptr;
+  if (g.exec_poll) (void)hipGraphExecDestroy(g.exec_poll);
+  g.exec_poll = nullptr;
 }
 
 // Transform schedule of an executor: tile width (lines per workgroup) and
@@ -891,12 +897,12 @@ int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more,
   return DOT_OK;
 }
 
-// Capture kGraphIters iterations starting at an iteration count it (it % 10
-// == 0 keeps the check positions aligned) into a graph, on the cache's own
+// Capture n iterations (a multiple of kGraphIters) starting at an iteration
+// count it (it % 10 == 0 keeps the check positions aligned) into a graph, on the cache's own
 // stream (the caller's stream may be the legacy default stream, which cannot
 // be captured); the graph is then launched on the caller's stream.
 template <typename T, int D>
-int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
+int capture_block(const Exec& E, int it, hipGraphExec_t* out, int n = kGraphIters) {
   Exec Ec = E;
   Ec.prof = nullptr;  // no events inside a captured graph
   if (!E.graphs->cap) HIP_OK(hipStreamCreateWithFlags(&E.graphs->cap, hipStreamNonBlocking));
@@ -911,7 +917,7 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out) {
   HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
   int rc = DOT_OK;
   Carry cy;
-  for (int k = 0; k < kGraphIters && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st, side, k + 1 < kGraphIters, &cy);
+  for (int k = 0; k < n && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st, side, k + 1 < n, &cy);
   hipError_t e = hipStreamEndCapture(st, &graph);
   if (rc) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -957,8 +963,15 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
   while (j < max_iters) {
     const int it = it0 + j;
     int rc;
-    if (graphs && E.graphs->warm && it % kGraphIters == 0 && max_iters - j >= kGraphIters && !cy.rhs_ready &&
-        !cy.cone_ready && !cy.beta_pending) {
+    const bool blk_ok = graphs && E.graphs->warm && it % kGraphIters == 0 && !cy.rhs_ready && !cy.cone_ready &&
+                        !cy.beta_pending;
+    if (blk_ok && since_poll == 0 && max_iters - j >= poll) {
+      hipGraphExec_t& ex = E.graphs->exec_poll;
+      if (!ex && (rc = capture_block<T, D>(E, it, &ex, poll))) return rc;
+      HIP_OK(hipGraphLaunch(ex, st));
+      j += poll;
+      since_poll += poll;
+    } else if (blk_ok && max_iters - j >= kGraphIters) {
       hipGraphExec_t& ex = E.graphs->exec;
       if (!ex && (rc = capture_block<T, D>(E, it, &ex))) return rc;
       HIP_OK(hipGraphLaunch(ex, st));
