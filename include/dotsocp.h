@@ -205,7 +205,8 @@ int dot_step_residuals(dot_plan* plan, const void* phi, const void* z, const voi
  * DOT_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
  * until the process ends, instead of the plan's buffers. A plan needs 768
  * bytes for the control block plus 160 bytes per workgroup of its residual
- * sweep (about 9,700 workgroups for 3D 32x64^3, 37,000 for 2D 32x1024^2);
+ * sweep (about 9,700 workgroups for 3D 32x64^3, 37,000 for 2D 32x1024^2) and
+ * 10,240 bytes for the first stage of their reduction;
  * beyond the array's size the call returns DOT_EINVAL before any device work.
  * The current device must be the plan's (DOT_EINVAL otherwise). Every call on
  * one GPU shares that GPU's array and leaves the last call's contents in it;

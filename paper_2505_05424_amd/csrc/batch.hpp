@@ -158,6 +158,17 @@ kb_resid(const Inst<T>* __restrict__ I, const uint16_t* __restrict__ map, int pa
   resid_body<T, D>(s.g, s.phi, s.q[par], s.alpha, s.beta, s.om, s.sw, s.c_lo, s.c_hi, s.partials, L - s.blk0);
 }
 
+// First stage of the residual reduction: kFinChunks blocks per instance
+// (block b: instance b / kFinChunks, chunk b % kFinChunks); instances below
+// kFinStageMinRows rows return at once.
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_fin_stage(const Inst<T>* __restrict__ I) {
+  const Inst<T>& s = I[blockIdx.x / kFinChunks];
+  if (!s.fa.staged || stopped(s)) return;
+  fin_stage_body(s.fa, s.partials, (int)(blockIdx.x % kFinChunks));
+}
+
 // One block of 256 threads per instance.
 template <typename T>
 __global__ void __launch_bounds__(256)

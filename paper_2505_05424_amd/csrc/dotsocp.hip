@@ -535,6 +535,7 @@ FinArgs fin_args(const dot_plan* P) {
   fa.c_norm2 = P->c_norm2;
   fa.d_norm2 = P->d_norm2;
   fa.nblocks = P->nblocks;
+  fa.staged = P->nblocks >= kFinStageMinRows ? 1 : 0;
   return fa;
 }
 
@@ -595,6 +596,7 @@ Ctl initial_ctl(const dot_plan* P) {
 struct Exec {
   int D = 0, precision = 0, ninst = 0, cadence = 5;
   int nact = 0;  // instances with workgroups in the launch grids (a compacted batch leaves out stopped ones)
+  int nstaged = 0;  // of those, instances whose residual partials take the two-stage reduction
   void* d_inst = nullptr;
   const uint16_t* map_nodes = nullptr;
   const uint16_t* map_axis[kMaxAxes] = {nullptr, nullptr, nullptr, nullptr};
@@ -780,8 +782,9 @@ int update_iter(const Exec& E, int par, int check, hipStream_t st, bool rhs_next
   return launch_beta<T, D>(E, par, check, st, rhs_next);
 }
 
-// Residual partials at the iterate in q[qpar], then one finalize block per
-// instance.
+// Residual partials at the iterate in q[qpar], the first stage of their
+// reduction (kFinChunks blocks per instance; large instances only), then one
+// finalize block per instance.
 template <typename T, int D>
 int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
   const Inst<T>* I = (const Inst<T>*)E.d_inst;
@@ -792,6 +795,10 @@ int check_iter(const Exec& E, int qpar, int update_ctl, hipStream_t st) {
   HIP_OK(hipGetLastError());
   {
     ProfScope ps(E.prof, DOT_K_FINAL, st);
+    if (E.nstaged > 0) {
+      hipLaunchKernelGGL((kb_fin_stage<T>), dim3(E.ninst * kFinChunks), dim3(256), 0, st, I);
+      HIP_OK(hipGetLastError());
+    }
     hipLaunchKernelGGL((kb_finalize<T>), dim3(E.ninst), dim3(256), 0, st, I, update_ctl);
   }
   HIP_OK(hipGetLastError());
@@ -1068,6 +1075,7 @@ Exec plan_exec(dot_plan* P, int slot) {
   E.grid_nodes = (unsigned)P->nblocks;
   E.ntri = P->tri ? 1 : 0;
   E.ntri_long = P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
+  E.nstaged = P->nblocks >= kFinStageMinRows ? 1 : 0;
   E.nodes = P->g.nb;
   for (int a = 0; a <= P->D; ++a) {
     E.map_axis[a] = nullptr;
@@ -1238,9 +1246,10 @@ int noalloc_ptr(int device, unsigned char** out) {
 }
 
 // Bytes of the scratch array one residual evaluation of P takes: the control
-// block, then kNumSums partial rows of one entry per workgroup.
+// block, then kNumSums partial rows of one entry per workgroup and the
+// kFinChunks stage rows of the reduction.
 size_t noalloc_bytes(const dot_plan* P) {
-  return align256(sizeof(Ctl)) + (size_t)kNumSums * (size_t)P->nblocks * sizeof(double);
+  return align256(sizeof(Ctl)) + (size_t)kNumSums * (size_t)(P->nblocks + kFinChunks) * sizeof(double);
 }
 
 template <typename T, int D>
@@ -1404,10 +1413,12 @@ int batch_layout(dot_batch* B, const Sched& s, const std::vector<char>* act = nu
   E.grid_nodes = (unsigned)map_off[0];
   E.ntri = 0;
   E.ntri_long = 0;
+  E.nstaged = 0;
   E.nodes = 0;
   for (dot_plan* P : plans) {
     E.ntri += P->tri ? 1 : 0;
     E.ntri_long += P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
+    E.nstaged += P->nblocks >= kFinStageMinRows ? 1 : 0;
     E.nodes += P->g.nb;
   }
   E.map_nodes = B->d_maps;
@@ -1825,11 +1836,13 @@ int dot_plan_create(const dot_problem* p, dot_plan** out) {
   P->off_dw = lay.off_dw;
   P->ctl_offset = lay.ctl_offset;
   P->partials_offset = P->ctl_offset + align256(sizeof(Ctl));
-  P->state_bytes = P->partials_offset + align256((size_t)P->partial_rows * kNumSums * sizeof(double));
+  // partial rows, then the stage rows of their first reduction stage
+  const size_t partial_bytes = (size_t)(P->partial_rows + kFinChunks) * kNumSums * sizeof(double);
+  P->state_bytes = P->partials_offset + align256(partial_bytes);
   if (P->precision == DOT_MIXED) HIP_OK(hipMalloc(&P->step_scratch, pb));
   HIP_OK(hipMalloc((void**)&P->step_ctl, sizeof(Ctl)));
-  HIP_OK(hipMalloc((void**)&P->step_partials, (size_t)P->partial_rows * kNumSums * sizeof(double)));
-  HIP_OK(hipMemset(P->step_partials, 0, (size_t)P->partial_rows * kNumSums * sizeof(double)));
+  HIP_OK(hipMalloc((void**)&P->step_partials, partial_bytes));
+  HIP_OK(hipMemset(P->step_partials, 0, partial_bytes));
   HIP_OK(hipHostMalloc((void**)&P->host_ctl, sizeof(Ctl), hipHostMallocDefault));
   HIP_OK(hipMalloc(&P->d_inst, 2 * inst_slot_bytes()));
   *out = P.release();
@@ -2823,6 +2836,7 @@ int ctx_rebuild(dot_ctx* C, hipStream_t st) {
   for (dot_plan* P : act) {
     E.ntri += P->tri ? 1 : 0;
     E.ntri_long += P->tri && P->g.N[P->D] > kTriPartMaxNodes ? 1 : 0;
+    E.nstaged += P->nblocks >= kFinStageMinRows ? 1 : 0;
     E.nodes += P->g.nb;
   }
   size_t map_off[kMaxAxes] = {0, 0, 0, 0};
@@ -3016,8 +3030,9 @@ size_t dot_footprint_bytes(const dot_problem* p) {
   s += (size_t)(4 * D + 2 + 4 * D) * pb;                     // beta, W
   s = align256(s) + nb * 8;                                  // w_{K-1} - w_0 (FP64)
   s = align256(s) + align256(sizeof(Ctl));
-  s += align256((nb / ((size_t)p->n[0] + 1) + kBlock - 1) / kBlock * ((size_t)p->n[0] + 1) * kNumSums *
-                sizeof(double));
+  // partial rows (one per workgroup at one slice each), then the reduction's stage rows
+  const size_t rows = (nb / ((size_t)p->n[0] + 1) + kBlock - 1) / kBlock * ((size_t)p->n[0] + 1) + kFinChunks;
+  s += align256(rows * kNumSums * sizeof(double));
   return s;
 }
 

@@ -772,15 +772,47 @@ struct FinArgs {
   double c_norm2;  // sum c~^2
   double d_norm2;  // sum d^2 = 2 * number of cells
   int64_t nblocks;
+  int32_t staged;  // the partials are reduced in two stages (nblocks >= kFinStageMinRows)
 };
+
+// The workgroup partials of a large instance are reduced in two stages:
+// kFinChunks workgroups each sum a contiguous range of the rows into one
+// stage row (one workgroup alone is bound by how many loads one CU keeps in
+// flight: 8,547 rows took 35 us, 36,945 rows 133 us), then the finalize block
+// sums the stage rows. The stage rows follow the partial rows: slot k of
+// stage row c at partials[kNumSums * nblocks + k * kFinChunks + c]. Below
+// kFinStageMinRows rows the finalize block sums the rows itself (the extra
+// launch cost more than it saved there).
+constexpr int kFinChunks = 64;
+constexpr int64_t kFinStageMinRows = 8192;
+
+__device__ __forceinline__ double* fin_stage_rows(const FinArgs& fa, double* partials) {
+  return partials + (size_t)kNumSums * (size_t)fa.nblocks;
+}
+
+// First stage: rows [n c / kFinChunks, n (c + 1) / kFinChunks) of every slot,
+// each thread adding its rows in order, then the wave and block sums.
+__device__ __forceinline__ void fin_stage_body(const FinArgs& fa, double* __restrict__ partials, int chunk) {
+  const int64_t n = fa.nblocks;
+  const int64_t r0 = n * chunk / kFinChunks, r1 = n * (chunk + 1) / kFinChunks;
+  gp<const double> pr = glob(partials);
+  double v[kNumSums];
+#pragma unroll
+  for (int k = 0; k < kNumSums; ++k) v[k] = 0.0;
+  for (int64_t j = r0 + threadIdx.x; j < r1; j += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) v[k] += pr[k * n + j];
+  }
+  block_partials<kNumSums>(v, fin_stage_rows(fa, partials), (uint32_t)chunk, (uint32_t)kFinChunks, -1);
+}
 
 __device__ __forceinline__ double eta_ratio(double num2, double a2, double b2, double vol) {
   return sqrt(vol * num2) / (1.0 + sqrt(vol * a2) + sqrt(vol * b2));
 }
 
-// Sums the block partials in a fixed order, forms the residuals, applies the
-// sigma rule of Sec. 5.3 on its schedule and sets the stop flag. One block
-// per instance.
+// Sums the block partials (their stage rows when staged) in a fixed order,
+// forms the residuals, applies the sigma rule of Sec. 5.3 on its schedule and
+// sets the stop flag. One block per instance, after fin_stage_body.
 __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* __restrict__ partials,
                                               Ctl* __restrict__ ctl, int update_ctl) {
   __shared__ double acc[1024 / 64][kNumSums];
@@ -790,19 +822,20 @@ __device__ __forceinline__ void finalize_body(const FinArgs& fa, const double* _
   // the partial sums
   CtlState c;
   if (threadIdx.x == 0) c = *static_cast<const CtlState*>(ctl);
-  // one pass over the workgroup partials: each thread sums every slot of its
-  // workgroups (slot-major rows, read coalesced), then the slots are reduced
-  // across the block; waves past the last workgroup hold zeros and skip the
+  // one pass over the stage rows (or the workgroup rows): each thread sums
+  // every slot of its rows (slot-major, read coalesced), then the slots are
+  // reduced across the block; waves past the last row hold zeros and skip the
   // cross-lane sums
-  gp<const double> pr = glob(partials);
+  const int64_t rows = fa.staged ? kFinChunks : fa.nblocks;
+  gp<const double> pr = glob(fa.staged ? fin_stage_rows(fa, const_cast<double*>(partials)) : partials);
   double v[kNumSums];
 #pragma unroll
   for (int k = 0; k < kNumSums; ++k) v[k] = 0.0;
-  for (int64_t j = threadIdx.x; j < fa.nblocks; j += blockDim.x) {
+  for (int64_t j = threadIdx.x; j < rows; j += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) v[k] += pr[k * fa.nblocks + j];
+    for (int k = 0; k < kNumSums; ++k) v[k] += pr[k * rows + j];
   }
-  if ((int64_t)w * 64 < fa.nblocks) wave_sums<kNumSums>(v);
+  if ((int64_t)w * 64 < rows) wave_sums<kNumSums>(v);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) acc[w][k] = v[k];
