@@ -1493,6 +1493,14 @@ struct BatchRunF {
     const int count = (int)B->plans.size();
     HIP_OK(hipMemcpyAsync(B->host_ctl, ws, B->ctl_stride * count, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    const char* hc = reinterpret_cast<const char*>(B->host_ctl);
+    bool any_running = false;
+    for (int i = 0; i < count; ++i)
+      any_running = any_running || !reinterpret_cast<const Ctl*>(hc + (size_t)i * B->ctl_stride)->stop;
+    if (!any_running) {  // nothing to iterate: no launch at all
+      if (done) *done = 0;
+      return DOT_OK;
+    }
     int rc = batch_compact<T>(B, ws, st, true);
     if (rc || (rc = batch_descriptors<T>(B, ws, st))) return rc;
     // the smallest time budget of the instances bounds the call

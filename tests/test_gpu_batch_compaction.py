@@ -143,3 +143,18 @@ def test_promoted_members_continue_together_in_an_fp64_batch():
     # the FP64 batch is now at 200 iterations, the mixed one at 120
     with pytest.raises(B.DotError):
         B.dot_batch_promote_member(mb, mws.data_ptr(), 2, fb, fws.data_ptr(), 0, st)
+
+
+def test_run_of_a_batch_whose_instances_all_stopped_changes_nothing():
+    """Once every instance has stopped, dot_batch_run launches nothing and
+    returns the same results."""
+    insts = [dotgen.tiny_instance(2, (4, 7, 300), seed=151, floor=0.0, masked=True),
+             dotgen.tiny_instance(2, (8, 20, 24), seed=161, floor=0.0)]
+    tols = [0.3, 0.1]
+    print("[case] run after every instance stopped", flush=True)
+    batch, ws, st, res = _run_batch(insts, tols, B.DOT_FP64, 200)
+    assert all(B.TERM_NAMES[r.term] == "converged" for r in res)
+    before = G.host(ws).copy()
+    res2 = B.dot_batch_run(batch, ws.data_ptr(), 200, st)
+    assert [(r.iters, r.objective, r.eta_dot) for r in res2] == [(r.iters, r.objective, r.eta_dot) for r in res]
+    assert np.array_equal(G.host(ws), before)
