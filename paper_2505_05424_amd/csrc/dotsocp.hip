@@ -37,6 +37,14 @@ namespace {
 
 thread_local std::string g_err;
 
+// Graph captures and the calls that allocate, free or otherwise synchronise
+// the whole device are serialised across host threads: such a call from one
+// thread while another thread captures can invalidate that capture (the
+// serving driver steps one context per host thread). Recursive, since entry
+// points that hold it call others that take it.
+std::recursive_mutex g_dev_mu;
+using DevLock = std::lock_guard<std::recursive_mutex>;
+
 int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -910,6 +918,7 @@ int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more,
 // be captured); the graph is then launched on the caller's stream.
 template <typename T, int D>
 int capture_block(const Exec& E, int it, hipGraphExec_t* out, int n = kGraphIters) {
+  DevLock lk(g_dev_mu);
   Exec Ec = E;
   Ec.prof = nullptr;  // no events inside a captured graph
   if (!E.graphs->cap) HIP_OK(hipStreamCreateWithFlags(&E.graphs->cap, hipStreamNonBlocking));
@@ -925,6 +934,12 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out, int n = kGraphIter
   int rc = DOT_OK;
   Carry cy;
   for (int k = 0; k < n && !rc; ++k) rc = one_iter<T, D>(Ec, it + k, st, side, k + 1 < n, &cy);
+  if (rc && side) {
+    // a failure between fork and join: join the second branch back before the
+    // capture ends (errors ignored; the capture is abandoned anyway)
+    (void)hipEventRecord(E.graphs->join, side);
+    (void)hipStreamWaitEvent(st, E.graphs->join, 0);
+  }
   hipError_t e = hipStreamEndCapture(st, &graph);
   if (rc) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -933,7 +948,10 @@ int capture_block(const Exec& E, int it, hipGraphExec_t* out, int n = kGraphIter
   if (e != hipSuccess) return fail(DOT_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
-  if (e != hipSuccess) return fail(DOT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  if (e != hipSuccess) {
+    *out = nullptr;
+    return fail(DOT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
   return DOT_OK;
 }
 
@@ -957,7 +975,8 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
       if (!reinterpret_cast<const Ctl*>(static_cast<const char*>(ctl_host) + i * ctl_stride)->stop) return false;
     return true;
   };
-  const bool graphs = E.graphs && E.graphs->enabled && !(E.prof && E.prof->cls >= 0) && E.cadence == 5;
+  bool use_graphs = E.graphs && E.graphs->enabled && !(E.prof && E.prof->cls >= 0) && E.cadence == 5;
+  int capture_failures = 0;
   hipStream_t side = nullptr;
   if (overlapped(E)) {
     int rc0 = branch_streams(E.graphs);
@@ -970,22 +989,36 @@ int run_iters(const Exec& E, int it0, int max_iters, const void* ctl_dev, size_t
   while (j < max_iters) {
     const int it = it0 + j;
     int rc;
-    const bool blk_ok = graphs && E.graphs->warm && it % kGraphIters == 0 && !cy.rhs_ready && !cy.cone_ready &&
-                        !cy.beta_pending;
+    const bool blk_ok = use_graphs && E.graphs->warm && it % kGraphIters == 0 && !cy.rhs_ready &&
+                        !cy.cone_ready && !cy.beta_pending;
+    // a block replays its captured graph; a capture that fails (nothing of
+    // it ran) leaves the block to plain launches, and after two failures this
+    // call launches plainly
+    auto captured = [&](hipGraphExec_t& ex, int n) -> bool {
+      if (ex) return true;
+      if (capture_block<T, D>(E, it, &ex, n) == DOT_OK) return true;
+      (void)hipGetLastError();
+      if (++capture_failures >= 2) use_graphs = false;
+      return false;
+    };
+    bool ran = false;
     if (blk_ok && since_poll == 0 && max_iters - j >= poll) {
-      hipGraphExec_t& ex = E.graphs->exec_poll;
-      if (!ex && (rc = capture_block<T, D>(E, it, &ex, poll))) return rc;
-      HIP_OK(hipGraphLaunch(ex, st));
-      j += poll;
-      since_poll += poll;
+      if (captured(E.graphs->exec_poll, poll)) {
+        HIP_OK(hipGraphLaunch(E.graphs->exec_poll, st));
+        j += poll;
+        since_poll += poll;
+        ran = true;
+      }
     } else if (blk_ok && max_iters - j >= kGraphIters) {
-      hipGraphExec_t& ex = E.graphs->exec;
-      if (!ex && (rc = capture_block<T, D>(E, it, &ex))) return rc;
-      HIP_OK(hipGraphLaunch(ex, st));
-      // a block starts with its own right-hand side and ends with a check
-      j += kGraphIters;
-      since_poll += kGraphIters;
-    } else {
+      if (captured(E.graphs->exec, kGraphIters)) {
+        HIP_OK(hipGraphLaunch(E.graphs->exec, st));
+        // a block starts with its own right-hand side and ends with a check
+        j += kGraphIters;
+        since_poll += kGraphIters;
+        ran = true;
+      }
+    }
+    if (!ran) {
       // an iteration before a poll completes its iterate (nothing deferred)
       const bool more = j + 1 < max_iters && since_poll + 1 < poll;
       if ((rc = one_iter<T, D>(E, it, st, side, more, &cy))) return rc;
@@ -1372,6 +1405,7 @@ bool laid_out(const dot_batch* B, int i) { return B->active.empty() || B->active
 // the schedule change no computed value: an instance's workgroups index its
 // own planes by their position among its own blocks.
 int batch_layout(dot_batch* B, const Sched& s, const std::vector<char>* act = nullptr) {
+  DevLock lk(g_dev_mu);
   const std::vector<char> on = act ? *act : B->active;
   const int count = (int)B->plans.size();
   std::vector<dot_plan*> plans;
@@ -1726,6 +1760,7 @@ extern "C" {
 const char* dot_last_error(void) { return g_err.c_str(); }
 
 void dot_plan_destroy(dot_plan* P) {
+  DevLock lk(g_dev_mu);
   if (!P) return;
   (void)hipFree(P->sw_sp);
   (void)hipFree(P->om_sp);
@@ -1744,6 +1779,7 @@ void dot_plan_destroy(dot_plan* P) {
 }
 
 int dot_plan_create(const dot_problem* p, dot_plan** out) {
+  DevLock lk(g_dev_mu);
   if (!out) return fail(DOT_EINVAL, "null output pointer");
   *out = nullptr;
   int rc = validate(p);
@@ -1995,7 +2031,11 @@ int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* 
   int rc = dot_plan_create(p, &P);
   if (rc) return rc;
   void* state = nullptr;
-  hipError_t e = hipMalloc(&state, P->state_bytes);
+  hipError_t e;
+  {
+    DevLock lk(g_dev_mu);
+    e = hipMalloc(&state, P->state_bytes);
+  }
   if (e != hipSuccess) {
     dot_plan_destroy(P);
     return fail(DOT_ENOMEM, "state allocation failed");
@@ -2003,7 +2043,10 @@ int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* 
   rc = dot_state_reset(P, state, nullptr);
   if (!rc) rc = dot_run(P, state, p->max_iter, nullptr, res);
   if (!rc) rc = dot_extract(P, state, rho_out, m_out, nullptr);
-  (void)hipFree(state);
+  {
+    DevLock lk(g_dev_mu);
+    (void)hipFree(state);
+  }
   dot_plan_destroy(P);
   return rc;
 }
@@ -2011,6 +2054,7 @@ int dot_solve(const dot_problem* p, double* rho_out, double* m_out, dot_result* 
 // ---- batches ---------------------------------------------------------------
 
 void dot_batch_destroy(dot_batch* B) {
+  DevLock lk(g_dev_mu);
   if (!B) return;
   for (auto* p : B->plans) dot_plan_destroy(p);
   (void)hipFree(B->d_inst);
@@ -2020,6 +2064,7 @@ void dot_batch_destroy(dot_batch* B) {
 }
 
 int dot_batch_create(const dot_problem* probs, int32_t count, dot_batch** out) {
+  DevLock lk(g_dev_mu);
   if (!out || !probs || count < 1 || count > 65535) return fail(DOT_EINVAL, "bad batch arguments");
   *out = nullptr;
   std::unique_ptr<dot_batch, void (*)(dot_batch*)> B(new (std::nothrow) dot_batch(), dot_batch_destroy);
@@ -2633,6 +2678,7 @@ int dot_solve_multilevel(const dot_problem* p, int32_t levels, double* rho_out, 
   std::vector<dot_plan*> plans(levels + 1, nullptr);
   std::vector<void*> states(levels + 1, nullptr);
   auto cleanup = [&]() {
+    DevLock lk(g_dev_mu);
     for (auto* s : states) (void)hipFree(s);
     for (auto* P : plans) dot_plan_destroy(P);
   };
@@ -2645,7 +2691,10 @@ int dot_solve_multilevel(const dot_problem* p, int32_t levels, double* rho_out, 
     // coarse level v: max{tol 10^-v, 1e-6}; the target level: tol
     if (v > 0) q.tol = std::max(p->tol * std::pow(10.0, -v), 1e-6);
     rc = dot_plan_create(&q, &plans[v]);
-    if (!rc && hipMalloc(&states[v], plans[v]->state_bytes) != hipSuccess) rc = fail(DOT_ENOMEM, "state allocation failed");
+    if (!rc) {
+      DevLock lk(g_dev_mu);
+      if (hipMalloc(&states[v], plans[v]->state_bytes) != hipSuccess) rc = fail(DOT_ENOMEM, "state allocation failed");
+    }
     if (!rc) rc = v == levels ? dot_state_reset(plans[v], states[v], nullptr)
                               : dot_prolong(plans[v + 1], states[v + 1], plans[v], states[v], nullptr);
     dot_result r{};
@@ -2784,6 +2833,7 @@ Request* find_req(dot_ctx* C, uint64_t ticket) {
 
 template <typename T>
 int ctx_rebuild(dot_ctx* C, hipStream_t st) {
+  DevLock lk(g_dev_mu);
   std::vector<Inst<T>> host;
   std::vector<uint16_t> maps;
   std::vector<dot_plan*> act;
@@ -3045,6 +3095,7 @@ size_t dot_footprint_bytes(const dot_problem* p) {
 }
 
 void dot_ctx_destroy(dot_ctx* C) {
+  DevLock lk(g_dev_mu);
   if (!C) return;
   int prev = -1;
   const bool other = hipGetDevice(&prev) == hipSuccess && prev != C->device && hipSetDevice(C->device) == hipSuccess;
@@ -3367,6 +3418,7 @@ int dot_ctx_create(int32_t device, int32_t D, int32_t precision, size_t hbm_budg
     return fail(DOT_EINVAL, "bad serving context arguments");
   int count = 0;
   if (device < -1) return fail(DOT_EINVAL, "device must be >= -1");
+  DevLock lk(g_dev_mu);
   if (device == -1) {
     HIP_OK(hipGetDevice(&device));
   } else {
