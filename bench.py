@@ -40,6 +40,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def section(name, fn, *a, **kw):
+    """Run one section after the headline; an error in it is reported in its
+    place in the line (the headline measured above stands)."""
+    try:
+        return fn(*a, **kw)
+    except Exception as e:  # noqa: BLE001
+        log(f"{name}: failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -616,7 +626,7 @@ def main():
     it_min = PM.iteration_min_bytes(D, n, w)
     traffic = profiled_traffic("2d_32x64x64_fp64", dominant)
     log("roofline at 2D 64x256x256 (mixed)")
-    large = large_roofline(torch, st)
+    large = section("roofline at 2D 64x256x256", large_roofline, torch, st)
 
     out = {
         "metric": "solves/s at KKT residual 1e-6 (plain FP64, one instance)",
@@ -670,20 +680,21 @@ def main():
         "roofline_bandwidth_bound_size": large,
     }
     log("large instance 32x1024x1024")
-    out["large_instance"] = large_section(torch, st)
+    out["large_instance"] = section("large instance", large_section, torch, st)
     log("multilevel")
-    out["multilevel"] = multilevel_section(torch, inst)
+    out["multilevel"] = section("multilevel", multilevel_section, torch, inst)
     log("mixed vs fp64 at 2D 64x256x256")
-    out["mixed_vs_fp64_2d_64x256x256"] = mixed_vs_fp64_config3(torch, st)
+    out["mixed_vs_fp64_2d_64x256x256"] = section("mixed vs fp64", mixed_vs_fp64_config3, torch, st)
     log("variants (tau)")
-    out["variants_tau"] = variants_section(torch, st, inst)
+    out["variants_tau"] = section("variants", variants_section, torch, st, inst)
     if args.batch > 0:
-        out["batched"] = batched_section(torch, st, args.batch)
+        out["batched"] = section("batched", batched_section, torch, st, args.batch)
     if args.serve_seconds > 0:
-        out["serving"] = serving_section(torch, args.serve_rate, args.serve_seconds, args.serve_drain)
+        out["serving"] = section("serving", serving_section, torch, args.serve_rate, args.serve_seconds,
+                                 args.serve_drain)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(iters[0], args.cpu_cfg3_iters)
+        out["cpu_baseline"] = section("cpu baseline", cpu_baseline, iters[0], args.cpu_cfg3_iters)
     print(json.dumps(out))
 
 
