@@ -282,11 +282,18 @@ int dot_batch_extract(dot_batch* batch, const void* workspace, int32_t index, do
 int dot_batch_profile_select(dot_batch* batch, int32_t kernel_class);
 int dot_batch_profile_read(dot_batch* batch, double* total_ms, int64_t* launches);
 
-/* Replay captured HIP graphs of 10 iterations inside dot_run / dot_batch_run
- * (default on; off runs the same launches one by one; results are bitwise
- * identical). Graphs are not used while a kernel class is being timed. */
+/* Replay captured HIP graphs (blocks of 10 iterations, and the 40 iterations
+ * between two polls of the control blocks) inside dot_run / dot_batch_run
+ * and the serving steps (default on; off runs the same launches one by one;
+ * results are bitwise identical). Graphs are not used while a kernel class
+ * is being timed. A capture that fails leaves its block to plain launches of
+ * the same kernels; after two failures a run call stops capturing. Either
+ * call drops the graphs captured so far. */
 int dot_plan_set_graphs(dot_plan* plan, int32_t enable);
 int dot_batch_set_graphs(dot_batch* batch, int32_t enable);
+/* Testing the fallback above: the next `count` graph captures in this
+ * process fail before they start (0 clears; DOT_EINVAL if negative). */
+int dot_test_fail_captures(int32_t count);
 
 /* ---- transform schedules and their autotuner ----------------------------- */
 /* The cosine-transform passes of the phi-step (Sec. 4, the Poisson solve of

@@ -36,7 +36,7 @@ EXPORTED = [
     "dot_footprint_bytes", "dot_ctx_create", "dot_ctx_destroy", "dot_ctx_submit", "dot_ctx_submit_ml", "dot_ctx_step", "dot_ctx_poll",
     "dot_ctx_fetch", "dot_ctx_stats", "dot_coarsen_data", "dot_prolong", "dot_solve_multilevel",
     "dot_step_residuals_noalloc", "dot_ctx_export", "dot_ctx_import", "dot_ctx_last_error", "dot_batch_promote",
-    "dot_ctx_keep_capped", "dot_batch_promote_member",
+    "dot_ctx_keep_capped", "dot_batch_promote_member", "dot_test_fail_captures",
 ]
 NOALLOC_SCRATCH_BYTES = 8 << 20
 
@@ -172,6 +172,7 @@ def load(path: Optional[str] = None) -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_double), vp]
     lib.dot_plan_set_graphs.argtypes = [vp, i32]
     lib.dot_batch_set_graphs.argtypes = [vp, i32]
+    lib.dot_test_fail_captures.argtypes = [i32]
     for fn in ("dot_plan_set_schedule", "dot_batch_set_schedule", "dot_plan_get_schedule",
                "dot_batch_get_schedule"):
         getattr(lib, fn).argtypes = [vp, ctypes.POINTER(dot_schedule)]
@@ -378,6 +379,12 @@ def dot_step_residuals_noalloc(plan, phi_ptr, z_ptr, q_ptr, alpha_ptr, beta_ptr,
 
 def dot_plan_set_graphs(plan, enable: bool):
     _check(load().dot_plan_set_graphs(plan.handle, int(bool(enable))))
+
+
+def dot_test_fail_captures(count: int):
+    """The next `count` graph captures fail before they start (testing the
+    fallback to plain launches)."""
+    _check(load().dot_test_fail_captures(int(count)))
 
 
 def dot_batch_set_graphs(batch, enable: bool):

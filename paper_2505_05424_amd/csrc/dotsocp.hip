@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -44,6 +45,9 @@ thread_local std::string g_err;
 // points that hold it call others that take it.
 std::recursive_mutex g_dev_mu;
 using DevLock = std::lock_guard<std::recursive_mutex>;
+
+// Captures still to fail on purpose (dot_test_fail_captures).
+std::atomic<int> g_fail_captures{0};
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -919,6 +923,8 @@ int one_iter(const Exec& E, int it, hipStream_t st, hipStream_t side, bool more,
 template <typename T, int D>
 int capture_block(const Exec& E, int it, hipGraphExec_t* out, int n = kGraphIters) {
   DevLock lk(g_dev_mu);
+  for (int f = g_fail_captures.load(); f > 0;)
+    if (g_fail_captures.compare_exchange_weak(f, f - 1)) return fail(DOT_EDEVICE, "capture failed on purpose (test)");
   Exec Ec = E;
   Ec.prof = nullptr;  // no events inside a captured graph
   if (!E.graphs->cap) HIP_OK(hipStreamCreateWithFlags(&E.graphs->cap, hipStreamNonBlocking));
@@ -2020,9 +2026,16 @@ int dot_profile_read(dot_plan* P, double* total_ms, int64_t* launches) {
   return DOT_OK;
 }
 
+int dot_test_fail_captures(int32_t count) {
+  if (count < 0) return fail(DOT_EINVAL, "count must be >= 0");
+  g_fail_captures.store(count);
+  return DOT_OK;
+}
+
 int dot_plan_set_graphs(dot_plan* P, int32_t enable) {
   if (!P) return fail(DOT_EINVAL, "null plan");
   P->graphs.enabled = enable != 0;
+  drop_graph(P->graphs);  // the next run captures anew
   return DOT_OK;
 }
 
@@ -2179,6 +2192,7 @@ int dot_batch_extract(dot_batch* B, const void* ws, int32_t index, double* rho_o
 int dot_batch_set_graphs(dot_batch* B, int32_t enable) {
   if (!B) return fail(DOT_EINVAL, "null batch");
   B->graphs.enabled = enable != 0;
+  drop_graph(B->graphs);  // the next run captures anew
   return DOT_OK;
 }
 

@@ -235,18 +235,25 @@ def test_dot_solve_one_shot():
 
 @pytest.mark.parametrize("name,iters", [("2d-mask-8x20x24", 137), ("3d-6x9x10x7", 64)])
 def test_graph_replay_equals_plain_launches(name, iters):
-    """Captured 10-iteration graphs replayed many times, with host polls and
-    syncs between replays, give bitwise the iterates of plain launches."""
+    """Captured graphs replayed many times, with host polls and syncs between
+    replays, give bitwise the iterates of plain launches; so does a run whose
+    first two captures fail (forced from the host before they start: the
+    blocks fall back to plain launches, and the next run call captures)."""
     inst, P, plan = _setup(name)
     states = []
-    for graphs in (False, True):
+    for graphs, failures in ((False, 0), (True, 0), (True, 2)):
         B.dot_plan_set_graphs(plan, graphs)
         s = G.GpuState(plan)
         s.reset()
-        s.run(33)
+        B.dot_test_fail_captures(failures)
+        try:
+            s.run(33)
+        finally:
+            B.dot_test_fail_captures(0)
         s.run(iters - 33)
         states.append(s.raw().copy())
     assert np.array_equal(states[0], states[1])
+    assert np.array_equal(states[0], states[2])
 
 
 def test_headline_solve_matches_the_converged_oracle():
